@@ -1,0 +1,696 @@
+/*
+ * Oracle: the sweep, replayed serially in FP64 (test infrastructure only).
+ *
+ * One sweep of one system, in order:
+ *  for each level band (ascending lambda):
+ *    grid shift u from stream (tag 32+l); periodic grid of side h = L/n, or for an
+ *    infinite system a grid over the bounding box of the positions;
+ *    for colour 0..7, for each cell of that colour in ascending id:
+ *      S_c = particles within hi of the cell, H_c = within hi + r_int (ascending id);
+ *      K_c = stochastic rounding of T_l |S_c| / N (stream tag 16+l);
+ *      for each trial t < K_c (stream tag l, cell, t):
+ *        lambda in the band (App. D), anchor a uniform in S_c, V uniform in the unit
+ *        ball by rejection (App. D), b = r_a + lambda V; b outside the cell: next t;
+ *        else a recycling chain with this lambda: p = V'/|V'| (App. D), n = number of
+ *        particles within lambda of b, A_w = A0 lambda / sqrt(n) (Eq. "Wavelet amplitude"),
+ *        displacement A_w w((r-b)/lambda, p) (Eqs. "Oseen as <ww>", "Tapered wavelet"),
+ *        dU over the bonds and WCA pairs the members touch, Metropolis test
+ *        (Eq. "Metropolis test"); after a rejection the same lambda is reused with a
+ *        new anchor, b (redrawn until it lies in the cell) and p (App. D recycling),
+ *        up to retry_cap attempts.
+ *  plane waves (periodic): H_F = stochastic rounding of N P_F chains; k from the cube
+ *  or the quasi-continuous shell (App. D), phase Phi and e-hat perpendicular to k,
+ *  displacement A_F cos(k.r + Phi) e-hat on every particle (Eq. "Oseen as <FF>"),
+ *  A_F = 2 A0 / (k sqrt(5 N)) (Eq. "Fourier strain energy" with dU_est/mu = A0^2 M6/(2pi)^3),
+ *  k = 0 accepted without displacement; a rejection permutes and sign-flips k.
+ *  time advances by dt per accepted chain (App. D, last paragraph).
+ */
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include "wo_internal.h"
+
+#define TAG_SHIFT 32
+#define TAG_META 16
+#define TAG_PWCOUNT 48
+#define TAG_PW 49
+
+static void trace_push(wo_ctx* c, int kind, int sys, int level, int64_t cell, int64_t trial,
+                       int retry, int64_t n, int acc, int extra, double dU, double thr) {
+    if (c->trace_n >= c->trace_cap) return;
+    wo_trace_rec* r = &c->trace[c->trace_n++];
+    r->kind = kind;
+    r->system = sys;
+    r->sweep = (int32_t)c->sweep;
+    r->level = level;
+    r->cell = (int32_t)cell;
+    r->trial = (int32_t)trial;
+    r->retry = retry;
+    r->n = (int32_t)n;
+    r->accepted = acc;
+    r->extra = extra;
+    r->dU = dU;
+    r->thr = thr;
+}
+
+/* ---------------------------------------------------------------- potentials ------ */
+static double u_bond(const wo_ctx* c, double r2) {
+    if (c->p.bond_type == WO_BOND_FENE) {
+        double R02 = c->p.R0 * c->p.R0;
+        if (r2 >= R02) return INFINITY;
+        return -0.5 * c->p.k_bond * R02 * log(1.0 - r2 / R02);
+    }
+    if (c->p.bond_type == WO_BOND_HARMONIC) return 0.5 * c->p.k_bond * r2;
+    return 0.0;
+}
+
+static double u_pair(const wo_ctx* c, double r2) {
+    if (r2 >= c->rc2) return 0.0;
+    if (r2 <= 0.0) return INFINITY;
+    double s2 = c->p.sigma * c->p.sigma / r2;
+    double s6 = s2 * s2 * s2;
+    return 4.0 * c->p.eps * (s6 * s6 - s6 + 0.25);
+}
+
+/* ------------------------------------------------------------------ geometry ------ */
+typedef struct {
+    int periodic;
+    double L, invL;
+    double o[3];
+    double h, invh, half;
+    int64_t n[3];
+    double hi, rh;
+} grid_t;
+
+static double minimg(const grid_t* g, double d) {
+    if (g->periodic) d = d - g->L * rint(d * g->invL);
+    return d;
+}
+
+static double pair_r2(const wo_ctx* c, const wo_system* s, double ax, double ay, double az,
+                      double bx, double by, double bz) {
+    double dx = ax - bx, dy = ay - by, dz = az - bz;
+    if (c->p.periodic) {
+        double L = s->L, invL = 1.0 / s->L;
+        dx = dx - L * rint(dx * invL);
+        dy = dy - L * rint(dy * invL);
+        dz = dz - L * rint(dz * invL);
+    }
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+static void make_grid(wo_ctx* c, wo_system* s, int sysid, int level, grid_t* g) {
+    const wo_level_info* lv = &s->lev[level];
+    wo_stream st;
+    wo_stream_init(&st, c->p.seed, sysid, c->sweep, TAG_SHIFT + level, 0, 0, 0, 0);
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = wo_next_co(&st);
+    g->periodic = c->p.periodic;
+    g->hi = lv->hi;
+    g->rh = lv->hi + lv->r_int;
+    g->h = lv->h;
+    g->invh = 1.0 / lv->h;
+    g->half = 0.5 * lv->h;
+    if (c->p.periodic) {
+        g->L = s->L;
+        g->invL = 1.0 / s->L;
+        for (int a = 0; a < 3; ++a) {
+            g->o[a] = lv->h * u[a];
+            g->n[a] = lv->ncell;
+        }
+    } else {
+        g->L = 0.0;
+        g->invL = 0.0;
+        double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t i = s->b0; i < s->b1; ++i) {
+            double v[3] = {c->x[i], c->y[i], c->z[i]};
+            for (int a = 0; a < 3; ++a) {
+                if (v[a] < mn[a]) mn[a] = v[a];
+                if (v[a] > mx[a]) mx[a] = v[a];
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            g->o[a] = mn[a] - lv->hi - lv->h * u[a];
+            g->n[a] = (int64_t)floor((mx[a] + lv->hi - g->o[a]) * g->invh) + 1;
+        }
+    }
+}
+
+static int64_t cell_of_point(const grid_t* g, double bx, double by, double bz) {
+    double b[3] = {bx, by, bz};
+    int64_t ic[3];
+    for (int a = 0; a < 3; ++a) {
+        double v = b[a];
+        if (g->periodic) v = v - g->L * floor(v * g->invL);
+        int64_t i = (int64_t)floor((v - g->o[a]) * g->invh);
+        if (g->periodic) {
+            i %= g->n[a];
+            if (i < 0) i += g->n[a];
+        } else if (i < 0 || i >= g->n[a]) {
+            return -1;
+        }
+        ic[a] = i;
+    }
+    return ic[0] + g->n[0] * (ic[1] + g->n[1] * ic[2]);
+}
+
+static double dist2_cell(const grid_t* g, const int64_t ic[3], double x, double y, double z) {
+    double v[3] = {x, y, z}, acc[3];
+    for (int a = 0; a < 3; ++a) {
+        double cen = g->o[a] + ((double)ic[a] + 0.5) * g->h;
+        double d = minimg(g, v[a] - cen);
+        double e = fabs(d) - g->half;
+        if (e < 0.0) e = 0.0;
+        acc[a] = e * e;
+    }
+    return (acc[0] + acc[1]) + acc[2];
+}
+
+/* ------------------------------------------------------------ one cell phase ----- */
+static int draw_centre(wo_ctx* c, wo_stream* st, const grid_t* g, int64_t cell, int64_t nS,
+                       double lam, int64_t* anchor, double b[3]) {
+    int64_t a = c->S[wo_next_index(st, nS)];
+    double vx, vy, vz, ss;
+    do {
+        vx = 2.0 * wo_next_co(st) - 1.0;
+        vy = 2.0 * wo_next_co(st) - 1.0;
+        vz = 2.0 * wo_next_co(st) - 1.0;
+        ss = (vx * vx + vy * vy) + vz * vz;
+    } while (ss > 1.0);
+    b[0] = c->x[a] + lam * vx;
+    b[1] = c->y[a] + lam * vy;
+    b[2] = c->z[a] + lam * vz;
+    *anchor = a;
+    return cell_of_point(g, b[0], b[1], b[2]) == cell;
+}
+
+static void draw_direction(wo_stream* st, double p[3]) {
+    double vx, vy, vz, ss;
+    do {
+        vx = 2.0 * wo_next_co(st) - 1.0;
+        vy = 2.0 * wo_next_co(st) - 1.0;
+        vz = 2.0 * wo_next_co(st) - 1.0;
+        ss = (vx * vx + vy * vy) + vz * vz;
+    } while (ss > 1.0 || ss == 0.0);
+    double nrm = sqrt(ss);
+    p[0] = vx / nrm;
+    p[1] = vy / nrm;
+    p[2] = vz / nrm;
+}
+
+/* one Metropolis test of a wavelet move; returns 1 if accepted (positions updated) */
+static int wavelet_attempt(wo_ctx* c, wo_system* s, int sysid, int level, int64_t cell,
+                           int64_t t, int r, int64_t nS, int64_t nH, double lam, int64_t anchor,
+                           const double b[3], const double p[3], double u_acc) {
+    double L = s->L, invL = c->p.periodic ? 1.0 / s->L : 0.0;
+    int per = c->p.periodic;
+    double lam2 = lam * lam;
+    int64_t stamp = ++c->mark_stamp;
+    int64_t n = 0;
+    /* members: S_c in ascending id within lambda of b, plus the anchor */
+    for (int64_t q = 0; q < nS; ++q) {
+        int64_t j = c->S[q];
+        double d[3] = {c->x[j] - b[0], c->y[j] - b[1], c->z[j] - b[2]};
+        if (per)
+            for (int a = 0; a < 3; ++a) d[a] = d[a] - L * rint(d[a] * invL);
+        double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+        if (d2 <= lam2 || j == anchor) {
+            c->M[n] = j;
+            c->mark[j] = stamp;
+            double xr[3] = {d[0] / lam, d[1] / lam, d[2] / lam};
+            /* displacement computed below once n is known; stash scaled offsets */
+            c->nx[j] = xr[0];
+            c->ny[j] = xr[1];
+            c->nz[j] = xr[2];
+            ++n;
+        }
+    }
+    double A = c->p.A0 * lam / sqrt((double)n);
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t j = c->M[q];
+        double xr[3] = {c->nx[j], c->ny[j], c->nz[j]}, w[3];
+        double rr = sqrt((xr[0] * xr[0] + xr[1] * xr[1]) + xr[2] * xr[2]);
+        double f = rr < 1.0 ? A * (1.0 - rr) : 0.0;
+        w[0] = f * (p[1] * xr[2] - p[2] * xr[1]);
+        w[1] = f * (p[2] * xr[0] - p[0] * xr[2]);
+        w[2] = f * (p[0] * xr[1] - p[1] * xr[0]);
+        c->nx[j] = c->x[j] + w[0];
+        c->ny[j] = c->y[j] + w[1];
+        c->nz[j] = c->z[j] + w[2];
+    }
+    /* energy change: bonds and WCA pairs with at least one member, each once */
+    double dU = 0.0, rint2 = c->r_int * c->r_int;
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t j = c->M[q];
+        double jx = c->x[j], jy = c->y[j], jz = c->z[j];
+        double kx = c->nx[j], ky = c->ny[j], kz = c->nz[j];
+        if (c->p.bond_type != WO_BOND_NONE) {
+            int64_t part[2] = {-1, -1};
+            if (j + 1 < s->b1 && c->bond_next[j]) part[0] = j + 1;
+            if (j > s->b0 && c->bond_next[j - 1]) part[1] = j - 1;
+            for (int e = 0; e < 2; ++e) {
+                int64_t m = part[e];
+                if (m < 0) continue;
+                int mem = c->mark[m] == stamp;
+                if (mem && m < j) continue;
+                double r2o = pair_r2(c, s, jx, jy, jz, c->x[m], c->y[m], c->z[m]);
+                double r2n = mem ? pair_r2(c, s, kx, ky, kz, c->nx[m], c->ny[m], c->nz[m])
+                                 : pair_r2(c, s, kx, ky, kz, c->x[m], c->y[m], c->z[m]);
+                if (r2o > rint2) c->obs.violations++;
+                dU += u_bond(c, r2n) - u_bond(c, r2o);
+            }
+        }
+        if (c->p.wca) {
+            for (int64_t q2 = 0; q2 < nH; ++q2) {
+                int64_t m = c->H[q2];
+                if (m == j) continue;
+                int mem = c->mark[m] == stamp;
+                if (mem && m < j) continue;
+                double r2o = pair_r2(c, s, jx, jy, jz, c->x[m], c->y[m], c->z[m]);
+                double r2n = mem ? pair_r2(c, s, kx, ky, kz, c->nx[m], c->ny[m], c->nz[m])
+                                 : pair_r2(c, s, kx, ky, kz, c->x[m], c->y[m], c->z[m]);
+                if (r2o < c->rc2 || r2n < c->rc2) dU += u_pair(c, r2n) - u_pair(c, r2o);
+            }
+        }
+    }
+    double thr = -c->p.kT * log(u_acc);
+    int acc = dU <= thr;
+    c->obs.attempts[level]++;
+    c->obs.bead_updates[level] += n;
+    trace_push(c, 0, sysid, level, cell, t, r, n, acc, (int)anchor, dU, thr);
+    if (acc) {
+        for (int64_t q = 0; q < n; ++q) {
+            int64_t j = c->M[q];
+            c->x[j] = c->nx[j];
+            c->y[j] = c->ny[j];
+            c->z[j] = c->nz[j];
+        }
+        c->obs.accepts[level]++;
+    }
+    return acc;
+}
+
+static void process_cell(wo_ctx* c, wo_system* s, int sysid, int level, const grid_t* g,
+                         int64_t cell, const int64_t ic[3]) {
+    const wo_level_info* lv = &s->lev[level];
+    int64_t nS = 0, nH = 0;
+    double hi2 = g->hi * g->hi, rh2 = g->rh * g->rh;
+    for (int64_t j = s->b0; j < s->b1; ++j) {
+        double d2 = dist2_cell(g, ic, c->x[j], c->y[j], c->z[j]);
+        if (d2 <= hi2) c->S[nS++] = j;
+        if (d2 <= rh2) c->H[nH++] = j;
+    }
+    /* number of trials: stochastic rounding of T_l |S_c| / N */
+    double mu = (lv->T * (double)nS) / (double)s->N;
+    int64_t K = (int64_t)floor(mu);
+    wo_stream ms;
+    wo_stream_init(&ms, c->p.seed, sysid, c->sweep, TAG_META + level, cell, 0, 0, 0);
+    if (wo_next_co(&ms) < mu - (double)K) K += 1;
+    if (K > 0xFFFFF) { K = 0xFFFFF; c->obs.violations++; }
+    int64_t hits = 0;
+    for (int64_t t = 0; t < K; ++t) {
+        wo_stream st;
+        wo_stream_init(&st, c->p.seed, sysid, c->sweep, level, cell, t, 0, 0);
+        double lam = wo_draw_lambda(wo_next_co(&st), lv->lo, lv->hi);
+        int64_t anchor;
+        double b[3];
+        c->obs.trials[level]++;
+        if (!draw_centre(c, &st, g, cell, nS, lam, &anchor, b)) continue;
+        c->obs.hits[level]++;
+        ++hits;
+        for (int r = 0;;) {
+            double p[3];
+            draw_direction(&st, p);
+            double u_acc = wo_next_oc(&st);
+            if (wavelet_attempt(c, s, sysid, level, cell, t, r, nS, nH, lam, anchor, b, p, u_acc)) {
+                s->accepted++;
+                c->obs.accepted_total++;
+                break;
+            }
+            if (++r >= c->p.retry_cap) { c->obs.caps[level]++; break; }
+            int found = 0;
+            for (int j = 0; j < 4096; ++j) {
+                wo_stream_init(&st, c->p.seed, sysid, c->sweep, level, cell, t, r, j);
+                if (draw_centre(c, &st, g, cell, nS, lam, &anchor, b)) { found = 1; break; }
+                c->obs.redraws[level]++;
+            }
+            if (!found) { c->obs.caps[level]++; break; }
+        }
+    }
+    trace_push(c, 1, sysid, level, cell, K, (int)nS, nH, (int)hits, 0, 0.0, 0.0);
+}
+
+/* ------------------------------------------------------------- plane waves -------- */
+static const int PERM[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+static void sample_k(wo_ctx* c, wo_system* s, wo_stream* st, int l[3]) {
+    int NL = c->p.n_layers, D = 2 * NL + 1;
+    if (wo_next_co(st) < s->info.P_cube) {
+        double target = wo_next_co(st) * s->info.W_cube;
+        int64_t lo = 0, hi = (int64_t)s->info.n_modes - 1;
+        while (lo < hi) { /* smallest i with cdf[i] > target */
+            int64_t mid = (lo + hi) / 2;
+            if (s->cube_cdf[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        int64_t i = lo;
+        l[0] = (int)(i / ((int64_t)D * D)) - NL;
+        l[1] = (int)((i / D) % D) - NL;
+        l[2] = (int)(i % D) - NL;
+        return;
+    }
+    double invks = s->L / (2.0 * WO_PI);
+    for (;;) {
+        double us = wo_next_co(st) * s->n_shell;
+        int64_t i = (int64_t)floor(us);
+        double fr = us - (double)i;
+        double sv = s->shell_s[i] + fr * (s->shell_s[i + 1] - s->shell_s[i]);
+        double v[3];
+        draw_direction(st, v);
+        if (!(sv > 1e-12)) continue;
+        double kmag = (s->x_s / sv) / s->lmax;
+        int ok = 1, inside = 1;
+        for (int a = 0; a < 3; ++a) {
+            double la = rint(kmag * v[a] * invks);
+            if (fabs(la) > 1048576.0) ok = 0;
+            l[a] = ok ? (int)la : 0;
+            if (abs(l[a]) > NL) inside = 0;
+        }
+        if (ok && !inside) return;
+    }
+}
+
+static int pw_attempt(wo_ctx* c, wo_system* s, int sysid, int64_t h, int r, const int l[3],
+                      double Phi, double psi, double u_acc) {
+    double ks = 2.0 * WO_PI / s->L;
+    double k[3] = {ks * (double)l[0], ks * (double)l[1], ks * (double)l[2]};
+    double kmag = sqrt((k[0] * k[0] + k[1] * k[1]) + k[2] * k[2]);
+    double kh[3] = {k[0] / kmag, k[1] / kmag, k[2] / kmag};
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+        if (fabs(kh[a]) < fabs(kh[ax])) ax = a;
+    double ref[3] = {0.0, 0.0, 0.0};
+    ref[ax] = 1.0;
+    double e1[3] = {kh[1] * ref[2] - kh[2] * ref[1], kh[2] * ref[0] - kh[0] * ref[2],
+                    kh[0] * ref[1] - kh[1] * ref[0]};
+    double n1 = sqrt((e1[0] * e1[0] + e1[1] * e1[1]) + e1[2] * e1[2]);
+    for (int a = 0; a < 3; ++a) e1[a] = e1[a] / n1;
+    double e2[3] = {kh[1] * e1[2] - kh[2] * e1[1], kh[2] * e1[0] - kh[0] * e1[2],
+                    kh[0] * e1[1] - kh[1] * e1[0]};
+    double cp = cos(psi), sp = sin(psi);
+    double e[3] = {cp * e1[0] + sp * e2[0], cp * e1[1] + sp * e2[1], cp * e1[2] + sp * e2[2]};
+    double AF = 2.0 * c->p.A0 / (kmag * sqrt(5.0 * (double)s->N));
+    for (int64_t j = s->b0; j < s->b1; ++j) {
+        double ph = ((k[0] * c->x[j] + k[1] * c->y[j]) + k[2] * c->z[j]) + Phi;
+        double f = AF * cos(ph);
+        c->nx[j] = c->x[j] + f * e[0];
+        c->ny[j] = c->y[j] + f * e[1];
+        c->nz[j] = c->z[j] + f * e[2];
+    }
+    double dU = 0.0;
+    if (c->p.bond_type != WO_BOND_NONE) {
+        for (int64_t j = s->b0; j + 1 < s->b1; ++j) {
+            if (!c->bond_next[j]) continue;
+            double r2o = pair_r2(c, s, c->x[j], c->y[j], c->z[j], c->x[j + 1], c->y[j + 1], c->z[j + 1]);
+            double r2n = pair_r2(c, s, c->nx[j], c->ny[j], c->nz[j], c->nx[j + 1], c->ny[j + 1], c->nz[j + 1]);
+            dU += u_bond(c, r2n) - u_bond(c, r2o);
+        }
+    }
+    if (c->p.wca) {
+        for (int64_t j = s->b0; j < s->b1; ++j)
+            for (int64_t m = j + 1; m < s->b1; ++m) {
+                double r2o = pair_r2(c, s, c->x[j], c->y[j], c->z[j], c->x[m], c->y[m], c->z[m]);
+                double r2n = pair_r2(c, s, c->nx[j], c->ny[j], c->nz[j], c->nx[m], c->ny[m], c->nz[m]);
+                if (r2o < c->rc2 || r2n < c->rc2) dU += u_pair(c, r2n) - u_pair(c, r2o);
+            }
+    }
+    double thr = -c->p.kT * log(u_acc);
+    int acc = dU <= thr;
+    int extra = (int)((((uint32_t)(l[0] + 512) & 0x3FFu) << 20) | (((uint32_t)(l[1] + 512) & 0x3FFu) << 10) |
+                      ((uint32_t)(l[2] + 512) & 0x3FFu));
+    c->obs.pw_attempts++;
+    c->obs.pw_bead_updates += s->N;
+    trace_push(c, 2, sysid, -1, h, 0, r, s->N, acc, extra, dU, thr);
+    if (acc) {
+        for (int64_t j = s->b0; j < s->b1; ++j) {
+            c->x[j] = c->nx[j];
+            c->y[j] = c->ny[j];
+            c->z[j] = c->nz[j];
+        }
+        c->obs.pw_accepts++;
+    }
+    return acc;
+}
+
+static void plane_waves(wo_ctx* c, wo_system* s, int sysid) {
+    wo_stream cs;
+    wo_stream_init(&cs, c->p.seed, sysid, c->sweep, TAG_PWCOUNT, 0, 0, 0, 0);
+    double mu = (double)s->N * s->info.P_F;
+    int64_t HF = (int64_t)floor(mu);
+    if (wo_next_co(&cs) < mu - (double)HF) HF += 1;
+    for (int64_t h = 0; h < HF; ++h) {
+        c->obs.pw_chains++;
+        wo_stream st;
+        wo_stream_init(&st, c->p.seed, sysid, c->sweep, TAG_PW, 0, h, 0, 0);
+        int l[3];
+        sample_k(c, s, &st, l);
+        for (int r = 0;;) {
+            double Phi = 2.0 * WO_PI * wo_next_co(&st);
+            double psi = 2.0 * WO_PI * wo_next_co(&st);
+            double u_acc = wo_next_oc(&st);
+            if (l[0] == 0 && l[1] == 0 && l[2] == 0) {
+                c->obs.pw_k0++;
+                c->obs.pw_accepts++;
+                s->accepted++;
+                c->obs.accepted_total++;
+                trace_push(c, 2, sysid, -1, h, 0, r, 0, 1, (512 << 20) | (512 << 10) | 512, 0.0,
+                           -c->p.kT * log(u_acc));
+                break;
+            }
+            if (pw_attempt(c, s, sysid, h, r, l, Phi, psi, u_acc)) {
+                s->accepted++;
+                c->obs.accepted_total++;
+                break;
+            }
+            if (++r >= c->p.retry_cap) { c->obs.pw_caps++; break; }
+            wo_stream_init(&st, c->p.seed, sysid, c->sweep, TAG_PW, 0, h, r, 0);
+            int pi = (int)wo_next_index(&st, 6);
+            int nl[3] = {l[PERM[pi][0]], l[PERM[pi][1]], l[PERM[pi][2]]};
+            for (int a = 0; a < 3; ++a) l[a] = wo_next_co(&st) < 0.5 ? -nl[a] : nl[a];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------- sweep -------- */
+static void sweep_system(wo_ctx* c, int sysid) {
+    wo_system* s = &c->sys[sysid];
+    for (int level = 0; c->p.wavelets && level < s->n_levels; ++level) {
+        grid_t g;
+        make_grid(c, s, sysid, level, &g);
+        int64_t ncell = g.n[0] * g.n[1] * g.n[2];
+        for (int colour = 0; colour < 8; ++colour) {
+            for (int64_t cell = 0; cell < ncell; ++cell) {
+                int64_t ic[3] = {cell % g.n[0], (cell / g.n[0]) % g.n[1], cell / (g.n[0] * g.n[1])};
+                int col = (int)((ic[0] & 1) | ((ic[1] & 1) << 1) | ((ic[2] & 1) << 2));
+                if (col != colour) continue;
+                process_cell(c, s, sysid, level, &g, cell, ic);
+            }
+        }
+    }
+    if (c->p.periodic && c->p.plane_waves) plane_waves(c, s, sysid);
+}
+
+int wo_sweep(void* vctx, int64_t n_sweeps) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    for (int64_t k = 0; k < n_sweeps; ++k) {
+        for (int sysid = 0; sysid < c->nsys; ++sysid) sweep_system(c, sysid);
+        c->sweep++;
+        c->obs.sweeps++;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ setup --------- */
+int wo_init(void** out, const wo_params* p, int32_t n_systems, const int64_t* sys_bead_offset,
+            const double* sys_box_L, const double* sys_lambda_max, int64_t n_chains,
+            const int64_t* chain_offset, const double* pos_xyz, int64_t trace_capacity) {
+    *out = NULL;
+    wo_ctx* c = (wo_ctx*)calloc(1, sizeof(wo_ctx));
+    if (!c) return -1;
+    c->p = *p;
+    c->nsys = n_systems;
+    c->N = sys_bead_offset[n_systems];
+    int64_t N = c->N;
+    c->x = (double*)malloc(sizeof(double) * N);
+    c->y = (double*)malloc(sizeof(double) * N);
+    c->z = (double*)malloc(sizeof(double) * N);
+    c->nx = (double*)malloc(sizeof(double) * N);
+    c->ny = (double*)malloc(sizeof(double) * N);
+    c->nz = (double*)malloc(sizeof(double) * N);
+    c->S = (int64_t*)malloc(sizeof(int64_t) * N);
+    c->H = (int64_t*)malloc(sizeof(int64_t) * N);
+    c->M = (int64_t*)malloc(sizeof(int64_t) * N);
+    c->mark = (int64_t*)calloc(N, sizeof(int64_t));
+    c->bond_next = (uint8_t*)calloc(N > 0 ? N : 1, 1);
+    c->n_chains = n_chains;
+    c->chain_off = (int64_t*)malloc(sizeof(int64_t) * (n_chains + 1));
+    memcpy(c->chain_off, chain_offset, sizeof(int64_t) * (n_chains + 1));
+    for (int64_t i = 0; i < N; ++i) {
+        c->x[i] = pos_xyz[3 * i];
+        c->y[i] = pos_xyz[3 * i + 1];
+        c->z[i] = pos_xyz[3 * i + 2];
+    }
+    for (int64_t ch = 0; ch < n_chains; ++ch)
+        for (int64_t i = chain_offset[ch]; i + 1 < chain_offset[ch + 1]; ++i) c->bond_next[i] = 1;
+    c->trace_cap = trace_capacity;
+    c->trace = trace_capacity > 0 ? (wo_trace_rec*)malloc(sizeof(wo_trace_rec) * trace_capacity) : NULL;
+    c->rc2 = pow(2.0, 1.0 / 3.0) * p->sigma * p->sigma;
+    double rc = p->wca ? pow(2.0, 1.0 / 6.0) * p->sigma : 0.0;
+    if (p->bond_type == WO_BOND_FENE) c->r_int = p->R0 > rc ? p->R0 : rc;
+    else if (p->bond_type == WO_BOND_HARMONIC) c->r_int = p->r_int_harmonic > rc ? p->r_int_harmonic : rc;
+    else c->r_int = rc;
+    c->sys = (wo_system*)calloc(n_systems, sizeof(wo_system));
+    *out = c;
+    if (!(p->band_ratio > 1.0 && p->band_ratio <= 2.0)) { strcpy(c->err, "band_ratio must lie in (1, 2]"); return -2; }
+    if (!(p->lambda_min > 0.0)) { strcpy(c->err, "lambda_min must be positive"); return -2; }
+    for (int si = 0; si < n_systems; ++si) {
+        wo_system* s = &c->sys[si];
+        s->b0 = sys_bead_offset[si];
+        s->b1 = sys_bead_offset[si + 1];
+        s->N = s->b1 - s->b0;
+        s->L = sys_box_L ? sys_box_L[si] : p->box_L;
+        s->lmax = sys_lambda_max ? sys_lambda_max[si] : p->lambda_max;
+        if (!(s->lmax > p->lambda_min)) { strcpy(c->err, "lambda_max must exceed lambda_min"); return -2; }
+        if (p->periodic && s->lmax > 0.5 * s->L) { strcpy(c->err, "lambda_max must not exceed L/2"); return -2; }
+        /* systems with the same L/lambda_max share their plane-wave tables */
+        const wo_system* donor = NULL;
+        for (int sj = 0; sj < si && p->periodic && p->plane_waves; ++sj)
+            if (c->sys[sj].L / c->sys[sj].lmax == s->L / s->lmax) { donor = &c->sys[sj]; break; }
+        int rc_ = wo_build_system_tables(c, s, donor);
+        if (rc_) return rc_;
+        /* initial state must have finite energy */
+        for (int64_t j = s->b0; j + 1 < s->b1; ++j) {
+            if (!c->bond_next[j]) continue;
+            double r2 = pair_r2(c, s, c->x[j], c->y[j], c->z[j], c->x[j + 1], c->y[j + 1], c->z[j + 1]);
+            if (!isfinite(u_bond(c, r2))) { strcpy(c->err, "initial bond overstretched"); return -3; }
+        }
+    }
+    return 0;
+}
+
+int wo_positions(void* vctx, double* out) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    for (int64_t i = 0; i < c->N; ++i) {
+        out[3 * i] = c->x[i];
+        out[3 * i + 1] = c->y[i];
+        out[3 * i + 2] = c->z[i];
+    }
+    return 0;
+}
+
+int wo_set_positions(void* vctx, const double* xyz) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    for (int64_t i = 0; i < c->N; ++i) {
+        c->x[i] = xyz[3 * i];
+        c->y[i] = xyz[3 * i + 1];
+        c->z[i] = xyz[3 * i + 2];
+    }
+    return 0;
+}
+
+int wo_set_sweep(void* vctx, int64_t sweep) {
+    ((wo_ctx*)vctx)->sweep = sweep;
+    return 0;
+}
+
+int wo_observables(void* vctx, wo_obs* out) {
+    *out = ((wo_ctx*)vctx)->obs;
+    return 0;
+}
+
+int wo_system_tau(void* vctx, double* out) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    for (int i = 0; i < c->nsys; ++i) out[i] = c->sys[i].info.dt * (double)c->sys[i].accepted;
+    return 0;
+}
+
+/* Eq. "Radius of gyration": <Rg^2> = (1/(2 Nb^2)) sum_i sum_j r_ij^2, unwrapped positions */
+int wo_chain_rg2(void* vctx, double* out) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    for (int64_t ch = 0; ch < c->n_chains; ++ch) {
+        int64_t a = c->chain_off[ch], b = c->chain_off[ch + 1];
+        double acc = 0.0;
+        for (int64_t i = a; i < b; ++i)
+            for (int64_t j = a; j < b; ++j) {
+                double dx = c->x[i] - c->x[j], dy = c->y[i] - c->y[j], dz = c->z[i] - c->z[j];
+                acc += (dx * dx + dy * dy) + dz * dz;
+            }
+        double nb = (double)(b - a);
+        out[ch] = acc / (2.0 * nb * nb);
+    }
+    return 0;
+}
+
+int64_t wo_trace(void* vctx, wo_trace_rec* out, int64_t max) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    int64_t n = c->trace_n < max ? c->trace_n : max;
+    memcpy(out, c->trace, sizeof(wo_trace_rec) * n);
+    c->trace_n = 0;
+    return n;
+}
+
+int wo_get_level_info(void* vctx, int32_t system, wo_level_info* out, int32_t max) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    wo_system* s = &c->sys[system];
+    int n = s->n_levels < max ? s->n_levels : max;
+    memcpy(out, s->lev, sizeof(wo_level_info) * n);
+    return s->n_levels;
+}
+
+int wo_get_system_info(void* vctx, int32_t system, wo_system_info* out) {
+    *out = ((wo_ctx*)vctx)->sys[system].info;
+    return 0;
+}
+
+int wo_cell_ids(void* vctx, int32_t system, int64_t sweep, int32_t level, int32_t* out) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    wo_system* s = &c->sys[system];
+    int64_t keep = c->sweep;
+    c->sweep = sweep;
+    grid_t g;
+    make_grid(c, s, system, level, &g);
+    c->sweep = keep;
+    for (int64_t j = s->b0; j < s->b1; ++j) out[j - s->b0] = (int32_t)cell_of_point(&g, c->x[j], c->y[j], c->z[j]);
+    return 0;
+}
+
+int wo_cube_weights(void* vctx, int32_t system, double* out) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    wo_system* s = &c->sys[system];
+    if (!s->cube_w) return -1;
+    memcpy(out, s->cube_w, sizeof(double) * s->info.n_modes);
+    return s->info.n_modes;
+}
+
+int wo_shell_table(void* vctx, int32_t system, double* out, int32_t max) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    wo_system* s = &c->sys[system];
+    if (!s->shell_s) return -1;
+    int n = s->n_shell + 1 < max ? s->n_shell + 1 : max;
+    memcpy(out, s->shell_s, sizeof(double) * n);
+    return s->n_shell + 1;
+}
+
+const char* wo_last_error(void* vctx) { return vctx ? ((wo_ctx*)vctx)->err : "no context"; }
+
+void wo_free(void* vctx) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    if (!c) return;
+    for (int i = 0; i < c->nsys; ++i) wo_free_system_tables(&c->sys[i]);
+    free(c->sys);
+    free(c->x); free(c->y); free(c->z);
+    free(c->nx); free(c->ny); free(c->nz);
+    free(c->S); free(c->H); free(c->M); free(c->mark);
+    free(c->bond_next); free(c->chain_off); free(c->trace);
+    free(c);
+}
