@@ -1,0 +1,175 @@
+/*
+ * wmc.h - C ABI of the MI355X (gfx950) Wavelet Monte Carlo dynamics sweep.
+ *
+ * Method: Dyer & Ball, "Wavelet Monte Carlo dynamics: a new algorithm for simulating the
+ * hydrodynamics of interacting Brownian particles" (arXiv:1611.09160). Bead-spring
+ * polymers evolve by Metropolis-tested, spatially correlated moves:
+ *   - vector-wavelet moves (Sec. IV, App. D "Generating a wavelet"): radius lambda with PDF
+ *     ~ lambda^-4 on [lambda_min, lambda_max] (Eq. "PDF for lambda"), centre b uniform in a
+ *     ball of radius lambda around a uniformly picked bead (Eq. "PDF for b"), isotropic
+ *     polarisation p, amplitude A_w = A0 lambda / sqrt(n) (Eq. "Wavelet amplitude"),
+ *     displacement A_w w((r - b)/lambda, p) with the tapered wavelet
+ *     w(x, p) = (1 - |x|) p x x (Eqs. "Oseen as <ww>", "Tapered wavelet");
+ *   - plane-wave moves in periodic boxes (Sec. V): displacement A_F cos(k.r + Phi) e-hat on
+ *     every bead, e-hat perpendicular to k (Eq. "Oseen as <FF>"), A_F = (2/k) sqrt(dU_est/(mu N))
+ *     (Eq. "Fourier strain energy"), k from the periodic lattice (Eq. "Prob of k_l"),
+ *     made with probability P_F (Eq. "P(Fourier)");
+ *   - acceptance min(1, exp(-dU/kT)) (Eq. "Metropolis test"), lambda / k recycling after a
+ *     rejection and time advanced by dt per accepted move (App. D, Eqs. "Time step per
+ *     wavelet", "dt w+F").
+ * Interactions (Sec. II): FENE bonds (Eq. "FENE potential") or harmonic bonds, and WCA
+ * between all pairs, bonded ones included (Eq. "WCA potential").
+ *
+ * Every random number comes from counter-based Philox4x32-10 streams keyed by
+ * (seed; system, sweep, level or plane-wave tag, cell or chain, trial, retry, try), so a run
+ * is reproducible and resumable from (positions, sweep counter, seed).
+ *
+ * Conventions
+ *  - All functions return 0 on success or a negative WMC_E* code; the message is kept in
+ *    the context (wmc_last_error). No exception crosses the ABI.
+ *  - Host arrays are owned by the caller and only read (or written, for outputs) during
+ *    the call. The device arena is owned by the caller (e.g. a torch uint8 tensor on the
+ *    GPU) and must stay allocated until wmc_free; the library places all its device
+ *    state inside it and allocates no device memory of its own.
+ *  - hip_stream is a hipStream_t (NULL = the legacy default stream). wmc_sweep is
+ *    asynchronous on that stream; wmc_positions(to_device=1) too; the other calls
+ *    synchronise the stream before returning host data.
+ *  - Positions are FP64, [N][3] row-major (x, y, z per bead), unwrapped (a bead's
+ *    coordinates are never folded back into the box; minimum image is applied to every
+ *    difference).
+ *  - Beads are numbered 0..N-1. System s owns beads [sys_bead_offset[s],
+ *    sys_bead_offset[s+1]); chain c owns beads [chain_offset[c], chain_offset[c+1]) and
+ *    bonds join consecutive beads of one chain; chains may not cross systems.
+ */
+#ifndef WMC_H
+#define WMC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    WMC_OK = 0,
+    WMC_EINVAL = -1,     /* bad argument or parameter */
+    WMC_ESTATE = -2,     /* initial state has infinite energy (overstretched bond, overlap) */
+    WMC_EARENA = -3,     /* device arena missing or too small */
+    WMC_EHIP = -4,       /* a HIP runtime call failed */
+    WMC_ECAPACITY = -5   /* a per-cell list overflowed its capacity during a sweep */
+};
+
+enum { WMC_BOND_NONE = 0, WMC_BOND_FENE = 1, WMC_BOND_HARMONIC = 2 };
+enum { WMC_FP64 = 0, WMC_MIXED = 1 };
+
+#define WMC_MAX_LEVELS 16
+
+typedef struct wmc_ctx wmc_ctx;
+
+/* Run parameters (Sec. II units: lengths in sigma, energies in epsilon). */
+typedef struct {
+    int32_t periodic;        /* 1: cubic periodic box; 0: infinite system (single system only) */
+    int32_t plane_waves;     /* 1: plane-wave moves (periodic only), Sec. V */
+    int32_t wavelets;        /* 1: wavelet moves (0 only for plane-wave-only checks) */
+    int32_t precision;       /* WMC_FP64, or WMC_MIXED: FP32 energy terms with FP64 recheck */
+    double box_L;            /* box side, used when sys_box_L is NULL */
+    double lambda_min;       /* smallest wavelet radius; sets a = lambda_min / lambda_a */
+    double lambda_max;       /* largest wavelet radius (<= L/2), used when sys_lambda_max is NULL */
+    double band_ratio;       /* lambda_hi / lambda_lo of one level band, in (1, 2] (2 = octaves) */
+    double A0;               /* dimensionless move amplitude (Eq. "Wavelet amplitude") */
+    double kT;               /* thermal energy */
+    int32_t bond_type;       /* WMC_BOND_* */
+    int32_t wca;             /* 1: WCA between all pairs */
+    double k_bond;           /* FENE k, or harmonic k of U = (k/2) r^2 */
+    double R0;               /* FENE maximum bond length */
+    double sigma, eps;       /* WCA parameters */
+    double r_int_harmonic;   /* interaction halo used with harmonic bonds (> longest bond) */
+    int32_t n_layers;        /* half-width of the discrete k cube (App. D, 15) */
+    int32_t retry_cap;       /* attempts per recycling chain before giving up (64) */
+    uint64_t seed;           /* Philox key */
+} wmc_params;
+
+/* Counters summed over systems (wmc_observables). */
+typedef struct {
+    int64_t sweeps;
+    int64_t trials[WMC_MAX_LEVELS];       /* trial centres drawn */
+    int64_t hits[WMC_MAX_LEVELS];         /* trials whose centre fell in their cell */
+    int64_t attempts[WMC_MAX_LEVELS];     /* Metropolis tests */
+    int64_t accepts[WMC_MAX_LEVELS];
+    int64_t caps[WMC_MAX_LEVELS];         /* chains ended by the retry cap */
+    int64_t redraws[WMC_MAX_LEVELS];      /* centre redraws that missed during retries */
+    int64_t bead_updates[WMC_MAX_LEVELS]; /* sum over attempts of the beads displaced */
+    int64_t pw_chains, pw_attempts, pw_accepts, pw_k0, pw_caps, pw_bead_updates;
+    int64_t violations;                   /* bonds found longer than the halo width */
+    int64_t accepted_total;               /* accepted chains, wavelet + plane wave */
+    int64_t rechecks;                     /* WMC_MIXED: decisions re-evaluated in FP64 */
+    int64_t overflows;                    /* cell lists that exceeded capacity (must be 0) */
+    int64_t grid_rebuilds;                /* neighbour-grid rebuilds */
+} wmc_obs;
+
+/* One trace record per Metropolis test (kind 0 wavelet, 2 plane wave) and per cell phase
+ * (kind 1: trial = trial count, retry = |S_c|, n = |H_c| or 0, accepted = hits). */
+typedef struct {
+    int32_t kind, system, sweep, level, cell, trial, retry, n, accepted, extra;
+    double dU, thr;
+} wmc_trace_rec;
+
+/* Bytes of device arena wmc_init needs for this problem (same arguments as wmc_init). */
+int wmc_arena_bytes(const wmc_params* p, int32_t n_systems, const int64_t* sys_bead_offset,
+                    const double* sys_box_L, const double* sys_lambda_max, int64_t n_chains,
+                    const int64_t* chain_offset, int64_t trace_capacity, size_t* out_bytes);
+
+/* Validate parameters, build the per-system schedule tables (levels, P_F, k tables, dt),
+ * copy the positions [N][3] to the device arena, check that the initial energy is finite.
+ * sys_box_L / sys_lambda_max may be NULL (then params.box_L / params.lambda_max apply to
+ * every system). trace_capacity > 0 reserves room for that many trace records. */
+int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t n_systems, const int64_t* sys_bead_offset,
+             const double* sys_box_L, const double* sys_lambda_max, int64_t n_chains,
+             const int64_t* chain_offset, const double* pos_xyz, int64_t trace_capacity,
+             void* device_arena, size_t arena_bytes, void* hip_stream);
+
+/* Run n_sweeps sweeps, asynchronously on hip_stream. One sweep = every wavelet level band
+ * in colour phases, then the plane-wave chains (Sec. IV-V as summarised above). */
+int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* hip_stream);
+
+/* Copy positions [N][3] FP64 to out_xyz: host memory (to_device = 0, synchronous) or device
+ * memory (to_device = 1, asynchronous on hip_stream). */
+int wmc_positions(wmc_ctx* c, double* out_xyz, int32_t to_device, void* hip_stream);
+
+/* Replace the positions (host [N][3]) and set the sweep counter (which keys the streams). */
+int wmc_set_state(wmc_ctx* c, const double* pos_xyz, int64_t sweep, void* hip_stream);
+
+/* Counters (synchronises the stream). */
+int wmc_observables(wmc_ctx* c, wmc_obs* out);
+
+/* Physical time per system in units of tau (Eq. "Unit of Time"): dt x accepted chains. */
+int wmc_system_tau(wmc_ctx* c, double* out /* [n_systems] */);
+
+/* Mean-square radius of gyration of every chain (Eq. "Radius of gyration"). */
+int wmc_chain_rg2(wmc_ctx* c, double* out /* [n_chains] */);
+
+/* Move up to max trace records to out (host) and clear the trace; returns the count in
+ * *n_out. Records are in completion order; sort by (sweep, system, level, cell, trial, retry). */
+int wmc_trace(wmc_ctx* c, wmc_trace_rec* out, int64_t max, int64_t* n_out);
+
+/* Schedule constants of one system, for inspection: per level (lo, hi, p, T, h, ncell) and
+ * (P_F, R, N_k, P_cube, P_k0, dt). levels_out holds 6 doubles per level. */
+int wmc_system_info(wmc_ctx* c, int32_t system, double* levels_out, int32_t* n_levels,
+                    double* pw_out /* 6 doubles */);
+
+/* Cell index of every bead of one system in the grid of (sweep, level) at the current
+ * positions (the cell a wavelet centre at that point would belong to). out is host [N_s]. */
+int wmc_cell_ids(wmc_ctx* c, int32_t system, int64_t sweep, int32_t level, int32_t* out);
+
+/* Philox4x32-10 on the device for n consecutive counters starting at ctr (ctr[0] is
+ * incremented), key fixed; out is host [n][4]. For cross-checking the generator. */
+int wmc_philox(const uint32_t ctr[4], const uint32_t key[2], int64_t n, uint32_t* out,
+               void* device_scratch, size_t scratch_bytes, void* hip_stream);
+
+const char* wmc_last_error(const wmc_ctx* c);
+void wmc_free(wmc_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -34,6 +34,10 @@ typedef struct {
     int32_t n_shell;
     double x_s;
     int64_t accepted;
+    /* linked-cell list for pair search (the cell index method), periodic systems only */
+    int32_t nc;          /* cells per axis, 0 = no list (scan every bead) */
+    double cg, invcg;    /* cell side >= r_cut + twice the largest plane-wave amplitude */
+    int64_t* head;       /* [nc^3] first bead of each cell, -1 if empty */
 } wo_system;
 
 typedef struct {
@@ -51,6 +55,9 @@ typedef struct {
     /* scratch */
     int64_t *S, *H, *M;
     int64_t* mark;
+    int64_t *cnext, *cprev, *ccell;  /* per bead: linked-cell neighbours and its cell */
+    int64_t* seen;                    /* per bead stamp for de-duplicating candidates */
+    int64_t seen_stamp;
     int64_t mark_stamp;
     double *nx, *ny, *nz;
     wo_trace_rec* trace;

@@ -167,6 +167,77 @@ static double dist2_cell(const grid_t* g, const int64_t ic[3], double x, double 
     return (acc[0] + acc[1]) + acc[2];
 }
 
+/* ------------------------------------------------------ linked cells (pair search) -- */
+static int64_t cl_cell(const wo_system* s, double x, double y, double z) {
+    double v[3] = {x, y, z};
+    int64_t c[3];
+    for (int a = 0; a < 3; ++a) {
+        double w = v[a] - s->L * floor(v[a] / s->L);
+        int64_t i = (int64_t)floor(w * s->invcg);
+        if (i >= s->nc) i = s->nc - 1;
+        if (i < 0) i = 0;
+        c[a] = i;
+    }
+    return c[0] + s->nc * (c[1] + s->nc * c[2]);
+}
+
+static void cl_insert(wo_ctx* c, wo_system* s, int64_t i, int64_t cell) {
+    c->ccell[i] = cell;
+    c->cprev[i] = -1;
+    c->cnext[i] = s->head[cell];
+    if (s->head[cell] >= 0) c->cprev[s->head[cell]] = i;
+    s->head[cell] = i;
+}
+
+static void cl_remove(wo_ctx* c, wo_system* s, int64_t i) {
+    int64_t cell = c->ccell[i];
+    if (c->cprev[i] >= 0) c->cnext[c->cprev[i]] = c->cnext[i];
+    else s->head[cell] = c->cnext[i];
+    if (c->cnext[i] >= 0) c->cprev[c->cnext[i]] = c->cprev[i];
+}
+
+/* keep the list in step with a bead's new position */
+static void cl_moved(wo_ctx* c, wo_system* s, int64_t i) {
+    if (!s->nc) return;
+    int64_t cell = cl_cell(s, c->x[i], c->y[i], c->z[i]);
+    if (cell == c->ccell[i]) return;
+    cl_remove(c, s, i);
+    cl_insert(c, s, i, cell);
+}
+
+static void cl_build(wo_ctx* c, wo_system* s) {
+    if (!s->nc) return;
+    int64_t nc3 = (int64_t)s->nc * s->nc * s->nc;
+    for (int64_t k = 0; k < nc3; ++k) s->head[k] = -1;
+    for (int64_t i = s->b0; i < s->b1; ++i) cl_insert(c, s, i, cl_cell(s, c->x[i], c->y[i], c->z[i]));
+}
+
+/* call fn(m) once for every bead within the 27 cells around each of the points p and q
+ * (every bead within r_cut of p or of q), or for every bead of the system without a list */
+typedef void (*cand_fn)(wo_ctx* c, wo_system* s, int64_t m, void* arg);
+static void cl_candidates(wo_ctx* c, wo_system* s, const double p[3], const double q[3], cand_fn fn, void* arg) {
+    if (!s->nc) {
+        for (int64_t m = s->b0; m < s->b1; ++m) fn(c, s, m, arg);
+        return;
+    }
+    int64_t stamp = ++c->seen_stamp;
+    const double* pts[2] = {p, q};
+    for (int w = 0; w < 2; ++w) {
+        int64_t cc = cl_cell(s, pts[w][0], pts[w][1], pts[w][2]);
+        int64_t cx = cc % s->nc, cy = (cc / s->nc) % s->nc, cz = cc / ((int64_t)s->nc * s->nc);
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int64_t ex = (cx + dx + s->nc) % s->nc, ey = (cy + dy + s->nc) % s->nc, ez = (cz + dz + s->nc) % s->nc;
+                    for (int64_t m = s->head[ex + s->nc * (ey + s->nc * ez)]; m >= 0; m = c->cnext[m]) {
+                        if (c->seen[m] == stamp) continue;
+                        c->seen[m] = stamp;
+                        fn(c, s, m, arg);
+                    }
+                }
+    }
+}
+
 /* ------------------------------------------------------------ one cell phase ----- */
 static int draw_centre(wo_ctx* c, wo_stream* st, const grid_t* g, int64_t cell, int64_t nS,
                        double lam, int64_t* anchor, double b[3]) {
@@ -197,6 +268,19 @@ static void draw_direction(wo_stream* st, double p[3]) {
     p[0] = vx / nrm;
     p[1] = vy / nrm;
     p[2] = vz / nrm;
+}
+
+typedef struct {
+    int64_t j, stamp;
+    double jx, jy, jz, kx, ky, kz, acc;
+} pair_arg;
+
+static void pair_nonmember(wo_ctx* c, wo_system* s, int64_t m, void* vp) {
+    pair_arg* a = (pair_arg*)vp;
+    if (m == a->j || c->mark[m] == a->stamp) return;
+    double r2o = pair_r2(c, s, a->jx, a->jy, a->jz, c->x[m], c->y[m], c->z[m]);
+    double r2n = pair_r2(c, s, a->kx, a->ky, a->kz, c->x[m], c->y[m], c->z[m]);
+    if (r2o < c->rc2 || r2n < c->rc2) a->acc += u_pair(c, r2n) - u_pair(c, r2o);
 }
 
 /* one Metropolis test of a wavelet move; returns 1 if accepted (positions updated) */
@@ -262,14 +346,16 @@ static int wavelet_attempt(wo_ctx* c, wo_system* s, int sysid, int level, int64_
             }
         }
         if (c->p.wca) {
-            for (int64_t q2 = 0; q2 < nH; ++q2) {
-                int64_t m = c->H[q2];
-                if (m == j) continue;
-                int mem = c->mark[m] == stamp;
-                if (mem && m < j) continue;
+            /* pairs with non-members near the old or new position of j */
+            pair_arg pa = {j, stamp, jx, jy, jz, kx, ky, kz, 0.0};
+            double po[3] = {jx, jy, jz}, pn[3] = {kx, ky, kz};
+            cl_candidates(c, s, po, pn, pair_nonmember, &pa);
+            dU += pa.acc;
+            /* pairs of two members, each once */
+            for (int64_t q2 = q + 1; q2 < n; ++q2) {
+                int64_t m = c->M[q2];
                 double r2o = pair_r2(c, s, jx, jy, jz, c->x[m], c->y[m], c->z[m]);
-                double r2n = mem ? pair_r2(c, s, kx, ky, kz, c->nx[m], c->ny[m], c->nz[m])
-                                 : pair_r2(c, s, kx, ky, kz, c->x[m], c->y[m], c->z[m]);
+                double r2n = pair_r2(c, s, kx, ky, kz, c->nx[m], c->ny[m], c->nz[m]);
                 if (r2o < c->rc2 || r2n < c->rc2) dU += u_pair(c, r2n) - u_pair(c, r2o);
             }
         }
@@ -285,6 +371,7 @@ static int wavelet_attempt(wo_ctx* c, wo_system* s, int sysid, int level, int64_
             c->x[j] = c->nx[j];
             c->y[j] = c->ny[j];
             c->z[j] = c->nz[j];
+            cl_moved(c, s, j);
         }
         c->obs.accepts[level]++;
     }
@@ -360,7 +447,13 @@ static void sample_k(wo_ctx* c, wo_system* s, wo_stream* st, int l[3]) {
         return;
     }
     double invks = s->L / (2.0 * WO_PI);
-    for (;;) {
+    for (int tries = 0;; ++tries) {
+        if (tries >= 100000) { /* bounded like the GPU path; not reached with valid tables */
+            l[0] = NL + 1;
+            l[1] = 0;
+            l[2] = 0;
+            return;
+        }
         double us = wo_next_co(st) * s->n_shell;
         int64_t i = (int64_t)floor(us);
         double fr = us - (double)i;
@@ -378,6 +471,20 @@ static void sample_k(wo_ctx* c, wo_system* s, wo_stream* st, int l[3]) {
         }
         if (ok && !inside) return;
     }
+}
+
+typedef struct {
+    int64_t j;
+    double acc;
+} pw_arg;
+
+static void pw_pair(wo_ctx* c, wo_system* s, int64_t m, void* vp) {
+    pw_arg* a = (pw_arg*)vp;
+    int64_t j = a->j;
+    if (m <= j) return;
+    double r2o = pair_r2(c, s, c->x[j], c->y[j], c->z[j], c->x[m], c->y[m], c->z[m]);
+    double r2n = pair_r2(c, s, c->nx[j], c->ny[j], c->nz[j], c->nx[m], c->ny[m], c->nz[m]);
+    if (r2o < c->rc2 || r2n < c->rc2) a->acc += u_pair(c, r2n) - u_pair(c, r2o);
 }
 
 static int pw_attempt(wo_ctx* c, wo_system* s, int sysid, int64_t h, int r, const int l[3],
@@ -417,12 +524,14 @@ static int pw_attempt(wo_ctx* c, wo_system* s, int sysid, int64_t h, int r, cons
         }
     }
     if (c->p.wca) {
-        for (int64_t j = s->b0; j < s->b1; ++j)
-            for (int64_t m = j + 1; m < s->b1; ++m) {
-                double r2o = pair_r2(c, s, c->x[j], c->y[j], c->z[j], c->x[m], c->y[m], c->z[m]);
-                double r2n = pair_r2(c, s, c->nx[j], c->ny[j], c->nz[j], c->nx[m], c->ny[m], c->nz[m]);
-                if (r2o < c->rc2 || r2n < c->rc2) dU += u_pair(c, r2n) - u_pair(c, r2o);
-            }
+        /* every pair j < m within r_cut before or after the move; both beads move by at most
+         * A_F, and the cell side exceeds r_cut + 2 A_F, so the 27 cells around j hold them */
+        for (int64_t j = s->b0; j < s->b1; ++j) {
+            pw_arg pa = {j, 0.0};
+            double po[3] = {c->x[j], c->y[j], c->z[j]};
+            cl_candidates(c, s, po, po, pw_pair, &pa);
+            dU += pa.acc;
+        }
     }
     double thr = -c->p.kT * log(u_acc);
     int acc = dU <= thr;
@@ -437,6 +546,7 @@ static int pw_attempt(wo_ctx* c, wo_system* s, int sysid, int64_t h, int r, cons
             c->y[j] = c->ny[j];
             c->z[j] = c->nz[j];
         }
+        cl_build(c, s);
         c->obs.pw_accepts++;
     }
     return acc;
@@ -531,6 +641,10 @@ int wo_init(void** out, const wo_params* p, int32_t n_systems, const int64_t* sy
     c->H = (int64_t*)malloc(sizeof(int64_t) * N);
     c->M = (int64_t*)malloc(sizeof(int64_t) * N);
     c->mark = (int64_t*)calloc(N, sizeof(int64_t));
+    c->seen = (int64_t*)calloc(N, sizeof(int64_t));
+    c->cnext = (int64_t*)malloc(sizeof(int64_t) * N);
+    c->cprev = (int64_t*)malloc(sizeof(int64_t) * N);
+    c->ccell = (int64_t*)malloc(sizeof(int64_t) * N);
     c->bond_next = (uint8_t*)calloc(N > 0 ? N : 1, 1);
     c->n_chains = n_chains;
     c->chain_off = (int64_t*)malloc(sizeof(int64_t) * (n_chains + 1));
@@ -568,6 +682,22 @@ int wo_init(void** out, const wo_params* p, int32_t n_systems, const int64_t* sy
             if (c->sys[sj].L / c->sys[sj].lmax == s->L / s->lmax) { donor = &c->sys[sj]; break; }
         int rc_ = wo_build_system_tables(c, s, donor);
         if (rc_) return rc_;
+        /* linked cells: side >= r_cut + 2 x the largest plane-wave amplitude (k = 2 pi / L) */
+        s->nc = 0;
+        s->head = NULL;
+        if (p->periodic && p->wca) {
+            double AFmax = p->plane_waves ? 2.0 * p->A0 / ((2.0 * WO_PI / s->L) * sqrt(5.0 * (double)s->N)) : 0.0;
+            double side = sqrt(c->rc2) + 2.0 * AFmax + 1e-6;
+            int nc = (int)floor(s->L / side);
+            if (nc > 200) nc = 200;
+            if (nc >= 3) {
+                s->nc = nc;
+                s->cg = s->L / nc;
+                s->invcg = 1.0 / s->cg;
+                s->head = (int64_t*)malloc(sizeof(int64_t) * (size_t)nc * nc * nc);
+                cl_build(c, s);
+            }
+        }
         /* initial state must have finite energy */
         for (int64_t j = s->b0; j + 1 < s->b1; ++j) {
             if (!c->bond_next[j]) continue;
@@ -595,6 +725,7 @@ int wo_set_positions(void* vctx, const double* xyz) {
         c->y[i] = xyz[3 * i + 1];
         c->z[i] = xyz[3 * i + 2];
     }
+    for (int si = 0; si < c->nsys; ++si) cl_build(c, &c->sys[si]);
     return 0;
 }
 
@@ -686,7 +817,11 @@ const char* wo_last_error(void* vctx) { return vctx ? ((wo_ctx*)vctx)->err : "no
 void wo_free(void* vctx) {
     wo_ctx* c = (wo_ctx*)vctx;
     if (!c) return;
-    for (int i = 0; i < c->nsys; ++i) wo_free_system_tables(&c->sys[i]);
+    for (int i = 0; i < c->nsys; ++i) {
+        wo_free_system_tables(&c->sys[i]);
+        free(c->sys[i].head);
+    }
+    free(c->seen); free(c->cnext); free(c->cprev); free(c->ccell);
     free(c->sys);
     free(c->x); free(c->y); free(c->z);
     free(c->nx); free(c->ny); free(c->nz);

@@ -1,0 +1,1229 @@
+// Device side of libwmc: the Wavelet Monte Carlo dynamics sweep on gfx950.
+//
+// One sweep (Dyer & Ball, arXiv:1611.09160, Sec. IV-V, App. D), per system:
+//   for each wavelet level band (ascending lambda):
+//     rebuild the neighbour grid (counting sort of beads into cells of side >= r_cut + skin);
+//     for colour 0..7: one workgroup per cell of that colour (k_phase). Cells of one colour are
+//     at least 2 lambda_hi + r_int apart, so their moves touch disjoint beads and halos and run
+//     concurrently with the same result as any serial order.
+//   plane-wave chains (k_pw), one workgroup per system.
+// Beads are SoA FP64 in HBM; every workgroup reads and writes them directly (write-through),
+// keeping its cell's reach list, member list and member trial positions in LDS.
+// All schedule-deciding arithmetic (cells, reach lists, anchors, lambda, centres, member
+// tests) uses only IEEE add/mul/div/sqrt/floor/rint with contraction off.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+#include "wmc_internal.h"
+
+namespace wmc {
+
+// ------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplies mixing the
+// four counter words with the key; the key is bumped by two Weyl constants between rounds.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t lo0 = 0xD2511F53u * c[0];
+        uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+        uint32_t lo1 = 0xCD9E8D57u * c[2];
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        uint32_t n0 = hi1 ^ c[1] ^ k0;
+        uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// A stream is the sequence of doubles of one counter prefix:
+//   c0 = (r << 24) | (j << 12) | block, c1 = (system << 20) | t, c2 = (tag << 24) | cell,
+//   c3 = sweep; double i uses words 2(i&1), 2(i&1)+1 of block i>>1 (53 bits).
+struct Stream {
+    uint32_t c0, c1, c2, c3, k0, k1;
+    uint32_t next;
+    int32_t cached;
+    uint32_t w[4];
+    __device__ void init(const DevParams& P, int sys, int64_t sweep, int tag, int64_t cell, int64_t t, int r, int j) {
+        c0 = ((uint32_t)(r & 0xFF) << 24) | ((uint32_t)(j & 0xFFF) << 12);
+        c1 = ((uint32_t)(sys & 0xFFF) << 20) | (uint32_t)(t & 0xFFFFF);
+        c2 = ((uint32_t)(tag & 0xFF) << 24) | (uint32_t)(cell & 0xFFFFFF);
+        c3 = (uint32_t)sweep;
+        k0 = P.seed_lo;
+        k1 = P.seed_hi;
+        next = 0;
+        cached = -1;
+    }
+    __device__ uint64_t bits() {
+        uint32_t i = next++;
+        int32_t blk = (int32_t)((i >> 1) & 0xFFFu);
+        if (blk != cached) {
+            w[0] = c0 | (uint32_t)blk;
+            w[1] = c1;
+            w[2] = c2;
+            w[3] = c3;
+            philox10(w, k0, k1);
+            cached = blk;
+        }
+        uint32_t hi = (i & 1) ? w[2] : w[0];
+        uint32_t lo = (i & 1) ? w[3] : w[1];
+        return ((uint64_t)hi << 21) | ((uint64_t)lo >> 11);
+    }
+    __device__ double co() { return (double)bits() * 0x1.0p-53; }
+    __device__ double oc() { return ((double)bits() + 1.0) * 0x1.0p-53; }
+    __device__ int64_t index(int64_t n) { return (int64_t)__umul64hi(bits() << 11, (uint64_t)n); }
+};
+
+// x^(-1/3) on [1/8, 1] by a fixed 8 Newton steps y <- y (4 - x y^3)/3 from the line through
+// (1/8, 2) and (1, 1); no libm, so lambda (and the centre's cell) is bit-reproducible.
+__device__ __forceinline__ double inv_cbrt(double x) {
+    double y = 2.0 - (x - 0.125) * (8.0 / 7.0);
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+        double y3 = y * y * y;
+        y = y * (4.0 - x * y3) / 3.0;
+    }
+    return y;
+}
+
+// lambda in [lo, hi) with PDF ~ lambda^-4 (inverse transform of App. D with band edges)
+__device__ __forceinline__ double draw_lambda(double u, double lo, double hi) {
+    double cr = lo / hi;
+    double c = cr * cr * cr;
+    double x = 1.0 + u * (c - 1.0);
+    return lo * inv_cbrt(x);
+}
+
+__device__ __forceinline__ void ball(Stream& s, double& vx, double& vy, double& vz) {
+    double ss;
+    do {
+        vx = 2.0 * s.co() - 1.0;
+        vy = 2.0 * s.co() - 1.0;
+        vz = 2.0 * s.co() - 1.0;
+        ss = (vx * vx + vy * vy) + vz * vz;
+    } while (ss > 1.0);
+}
+
+__device__ __forceinline__ void direction(Stream& s, double& px, double& py, double& pz) {
+    double vx, vy, vz, ss;
+    do {
+        vx = 2.0 * s.co() - 1.0;
+        vy = 2.0 * s.co() - 1.0;
+        vz = 2.0 * s.co() - 1.0;
+        ss = (vx * vx + vy * vy) + vz * vz;
+    } while (ss > 1.0 || ss == 0.0);
+    double nrm = sqrt(ss);
+    px = vx / nrm;
+    py = vy / nrm;
+    pz = vz / nrm;
+}
+
+// ------------------------------------------------------------------------------ energies
+// FENE (Eq. "FENE potential"), harmonic (zero rest length), WCA (Eq. "WCA potential")
+__device__ __forceinline__ double u_bond(const DevParams& P, double r2) {
+    if (P.bond_type == WMC_BOND_FENE) {
+        if (r2 >= P.R02) return INFINITY;
+        return -0.5 * P.k_bond * P.R02 * log(1.0 - r2 / P.R02);
+    }
+    if (P.bond_type == WMC_BOND_HARMONIC) return 0.5 * P.k_bond * r2;
+    return 0.0;
+}
+__device__ __forceinline__ double u_pair(const DevParams& P, double r2) {
+    if (r2 >= P.rc2) return 0.0;
+    if (r2 <= 0.0) return INFINITY;
+    double s2 = P.sigma2 / r2;
+    double s6 = s2 * s2 * s2;
+    return 4.0 * P.eps * (s6 * s6 - s6 + 0.25);
+}
+
+// FP32 energy terms with an error bound, for WMC_MIXED (see k_phase)
+__device__ __forceinline__ float u_bond_f(const DevParams& P, float r2) {
+    float R02 = (float)P.R02;
+    if (P.bond_type == WMC_BOND_FENE) {
+        if (r2 >= R02) return INFINITY;
+        return -0.5f * (float)P.k_bond * R02 * logf(1.0f - r2 / R02);
+    }
+    if (P.bond_type == WMC_BOND_HARMONIC) return 0.5f * (float)P.k_bond * r2;
+    return 0.0f;
+}
+__device__ __forceinline__ float u_pair_f(const DevParams& P, float r2) {
+    if (r2 >= (float)P.rc2) return 0.0f;
+    if (r2 <= 0.0f) return INFINITY;
+    float s2 = (float)P.sigma2 / r2;
+    float s6 = s2 * s2 * s2;
+    return 4.0f * (float)P.eps * (s6 * s6 - s6 + 0.25f);
+}
+// |dU/d(r2)| * r2, the sensitivity of a term to a relative error of r2
+__device__ __forceinline__ double sens_bond(const DevParams& P, double r2) {
+    if (P.bond_type == WMC_BOND_FENE) return r2 >= P.R02 ? INFINITY : 0.5 * P.k_bond * r2 / (1.0 - r2 / P.R02);
+    if (P.bond_type == WMC_BOND_HARMONIC) return 0.5 * P.k_bond * r2;
+    return 0.0;
+}
+__device__ __forceinline__ double sens_pair(const DevParams& P, double r2) {
+    if (r2 >= P.rc2) return 0.0;
+    double s2 = P.sigma2 / r2, s6 = s2 * s2 * s2;
+    return 4.0 * P.eps * (6.0 * s6 * s6 + 3.0 * s6);
+}
+
+// ------------------------------------------------------------------------------ geometry
+struct Grid {
+    double o[3];
+    double h, invh, half, L, invL;
+    int64_t n[3];
+    int periodic;
+};
+
+__device__ __forceinline__ double minimg(const Grid& g, double d) {
+    return g.periodic ? d - g.L * rint(d * g.invL) : d;
+}
+
+__device__ int64_t cell_of_point(const Grid& g, double bx, double by, double bz) {
+    double b[3] = {bx, by, bz};
+    int64_t ic[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double v = b[a];
+        if (g.periodic) v = v - g.L * floor(v * g.invL);
+        int64_t i = (int64_t)floor((v - g.o[a]) * g.invh);
+        if (g.periodic) {
+            i %= g.n[a];
+            if (i < 0) i += g.n[a];
+        } else if (i < 0 || i >= g.n[a]) {
+            return -1;
+        }
+        ic[a] = i;
+    }
+    return ic[0] + g.n[0] * (ic[1] + g.n[1] * ic[2]);
+}
+
+__device__ __forceinline__ double dist2_cell(const Grid& g, const int64_t ic[3], double x, double y, double z) {
+    double v[3] = {x, y, z}, acc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double cen = g.o[a] + ((double)ic[a] + 0.5) * g.h;
+        double d = minimg(g, v[a] - cen);
+        double e = fabs(d) - g.half;
+        if (e < 0.0) e = 0.0;
+        acc[a] = e * e;
+    }
+    return (acc[0] + acc[1]) + acc[2];
+}
+
+__device__ void make_grid(const DevParams& P, const DevPtrs& D, const SysDesc& s, const LevelDesc& lv, int sys,
+                          int level, int64_t sweep, Grid& g) {
+    g.h = lv.h;
+    g.invh = 1.0 / lv.h;
+    g.half = 0.5 * lv.h;
+    g.periodic = P.periodic;
+    if (P.periodic) {
+        Stream st;
+        st.init(P, sys, sweep, TAG_SHIFT + level, 0, 0, 0, 0);
+        g.L = s.L;
+        g.invL = 1.0 / s.L;
+        for (int a = 0; a < 3; ++a) {
+            g.o[a] = lv.h * st.co();
+            g.n[a] = lv.n;
+        }
+    } else {
+        g.L = 0.0;
+        g.invL = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            g.o[a] = D.igrid[a];
+            g.n[a] = (int64_t)D.igrid[3 + a];
+        }
+    }
+}
+
+__device__ __forceinline__ double pair_r2(const DevParams& P, double invL, double L, double ax, double ay, double az,
+                                          double bx, double by, double bz) {
+    double dx = ax - bx, dy = ay - by, dz = az - bz;
+    if (P.periodic) {
+        dx = dx - L * rint(dx * invL);
+        dy = dy - L * rint(dy * invL);
+        dz = dz - L * rint(dz * invL);
+    }
+    return (dx * dx + dy * dy) + dz * dz;
+}
+
+__device__ __forceinline__ double wrap01(double v, double L, double invL) {
+    double w = v - L * floor(v * invL);
+    return w >= L ? 0.0 : w;
+}
+
+// range of neighbour-grid cells covering [lo, hi] on one axis (wrapped); count >= nf -> all
+__device__ __forceinline__ void fine_range(double lo, double hi, double invg, int nf, int& f0, int& cnt) {
+    int a = (int)floor(lo * invg), b = (int)floor(hi * invg);
+    cnt = b - a + 1;
+    if (cnt >= nf) {
+        f0 = 0;
+        cnt = nf;
+    } else {
+        f0 = ((a % nf) + nf) % nf;
+    }
+}
+
+// ------------------------------------------------------------------- workgroup helpers
+template <int W>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < W / 64; ++i) t += red[i];
+    return t;
+}
+template <int W>
+__device__ __forceinline__ double block_max(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double t = red[0];
+    for (int i = 1; i < W / 64; ++i) t = fmax(t, red[i]);
+    return t;
+}
+template <int W>
+__device__ __forceinline__ int block_min_int(int v, int* redi) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) redi[wv] = v;
+    __syncthreads();
+    int t = redi[0];
+    for (int i = 1; i < W / 64; ++i) t = min(t, redi[i]);
+    return t;
+}
+// exclusive prefix of a flag over the workgroup in thread order; returns the total
+template <int W>
+__device__ __forceinline__ int block_scan_flag(bool f, int& before, int* redi) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint64_t m = __ballot(f);
+    int in_wave = __popcll(m & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (lane == 0) redi[wv] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < W / 64; ++i) {
+        if (i < wv) off += redi[i];
+        tot += redi[i];
+    }
+    before = off + in_wave;
+    return tot;
+}
+
+__device__ __forceinline__ void atomic_max_double(unsigned long long* p, double v) {
+    // non-negative doubles order like their bit patterns
+    atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ void trace_push(const DevPtrs& D, int kind, int sys, int64_t sweep, int level, int64_t cell, int64_t trial,
+                           int retry, int64_t n, int acc, int extra, double dU, double thr) {
+    if (!D.trace) return;
+    unsigned long long i = atomicAdd(D.trace_n, 1ull);
+    if ((int64_t)i >= D.trace_cap) return;
+    wmc_trace_rec r;
+    r.kind = kind;
+    r.system = sys;
+    r.sweep = (int32_t)sweep;
+    r.level = level;
+    r.cell = (int32_t)cell;
+    r.trial = (int32_t)trial;
+    r.retry = retry;
+    r.n = (int32_t)n;
+    r.accepted = acc;
+    r.extra = extra;
+    r.dU = dU;
+    r.thr = thr;
+    D.trace[i] = r;
+}
+
+// ------------------------------------------------------------------ neighbour grid build
+__global__ void k_fine_count(DevPtrs D, int64_t N) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const SysDesc& s = D.sys[D.sys_id[i]];
+    double x = D.x[i], y = D.y[i], z = D.z[i];
+    D.xb[i] = x;
+    D.yb[i] = y;
+    D.zb[i] = z;
+    int nf = s.nf;
+    int cx = min(nf - 1, (int)floor(wrap01(x, s.L, s.invL) * s.invg));
+    int cy = min(nf - 1, (int)floor(wrap01(y, s.L, s.invL) * s.invg));
+    int cz = min(nf - 1, (int)floor(wrap01(z, s.L, s.invL) * s.invg));
+    int32_t fc = (int32_t)(s.fine_off + cx + (int64_t)nf * (cy + (int64_t)nf * cz));
+    D.fcell[i] = fc;
+    atomicAdd(&D.fcount[fc], 1);
+}
+
+// exclusive scan of the counts by one workgroup; also clears the per-system drift
+__global__ __launch_bounds__(1024) void k_fine_scan(DevPtrs D, int nsys) {
+    __shared__ int part[1024];
+    const int64_t T = D.total_fine;
+    const int tid = threadIdx.x;
+    const int64_t per = (T + 1023) / 1024;
+    const int64_t a = tid * per, b = min(T, a + per);
+    int acc = 0;
+    for (int64_t i = a; i < b; ++i) acc += D.fcount[i];
+    part[tid] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int i = 0; i < 1024; ++i) {
+            int v = part[i];
+            part[i] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int run = part[tid];
+    for (int64_t i = a; i < b; ++i) {
+        int v = D.fcount[i];
+        D.fstart[i] = run;
+        D.fcount[i] = 0;
+        run += v;
+    }
+    if (tid == 1023) D.fstart[T] = run;
+    for (int s = tid; s < nsys; s += 1024) D.drift[s] = 0ull;
+    if (tid == 0) atomicAdd(&D.cnt[CNT_REBUILD], 1ull);
+}
+
+__global__ void k_fine_scatter(DevPtrs D, int64_t N) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int32_t fc = D.fcell[i];
+    int pos = D.fstart[fc] + atomicAdd(&D.fcount[fc], 1);
+    D.fidx[pos] = (int32_t)i;
+}
+
+// order each cell's beads by index (deterministic candidate order) and clear the cursor
+__global__ void k_fine_sort(DevPtrs D) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= D.total_fine) return;
+    int a = D.fstart[c], b = D.fstart[c + 1];
+    for (int i = a + 1; i < b; ++i) {
+        int32_t v = D.fidx[i];
+        int j = i - 1;
+        while (j >= a && D.fidx[j] > v) {
+            D.fidx[j + 1] = D.fidx[j];
+            --j;
+        }
+        D.fidx[j + 1] = v;
+    }
+    D.fcount[c] = 0;
+}
+
+void launch_fine_build(const DevParams& P, const DevPtrs& D, int64_t N, hipStream_t st) {
+    if (N == 0) return;
+    int nb = (int)((N + 255) / 256);
+    hipLaunchKernelGGL(k_fine_count, dim3(nb), dim3(256), 0, st, D, N);
+    hipLaunchKernelGGL(k_fine_scan, dim3(1), dim3(1024), 0, st, D, P.nsys);
+    hipLaunchKernelGGL(k_fine_scatter, dim3(nb), dim3(256), 0, st, D, N);
+    int nc = (int)((D.total_fine + 255) / 256);
+    hipLaunchKernelGGL(k_fine_sort, dim3(nc), dim3(256), 0, st, D);
+}
+
+// ------------------------------------------------------- infinite-system level grid
+__global__ __launch_bounds__(1024) void k_bbox(DevParams P, DevPtrs D, int level, int64_t sweep) {
+    __shared__ double red[16];
+    const SysDesc& s = D.sys[0];
+    const LevelDesc& lv = D.lev[s.lvl_off + level];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = s.b0 + threadIdx.x; i < s.b1; i += 1024) {
+        double v[3] = {D.x[i], D.y[i], D.z[i]};
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = fmin(mn[a], v[a]);
+            mx[a] = fmax(mx[a], v[a]);
+        }
+    }
+    double gmn[3], gmx[3];
+    for (int a = 0; a < 3; ++a) {
+        gmn[a] = -block_max<1024>(-mn[a], red);
+        gmx[a] = block_max<1024>(mx[a], red);
+    }
+    if (threadIdx.x == 0) {
+        Stream st;
+        st.init(P, 0, sweep, TAG_SHIFT + level, 0, 0, 0, 0);
+        double invh = 1.0 / lv.h;
+        for (int a = 0; a < 3; ++a) {
+            double o = gmn[a] - lv.hi - lv.h * st.co();
+            D.igrid[a] = o;
+            D.igrid[3 + a] = (double)((int64_t)floor((gmx[a] + lv.hi - o) * invh) + 1);
+        }
+    }
+}
+
+void launch_bbox(const DevParams& P, const DevPtrs& D, int level, int64_t sweep, hipStream_t st) {
+    hipLaunchKernelGGL(k_bbox, dim3(1), dim3(1024), 0, st, P, D, level, sweep);
+}
+
+// --------------------------------------------------------------------- cell phase
+// One workgroup processes one cell of the current colour:
+//  1. reach list S_c = beads within lambda_hi of the cell, ascending index (from the
+//     neighbour grid and an LDS bitonic sort, or a bead-order scan for large cells);
+//  2. K_c = stochastic rounding of T_l |S_c| / N trials;
+//  3. trials are evaluated W at a time in parallel (each trial has its own stream and only
+//     reads positions), the first hit starts a recycling chain run by the whole workgroup:
+//     direction, members (ballot compaction), displacement, dU over bonds and WCA pairs
+//     (neighbour grid), reduction, Metropolis test, write-through on accept; after a
+//     rejection W centre redraws are tried in parallel and the first hit continues.
+template <int W, int CAPS, int CAPM>
+struct PhaseShared {
+    int32_t S[CAPS];
+    int32_t M[CAPM];
+    double MX[CAPM], MY[CAPM], MZ[CAPM];
+    double red[W / 64 > 0 ? W / 64 : 1];
+    int redi[W / 64 > 0 ? W / 64 : 1];
+    int count;
+    double pub_b[3];
+    double pub_lam;
+    int32_t pub_a;
+    uint32_t pub_next;
+};
+
+template <int W, int CAPS, int CAPM>
+__device__ void process_cell(const DevParams& P, const DevPtrs& D, PhaseShared<W, CAPS, CAPM>& sh, int sys,
+                             int level, int colour, int64_t local, int64_t sweep, const Grid& g) {
+    const SysDesc& s = D.sys[sys];
+    const LevelDesc& lv = D.lev[s.lvl_off + level];
+    const int tid = threadIdx.x;
+    // cell coordinates of the local-th cell of this colour
+    int64_t ic[3];
+    if (P.periodic) {
+        int64_t m = lv.n >= 2 ? lv.n / 2 : 1;
+        ic[0] = 2 * (local % m) + (lv.n >= 2 ? (colour & 1) : 0);
+        ic[1] = 2 * ((local / m) % m) + (lv.n >= 2 ? ((colour >> 1) & 1) : 0);
+        ic[2] = 2 * (local / (m * m)) + (lv.n >= 2 ? ((colour >> 2) & 1) : 0);
+    } else {
+        int64_t mx = (g.n[0] - (colour & 1) + 1) / 2, my = (g.n[1] - ((colour >> 1) & 1) + 1) / 2;
+        ic[0] = 2 * (local % mx) + (colour & 1);
+        ic[1] = 2 * ((local / mx) % my) + ((colour >> 1) & 1);
+        ic[2] = 2 * (local / (mx * my)) + ((colour >> 2) & 1);
+    }
+    const int64_t cell = ic[0] + g.n[0] * (ic[1] + g.n[1] * ic[2]);
+    const double hi2 = lv.hi * lv.hi;
+    const double Dg = __longlong_as_double((long long)D.drift[sys]);
+    const bool glob = lv.use_global != 0;
+    int32_t* Sg = D.slot_S + (lv.slot_base + local) * D.slot_len;
+    int32_t* Mg = D.slot_M + (lv.slot_base + local) * D.slot_len;
+    double* MXg = D.slot_MX + (lv.slot_base + local) * 3 * D.slot_len;
+
+    // ---- 1. reach list
+    int nS = 0;
+    bool overflow = false;
+    if (lv.identity) {
+        nS = s.N;
+    } else if (glob || !P.periodic) {
+        // bead-order scan of the system, compacted in order
+        int32_t* dst = glob ? Sg : sh.S;
+        int base = 0;
+        for (int64_t c0 = s.b0; c0 < s.b1; c0 += W) {
+            int64_t j = c0 + tid;
+            bool f = false;
+            if (j < s.b1) f = dist2_cell(g, ic, D.x[j], D.y[j], D.z[j]) <= hi2;
+            int before;
+            int tot = block_scan_flag<W>(f, before, sh.redi);
+            if (f) {
+                int idx = base + before;
+                if (glob || idx < CAPS) dst[idx] = (int32_t)j;
+            }
+            base += tot;
+        }
+        nS = base;
+        if (!glob && nS > CAPS) overflow = true;
+    } else {
+        // neighbour-grid gather into LDS, then bitonic sort by bead index
+        if (tid == 0) sh.count = 0;
+        __syncthreads();
+        double R = lv.hi + Dg + 1e-9 * s.L;
+        int f0[3], cn[3];
+        for (int a = 0; a < 3; ++a) {
+            double lo = g.o[a] + (double)ic[a] * g.h - R;
+            fine_range(lo, lo + g.h + 2.0 * R, s.invg, s.nf, f0[a], cn[a]);
+        }
+        const int total = cn[0] * cn[1] * cn[2];
+        for (int q = tid; q < total; q += W) {
+            int qx = q % cn[0], qy = (q / cn[0]) % cn[1], qz = q / (cn[0] * cn[1]);
+            int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
+            int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
+            for (int k = D.fstart[fc]; k < D.fstart[fc + 1]; ++k) {
+                int32_t j = D.fidx[k];
+                if (dist2_cell(g, ic, D.x[j], D.y[j], D.z[j]) <= hi2) {
+                    int idx = atomicAdd(&sh.count, 1);
+                    if (idx < CAPS) sh.S[idx] = j;
+                }
+            }
+        }
+        __syncthreads();
+        nS = sh.count;
+        if (nS > CAPS) {
+            overflow = true;
+        } else if (nS > 1) {
+            int np2 = 1;
+            while (np2 < nS) np2 <<= 1;
+            for (int i = nS + tid; i < np2; i += W) sh.S[i] = 0x7FFFFFFF;
+            __syncthreads();
+            for (int k = 2; k <= np2; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int i = tid; i < np2; i += W) {
+                        int l = i ^ j;
+                        if (l > i) {
+                            int32_t a = sh.S[i], b = sh.S[l];
+                            bool up = (i & k) == 0;
+                            if ((a > b) == up) {
+                                sh.S[i] = b;
+                                sh.S[l] = a;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (overflow) {
+        if (tid == 0) atomicAdd(&D.cnt[CNT_OVERFLOW], 1ull);
+        return;
+    }
+    const int32_t* S = lv.identity ? nullptr : (glob ? Sg : sh.S);
+    auto Sat = [&](int64_t i) -> int32_t { return S ? S[i] : (int32_t)(s.b0 + i); };
+
+    // ---- 2. number of trials
+    double mu = (lv.T * (double)nS) / (double)s.N;
+    int64_t K = (int64_t)floor(mu);
+    {
+        Stream ms;
+        ms.init(P, sys, sweep, TAG_META + level, cell, 0, 0, 0);
+        if (ms.co() < mu - (double)K) K += 1;
+    }
+    if (K > 0xFFFFF) {
+        K = 0xFFFFF;
+        if (tid == 0) atomicAdd(&D.cnt[CNT_VIOL], 1ull);
+    }
+    unsigned long long c_hits = 0, c_att = 0, c_acc = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0;
+    double d_local = 0.0;  // max drift of beads moved in this phase
+
+    const bool mixed = P.precision == WMC_MIXED;
+    const double L = s.L, invL = s.invL;
+    const double lam_hi = lv.hi;
+
+    // ---- 3. trials and chains
+    for (int64_t t0 = 0; t0 < K;) {
+        int64_t t = t0 + tid;
+        bool hit = false;
+        double lam = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
+        int32_t a = 0;
+        Stream st;
+        if (t < K && nS > 0) {
+            st.init(P, sys, sweep, level, cell, t, 0, 0);
+            lam = draw_lambda(st.co(), lv.lo, lam_hi);
+            a = Sat(st.index(nS));
+            double vx, vy, vz;
+            ball(st, vx, vy, vz);
+            bx = D.x[a] + lam * vx;
+            by = D.y[a] + lam * vy;
+            bz = D.z[a] + lam * vz;
+            hit = cell_of_point(g, bx, by, bz) == cell;
+        }
+        int first = block_min_int<W>(hit ? (int)(t - t0) : 0x7FFFFFFF, sh.redi);
+        if (first == 0x7FFFFFFF) {
+            t0 += W;
+            continue;
+        }
+        if (tid == first) {
+            sh.pub_lam = lam;
+            sh.pub_a = a;
+            sh.pub_b[0] = bx;
+            sh.pub_b[1] = by;
+            sh.pub_b[2] = bz;
+            sh.pub_next = st.next;
+        }
+        __syncthreads();
+        const int64_t tc = t0 + first;
+        lam = sh.pub_lam;
+        a = sh.pub_a;
+        double b[3] = {sh.pub_b[0], sh.pub_b[1], sh.pub_b[2]};
+        uint32_t nxt = sh.pub_next;
+        int jtry = 0;
+        ++c_hits;
+        const double lam2 = lam * lam;
+        for (int r = 0;;) {
+            // direction and acceptance draw continue the stream of (tc, r, jtry)
+            Stream cs;
+            cs.init(P, sys, sweep, level, cell, tc, r, jtry);
+            cs.next = nxt;
+            double px, py, pz;
+            direction(cs, px, py, pz);
+            const double u_acc = cs.oc();
+            __syncthreads();
+            // members: reach-list beads within lambda of b, plus the anchor, in list order
+            int32_t* Ml = glob ? Mg : sh.M;
+            double *MXl = glob ? MXg : sh.MX, *MYl = glob ? MXg + D.slot_len : sh.MY,
+                   *MZl = glob ? MXg + 2 * D.slot_len : sh.MZ;
+            int n = 0;
+            for (int c0 = 0; c0 < nS; c0 += W) {
+                int i = c0 + tid;
+                bool f = false;
+                int32_t j = 0;
+                if (i < nS) {
+                    j = Sat(i);
+                    double dx = minimg(g, D.x[j] - b[0]), dy = minimg(g, D.y[j] - b[1]), dz = minimg(g, D.z[j] - b[2]);
+                    double d2 = (dx * dx + dy * dy) + dz * dz;
+                    f = d2 <= lam2 || j == a;
+                }
+                int before;
+                int tot = block_scan_flag<W>(f, before, sh.redi);
+                if (f && (glob || n + before < CAPM)) Ml[n + before] = j;
+                n += tot;
+            }
+            if (!glob && n > CAPM) {
+                if (tid == 0) atomicAdd(&D.cnt[CNT_OVERFLOW], 1ull);
+                __syncthreads();
+                return;
+            }
+            const double A = P.A0 * lam / sqrt((double)n);
+            double dmax_l = 0.0;
+            for (int k = tid; k < n; k += W) {
+                int32_t j = Ml[k];
+                double xr0 = minimg(g, D.x[j] - b[0]) / lam;
+                double xr1 = minimg(g, D.y[j] - b[1]) / lam;
+                double xr2 = minimg(g, D.z[j] - b[2]) / lam;
+                double rr = sqrt((xr0 * xr0 + xr1 * xr1) + xr2 * xr2);
+                double f = rr < 1.0 ? A * (1.0 - rr) : 0.0;
+                double w0 = f * (py * xr2 - pz * xr1);
+                double w1 = f * (pz * xr0 - px * xr2);
+                double w2 = f * (px * xr1 - py * xr0);
+                MXl[k] = D.x[j] + w0;
+                MYl[k] = D.y[j] + w1;
+                MZl[k] = D.z[j] + w2;
+                D.tag[j] = k;
+                dmax_l = fmax(dmax_l, sqrt((w0 * w0 + w1 * w1) + w2 * w2));
+            }
+            const double dmax = block_max<W>(dmax_l, sh.red);  // includes a barrier: tags visible
+            const double D_eff = fmax(Dg, d_local);
+            // energy change over bonds and WCA pairs touching the members, each once
+            double acc = 0.0, accf = 0.0, sens = 0.0;
+            for (int k = tid; k < n; k += W) {
+                int32_t j = Ml[k];
+                double jx = D.x[j], jy = D.y[j], jz = D.z[j];
+                double kx = MXl[k], ky = MYl[k], kz = MZl[k];
+                if (P.bond_type != WMC_BOND_NONE) {
+                    int32_t part[2] = {-1, -1};
+                    if (j + 1 < s.b1 && D.bond_next[j]) part[0] = j + 1;
+                    if (j > s.b0 && D.bond_next[j - 1]) part[1] = j - 1;
+                    for (int e = 0; e < 2; ++e) {
+                        int32_t m = part[e];
+                        if (m < 0) continue;
+                        int km = D.tag[m];
+                        if (km >= 0 && m < j) continue;
+                        double mx = D.x[m], my = D.y[m], mz = D.z[m];
+                        double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my, nz = km >= 0 ? MZl[km] : mz;
+                        double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
+                        double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
+                        if (r2o > P.r_int * P.r_int) ++c_viol;
+                        if (mixed) {
+                            accf += (double)(u_bond_f(P, (float)r2n) - u_bond_f(P, (float)r2o));
+                            sens += sens_bond(P, r2n) + sens_bond(P, r2o);
+                        } else {
+                            acc += u_bond(P, r2n) - u_bond(P, r2o);
+                        }
+                    }
+                }
+                if (P.wca) {
+                    auto pair_term = [&](int32_t m) {
+                        if (m == j) return;
+                        int km = D.tag[m];
+                        if (km >= 0 && m < j) return;
+                        double mx = D.x[m], my = D.y[m], mz = D.z[m];
+                        double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my, nz = km >= 0 ? MZl[km] : mz;
+                        double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
+                        double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
+                        if (r2o < P.rc2 || r2n < P.rc2) {
+                            if (mixed) {
+                                accf += (double)(u_pair_f(P, (float)r2n) - u_pair_f(P, (float)r2o));
+                                sens += sens_pair(P, r2n) + sens_pair(P, r2o);
+                            } else {
+                                acc += u_pair(P, r2n) - u_pair(P, r2o);
+                            }
+                        }
+                    };
+                    if (P.periodic) {
+                        double R = P.rc + 2.0 * dmax + D_eff + 1e-9 * L;
+                        double cx = wrap01(jx, L, invL), cy = wrap01(jy, L, invL), cz = wrap01(jz, L, invL);
+                        int f0[3], cn[3];
+                        fine_range(cx - R, cx + R, s.invg, s.nf, f0[0], cn[0]);
+                        fine_range(cy - R, cy + R, s.invg, s.nf, f0[1], cn[1]);
+                        fine_range(cz - R, cz + R, s.invg, s.nf, f0[2], cn[2]);
+                        for (int qz = 0; qz < cn[2]; ++qz)
+                            for (int qy = 0; qy < cn[1]; ++qy)
+                                for (int qx = 0; qx < cn[0]; ++qx) {
+                                    int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
+                                    int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
+                                    for (int q = D.fstart[fc]; q < D.fstart[fc + 1]; ++q) pair_term(D.fidx[q]);
+                                }
+                    } else {
+                        for (int64_t m = s.b0; m < s.b1; ++m) pair_term((int32_t)m);
+                    }
+                }
+            }
+            double dU;
+            const double thr = -P.kT * log(u_acc);
+            if (mixed) {
+                // FP32 terms summed in FP64; each FP32 term is within ~4 ulp of r2 and of the
+                // energy: re-evaluate in FP64 when the decision is within the bound
+                double dU32 = block_sum<W>(accf, sh.red);
+                double bound = 64.0 * 0x1.0p-23 * block_sum<W>(sens, sh.red) + 1e-12;
+                if (isfinite(dU32) && fabs(dU32 - thr) > bound) {
+                    dU = dU32;
+                } else {
+                    // FP64 re-evaluation, same loops
+                    double acc64 = 0.0;
+                    for (int k = tid; k < n; k += W) {
+                        int32_t j = Ml[k];
+                        double jx = D.x[j], jy = D.y[j], jz = D.z[j];
+                        double kx = MXl[k], ky = MYl[k], kz = MZl[k];
+                        if (P.bond_type != WMC_BOND_NONE) {
+                            int32_t part[2] = {-1, -1};
+                            if (j + 1 < s.b1 && D.bond_next[j]) part[0] = j + 1;
+                            if (j > s.b0 && D.bond_next[j - 1]) part[1] = j - 1;
+                            for (int e = 0; e < 2; ++e) {
+                                int32_t m = part[e];
+                                if (m < 0) continue;
+                                int km = D.tag[m];
+                                if (km >= 0 && m < j) continue;
+                                double mx = D.x[m], my = D.y[m], mz = D.z[m];
+                                double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my,
+                                       nz = km >= 0 ? MZl[km] : mz;
+                                acc64 += u_bond(P, pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz)) -
+                                         u_bond(P, pair_r2(P, invL, L, jx, jy, jz, mx, my, mz));
+                            }
+                        }
+                        if (P.wca) {
+                            auto pair64 = [&](int32_t m) {
+                                if (m == j) return;
+                                int km = D.tag[m];
+                                if (km >= 0 && m < j) return;
+                                double mx = D.x[m], my = D.y[m], mz = D.z[m];
+                                double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my,
+                                       nz = km >= 0 ? MZl[km] : mz;
+                                double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
+                                double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
+                                if (r2o < P.rc2 || r2n < P.rc2) acc64 += u_pair(P, r2n) - u_pair(P, r2o);
+                            };
+                            if (P.periodic) {
+                                double R = P.rc + 2.0 * dmax + D_eff + 1e-9 * L;
+                                double cx = wrap01(jx, L, invL), cy = wrap01(jy, L, invL), cz = wrap01(jz, L, invL);
+                                int f0[3], cn[3];
+                                fine_range(cx - R, cx + R, s.invg, s.nf, f0[0], cn[0]);
+                                fine_range(cy - R, cy + R, s.invg, s.nf, f0[1], cn[1]);
+                                fine_range(cz - R, cz + R, s.invg, s.nf, f0[2], cn[2]);
+                                for (int qz = 0; qz < cn[2]; ++qz)
+                                    for (int qy = 0; qy < cn[1]; ++qy)
+                                        for (int qx = 0; qx < cn[0]; ++qx) {
+                                            int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf,
+                                                fz = (f0[2] + qz) % s.nf;
+                                            int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
+                                            for (int q = D.fstart[fc]; q < D.fstart[fc + 1]; ++q) pair64(D.fidx[q]);
+                                        }
+                            } else {
+                                for (int64_t m = s.b0; m < s.b1; ++m) pair64((int32_t)m);
+                            }
+                        }
+                    }
+                    dU = block_sum<W>(acc64, sh.red);
+                    if (tid == 0) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
+                }
+            } else {
+                dU = block_sum<W>(acc, sh.red);
+            }
+            const bool accept = dU <= thr;
+            if (tid == 0) trace_push(D, 0, sys, sweep, level, cell, tc, r, n, accept ? 1 : 0, a, dU, thr);
+            ++c_att;
+            c_beads += n;
+            for (int k = tid; k < n; k += W) {
+                int32_t j = Ml[k];
+                if (accept) {
+                    double nx = MXl[k], ny = MYl[k], nz = MZl[k];
+                    D.x[j] = nx;
+                    D.y[j] = ny;
+                    D.z[j] = nz;
+                    double dd = fmax(fabs(nx - D.xb[j]), fmax(fabs(ny - D.yb[j]), fabs(nz - D.zb[j])));
+                    d_local = fmax(d_local, dd);
+                }
+                D.tag[j] = -1;
+            }
+            d_local = block_max<W>(d_local, sh.red);  // barrier: writes visible
+            if (accept) {
+                ++c_acc;
+                break;
+            }
+            if (++r >= P.retry_cap) {
+                ++c_caps;
+                break;
+            }
+            // recycle lambda: redraw anchor and centre until the centre is in the cell
+            int found = -1;
+            for (int j0 = 0; j0 < 4096 && found < 0; j0 += W) {
+                int jj = j0 + tid;
+                bool h2 = false;
+                double ex = 0, ey = 0, ez = 0;
+                int32_t a2 = 0;
+                Stream rs;
+                if (jj < 4096) {
+                    rs.init(P, sys, sweep, level, cell, tc, r, jj);
+                    a2 = Sat(rs.index(nS));
+                    double vx, vy, vz;
+                    ball(rs, vx, vy, vz);
+                    ex = D.x[a2] + lam * vx;
+                    ey = D.y[a2] + lam * vy;
+                    ez = D.z[a2] + lam * vz;
+                    h2 = cell_of_point(g, ex, ey, ez) == cell;
+                }
+                int fj = block_min_int<W>(h2 ? jj : 0x7FFFFFFF, sh.redi);
+                if (fj != 0x7FFFFFFF) {
+                    if (jj == fj) {
+                        sh.pub_a = a2;
+                        sh.pub_b[0] = ex;
+                        sh.pub_b[1] = ey;
+                        sh.pub_b[2] = ez;
+                        sh.pub_next = rs.next;
+                    }
+                    found = fj;
+                }
+            }
+            __syncthreads();
+            if (found < 0) {
+                c_redraw += 4096;
+                ++c_caps;
+                break;
+            }
+            c_redraw += (unsigned long long)found;
+            a = sh.pub_a;
+            b[0] = sh.pub_b[0];
+            b[1] = sh.pub_b[1];
+            b[2] = sh.pub_b[2];
+            nxt = sh.pub_next;
+            jtry = found;
+            __syncthreads();
+        }
+        t0 = tc + 1;
+    }
+    // ---- counters
+    unsigned long long viol_all = (unsigned long long)block_sum<W>((double)c_viol, sh.red);
+    if (tid == 0) {
+        unsigned long long* C = D.cnt + CNT_LEVEL + level * 8;
+        atomicAdd(&C[0], (unsigned long long)K);
+        atomicAdd(&C[1], c_hits);
+        atomicAdd(&C[2], c_att);
+        atomicAdd(&C[3], c_acc);
+        atomicAdd(&C[4], c_caps);
+        atomicAdd(&C[5], c_redraw);
+        atomicAdd(&C[6], c_beads);
+        if (viol_all) atomicAdd(&D.cnt[CNT_VIOL], viol_all);
+        if (c_acc) {
+            atomicAdd(&D.cnt[CNT_ACCEPTED], c_acc);
+            atomicAdd(&D.sys_acc[sys], c_acc);
+        }
+        if (d_local > 0.0) atomic_max_double(&D.drift[sys], d_local);
+        trace_push(D, 1, sys, sweep, level, cell, K, nS, 0, (int)c_hits, 0, 0.0, 0.0);
+    }
+    __syncthreads();
+}
+
+template <int W, int CAPS, int CAPM>
+__global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, int colour, int64_t sweep,
+                                             const int32_t* bmap, int nblocks) {
+    __shared__ PhaseShared<W, CAPS, CAPM> sh;
+    if (P.periodic) {
+        const int sys = bmap[2 * blockIdx.x], local = bmap[2 * blockIdx.x + 1];
+        const SysDesc& s = D.sys[sys];
+        const LevelDesc& lv = D.lev[s.lvl_off + level];
+        Grid g;
+        make_grid(P, D, s, lv, sys, level, sweep, g);
+        process_cell<W, CAPS, CAPM>(P, D, sh, sys, level, colour, local, sweep, g);
+    } else {
+        const SysDesc& s = D.sys[0];
+        const LevelDesc& lv = D.lev[s.lvl_off + level];
+        Grid g;
+        make_grid(P, D, s, lv, 0, level, sweep, g);
+        int64_t mx = (g.n[0] - (colour & 1) + 1) / 2, my = (g.n[1] - ((colour >> 1) & 1) + 1) / 2,
+                mz = (g.n[2] - ((colour >> 2) & 1) + 1) / 2;
+        int64_t cells = mx * my * mz;
+        for (int64_t local = blockIdx.x; local < cells; local += gridDim.x)
+            process_cell<W, CAPS, CAPM>(P, D, sh, 0, level, colour, local, sweep, g);
+    }
+}
+
+void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
+                  const int32_t* bmap, int nblocks, hipStream_t st) {
+    if (nblocks <= 0) return;
+    if (variant == V64)
+        hipLaunchKernelGGL((k_phase<64, 512, 128>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour, sweep, bmap,
+                           nblocks);
+    else if (variant == V256)
+        hipLaunchKernelGGL((k_phase<256, 4096, 1024>), dim3(nblocks), dim3(256), 0, st, P, D, level, colour, sweep,
+                           bmap, nblocks);
+    else
+        hipLaunchKernelGGL((k_phase<1024, 8192, 1024>), dim3(nblocks), dim3(1024), 0, st, P, D, level, colour, sweep,
+                           bmap, nblocks);
+}
+
+// ------------------------------------------------------------------- plane waves
+// One workgroup per system runs its H_F chains (App. D "Generating a plane wave"): k from
+// the cube by inverse CDF or from the quasi-continuous shell, Phi and e-hat, displacement
+// A_F cos(k.r + Phi) e-hat on every bead, dU over every bond and WCA pair (neighbour
+// grid), Metropolis test, k permuted and sign-flipped after a rejection.
+__device__ void sample_k(const DevParams& P, const SysDesc& s, const DevPtrs& D, Stream& st, int l[3]) {
+    const int NL = P.n_layers, Dm = 2 * NL + 1;
+    if (st.co() < s.P_cube) {
+        const double* cdf = D.cube_cdf + s.cube_off;
+        double target = st.co() * s.W_cube;
+        int lo = 0, hi = s.n_modes - 1;
+        while (lo < hi) {
+            int mid = (lo + hi) / 2;
+            if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        l[0] = lo / (Dm * Dm) - NL;
+        l[1] = (lo / Dm) % Dm - NL;
+        l[2] = lo % Dm - NL;
+        return;
+    }
+    const double* sh = D.shell_s + s.shell_off;
+    for (int tries = 0;; ++tries) {
+        if (tries >= 100000) {  // never reached with valid tables; keeps the loop bounded
+            l[0] = NL + 1;
+            l[1] = 0;
+            l[2] = 0;
+            return;
+        }
+        double us = st.co() * s.n_shell;
+        int i = (int)floor(us);
+        double fr = us - (double)i;
+        double sv = sh[i] + fr * (sh[i + 1] - sh[i]);
+        double vx, vy, vz;
+        direction(st, vx, vy, vz);
+        if (!(sv > 1e-12)) continue;
+        double kmag = (s.x_s / sv) / s.lmax;
+        double v[3] = {vx, vy, vz};
+        bool ok = true, inside = true;
+        for (int a = 0; a < 3; ++a) {
+            double la = rint(kmag * v[a] * s.invks);
+            if (fabs(la) > 1048576.0) ok = false;
+            l[a] = ok ? (int)la : 0;
+            if (abs(l[a]) > NL) inside = false;
+        }
+        if (ok && !inside) return;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t sweep) {
+    __shared__ double red[16];
+    const int sys = blockIdx.x;
+    const SysDesc& s = D.sys[sys];
+    const int tid = threadIdx.x;
+    const double L = s.L, invL = s.invL;
+    Stream cs;
+    cs.init(P, sys, sweep, TAG_PWCOUNT, 0, 0, 0, 0);
+    double mu = (double)s.N * s.PF;
+    int64_t HF = (int64_t)floor(mu);
+    if (cs.co() < mu - (double)HF) HF += 1;
+    double Dg = __longlong_as_double((long long)D.drift[sys]);
+    unsigned long long c_att = 0, c_acc = 0, c_k0 = 0, c_caps = 0, c_beads = 0;
+    const int64_t NN = (int64_t)(D.sys[P.nsys - 1].b1);
+    double* NX = D.pw_new;
+    double* NY = D.pw_new + NN;
+    double* NZ = D.pw_new + 2 * NN;
+    for (int64_t h = 0; h < HF; ++h) {
+        Stream st;
+        st.init(P, sys, sweep, TAG_PW, 0, h, 0, 0);
+        int l[3];
+        sample_k(P, s, D, st, l);
+        for (int r = 0;;) {
+            const double Phi = 2.0 * kPi * st.co();
+            const double psi = 2.0 * kPi * st.co();
+            const double u_acc = st.oc();
+            const double thr = -P.kT * log(u_acc);
+            if (l[0] == 0 && l[1] == 0 && l[2] == 0) {
+                ++c_k0;
+                ++c_acc;
+                if (tid == 0)
+                    trace_push(D, 2, sys, sweep, -1, h, 0, r, 0, 1, (int)((512u << 20) | (512u << 10) | 512u), 0.0,
+                               thr);
+                break;
+            }
+            double k[3] = {s.ks * (double)l[0], s.ks * (double)l[1], s.ks * (double)l[2]};
+            double kmag = sqrt((k[0] * k[0] + k[1] * k[1]) + k[2] * k[2]);
+            double kh[3] = {k[0] / kmag, k[1] / kmag, k[2] / kmag};
+            int ax = 0;
+            for (int q = 1; q < 3; ++q)
+                if (fabs(kh[q]) < fabs(kh[ax])) ax = q;
+            double ref[3] = {0.0, 0.0, 0.0};
+            ref[ax] = 1.0;
+            double e1[3] = {kh[1] * ref[2] - kh[2] * ref[1], kh[2] * ref[0] - kh[0] * ref[2],
+                            kh[0] * ref[1] - kh[1] * ref[0]};
+            double n1 = sqrt((e1[0] * e1[0] + e1[1] * e1[1]) + e1[2] * e1[2]);
+            for (int q = 0; q < 3; ++q) e1[q] = e1[q] / n1;
+            double e2[3] = {kh[1] * e1[2] - kh[2] * e1[1], kh[2] * e1[0] - kh[0] * e1[2],
+                            kh[0] * e1[1] - kh[1] * e1[0]};
+            double cp = cos(psi), sp = sin(psi);
+            double e[3] = {cp * e1[0] + sp * e2[0], cp * e1[1] + sp * e2[1], cp * e1[2] + sp * e2[2]};
+            const double AF = 2.0 * P.A0 / (kmag * sqrt(5.0 * (double)s.N));
+            for (int64_t j = s.b0 + tid; j < s.b1; j += 1024) {
+                double ph = ((k[0] * D.x[j] + k[1] * D.y[j]) + k[2] * D.z[j]) + Phi;
+                double f = AF * cos(ph);
+                NX[j] = D.x[j] + f * e[0];
+                NY[j] = D.y[j] + f * e[1];
+                NZ[j] = D.z[j] + f * e[2];
+            }
+            __syncthreads();
+            double acc = 0.0;
+            const double R = P.rc + 2.0 * AF + Dg + 1e-9 * L;
+            for (int64_t j = s.b0 + tid; j < s.b1; j += 1024) {
+                double jx = D.x[j], jy = D.y[j], jz = D.z[j];
+                if (P.bond_type != WMC_BOND_NONE && j + 1 < s.b1 && D.bond_next[j]) {
+                    double r2o = pair_r2(P, invL, L, jx, jy, jz, D.x[j + 1], D.y[j + 1], D.z[j + 1]);
+                    double r2n = pair_r2(P, invL, L, NX[j], NY[j], NZ[j], NX[j + 1], NY[j + 1], NZ[j + 1]);
+                    acc += u_bond(P, r2n) - u_bond(P, r2o);
+                }
+                if (P.wca) {
+                    double cx = wrap01(jx, L, invL), cy = wrap01(jy, L, invL), cz = wrap01(jz, L, invL);
+                    int f0[3], cn[3];
+                    fine_range(cx - R, cx + R, s.invg, s.nf, f0[0], cn[0]);
+                    fine_range(cy - R, cy + R, s.invg, s.nf, f0[1], cn[1]);
+                    fine_range(cz - R, cz + R, s.invg, s.nf, f0[2], cn[2]);
+                    for (int qz = 0; qz < cn[2]; ++qz)
+                        for (int qy = 0; qy < cn[1]; ++qy)
+                            for (int qx = 0; qx < cn[0]; ++qx) {
+                                int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
+                                int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
+                                for (int q = D.fstart[fc]; q < D.fstart[fc + 1]; ++q) {
+                                    int32_t m = D.fidx[q];
+                                    if (m <= j) continue;
+                                    double r2o = pair_r2(P, invL, L, jx, jy, jz, D.x[m], D.y[m], D.z[m]);
+                                    double r2n = pair_r2(P, invL, L, NX[j], NY[j], NZ[j], NX[m], NY[m], NZ[m]);
+                                    if (r2o < P.rc2 || r2n < P.rc2) acc += u_pair(P, r2n) - u_pair(P, r2o);
+                                }
+                            }
+                }
+            }
+            const double dU = block_sum<1024>(acc, red);
+            const bool accept = dU <= thr;
+            ++c_att;
+            c_beads += s.N;
+            if (tid == 0) {
+                int extra = (int)((((uint32_t)(l[0] + 512) & 0x3FFu) << 20) | (((uint32_t)(l[1] + 512) & 0x3FFu) << 10) |
+                                  ((uint32_t)(l[2] + 512) & 0x3FFu));
+                trace_push(D, 2, sys, sweep, -1, h, 0, r, s.N, accept ? 1 : 0, extra, dU, thr);
+            }
+            if (accept) {
+                for (int64_t j = s.b0 + tid; j < s.b1; j += 1024) {
+                    D.x[j] = NX[j];
+                    D.y[j] = NY[j];
+                    D.z[j] = NZ[j];
+                }
+                Dg += AF;
+                ++c_acc;
+                __syncthreads();
+                break;
+            }
+            __syncthreads();
+            if (++r >= P.retry_cap) {
+                ++c_caps;
+                break;
+            }
+            st.init(P, sys, sweep, TAG_PW, 0, h, r, 0);
+            int pi = (int)st.index(6);
+            static const int PERM[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+            int nl[3] = {l[PERM[pi][0]], l[PERM[pi][1]], l[PERM[pi][2]]};
+            for (int q = 0; q < 3; ++q) l[q] = st.co() < 0.5 ? -nl[q] : nl[q];
+        }
+    }
+    if (tid == 0) {
+        unsigned long long* C = D.cnt + CNT_PW;
+        atomicAdd(&C[0], (unsigned long long)HF);
+        atomicAdd(&C[1], c_att);
+        atomicAdd(&C[2], c_acc);
+        atomicAdd(&C[3], c_k0);
+        atomicAdd(&C[4], c_caps);
+        atomicAdd(&C[5], c_beads);
+        if (c_acc) {
+            atomicAdd(&D.cnt[CNT_ACCEPTED], c_acc);
+            atomicAdd(&D.sys_acc[sys], c_acc);
+        }
+        atomic_max_double(&D.drift[sys], Dg);
+    }
+}
+
+void launch_pw(const DevParams& P, const DevPtrs& D, int64_t sweep, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL(k_pw, dim3(nsys), dim3(1024), 0, st, P, D, sweep);
+}
+
+// ------------------------------------------------------------------- observables
+// Eq. "Radius of gyration": (1/(2 Nb^2)) sum_ij r_ij^2 = (1/Nb) sum_i |r_i - r_cm|^2
+__global__ void k_rg2(DevPtrs D, const int64_t* chain_off, int64_t n_chains, double* out) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chains) return;
+    int64_t a = chain_off[c], b = chain_off[c + 1];
+    double nb = (double)(b - a), cx = 0, cy = 0, cz = 0;
+    for (int64_t i = a; i < b; ++i) {
+        cx += D.x[i];
+        cy += D.y[i];
+        cz += D.z[i];
+    }
+    cx /= nb;
+    cy /= nb;
+    cz /= nb;
+    double acc = 0.0;
+    for (int64_t i = a; i < b; ++i) {
+        double dx = D.x[i] - cx, dy = D.y[i] - cy, dz = D.z[i] - cz;
+        acc += (dx * dx + dy * dy) + dz * dz;
+    }
+    out[c] = acc / nb;
+}
+
+void launch_rg2(const DevPtrs& D, const int64_t* chain_off, int64_t n_chains, double* out, hipStream_t st) {
+    if (n_chains <= 0) return;
+    hipLaunchKernelGGL(k_rg2, dim3((unsigned)((n_chains + 255) / 256)), dim3(256), 0, st, D, chain_off, n_chains,
+                       out);
+}
+
+// ------------------------------------------------------------------- debug kernels
+__global__ void k_cell_ids(DevParams P, DevPtrs D, int sys, int level, int64_t sweep, int32_t* out) {
+    const SysDesc& s = D.sys[sys];
+    const LevelDesc& lv = D.lev[s.lvl_off + level];
+    Grid g;
+    make_grid(P, D, s, lv, sys, level, sweep, g);
+    int64_t i = s.b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.b1) return;
+    out[i - s.b0] = (int32_t)cell_of_point(g, D.x[i], D.y[i], D.z[i]);
+}
+
+void launch_cell_ids(const DevParams& P, const DevPtrs& D, int sys, int level, int64_t sweep, int64_t n, int32_t* out,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_cell_ids, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, D, sys, level, sweep, out);
+}
+
+__global__ void k_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1, int64_t n,
+                         uint32_t* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c[4] = {c0 + (uint32_t)i, c1, c2, c3};
+    philox10(c, k0, k1);
+    for (int q = 0; q < 4; ++q) out[4 * i + q] = c[q];
+}
+
+void launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ctr[0], ctr[1], ctr[2], ctr[3],
+                       key[0], key[1], n, out);
+}
+
+}  // namespace wmc

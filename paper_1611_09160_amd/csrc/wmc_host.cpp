@@ -1,0 +1,813 @@
+// Host side of libwmc: schedule constants, device arena layout and the C ABI (include/wmc.h).
+//
+// Schedule constants per system (Dyer & Ball, arXiv:1611.09160):
+//   levels   bands [lo, lo*band_ratio) from lambda_min up to lambda_max, probability mass
+//            p = (lo^-3 - hi^-3)/(lambda_min^-3 - lambda_max^-3) (Eq. "PDF for lambda"), expected
+//            chain starts per sweep T = N (1 - P_F) p; periodic cells: the largest even count n
+//            with L/n >= (2 hi + r_int)(1 + 1e-9), else a single cell.
+//   P_F      Eq. "P(Fourier)" with R = (L/lambda_max)^3 M6 N_k / (6 pi^2) (Sec. V.C); N_k normalises
+//            P(k_l) ~ I(|k_l| lambda_max) (Eq. "Prob of k_l") over the discrete cube of App. D plus
+//            the quasi-continuous shell outside it.
+//   dt       Eq. "dt w+F" with plane waves, Eq. "Time step per wavelet" without.
+// I(x) = int_x^inf q^3 phi~(q)^2 dq and J6(x) = int_x^inf q^6 phi~(q)^2 dq are integrated here
+// with 20-point Gauss-Legendre panels of width 1/2 plus asymptotic tails beyond Q = 4096.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "wmc_internal.h"
+
+using namespace wmc;
+
+struct wmc_ctx {
+    wmc_params p;
+    DevParams P;
+    DevPtrs D;
+    int32_t nsys;
+    int64_t N, n_chains;
+    std::vector<SysDesc> sys;
+    std::vector<LevelDesc> lev;
+    std::vector<std::vector<double>> level_out;  // per system: 6 doubles per level
+    std::vector<std::vector<double>> pw_out;     // per system: 6 doubles
+    int max_levels;
+    int phase_variant[WMC_MAX_LEVELS];
+    std::vector<int32_t> bmap_host;
+    int64_t bmap_off[WMC_MAX_LEVELS][8];
+    int32_t bmap_n[WMC_MAX_LEVELS][8];
+    int32_t* bmap_dev;
+    int64_t* chain_off_dev;
+    double* rg2_dev;
+    int64_t sweep;
+    char* arena;
+    size_t arena_bytes;
+    std::string err;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ tapered wavelet
+double phit(double q) {
+    // phi~(q) = 4 pi int_0^1 r^2 phi(r) sin(qr)/(qr) dr with phi = r^2/2 - r^3/3 - 1/6: for
+    // small q by its power series, else the closed form 4 pi q^-6 (5q sin q - (q^2-8) cos q - 8)
+    if (q < 2.5) {
+        double q2 = q * q, s = 0.0, pw = 1.0, fact = 1.0;
+        for (int n = 0; n < 28; ++n) {
+            double a = (double)(2 * n);
+            double moment = 0.5 / (a + 5.0) - 1.0 / (3.0 * (a + 6.0)) - 1.0 / (6.0 * (a + 3.0));
+            s += ((n & 1) ? -1.0 : 1.0) * moment * pw / fact;
+            pw *= q2;
+            fact *= (a + 2.0) * (a + 3.0);
+        }
+        return 4.0 * kPi * s;
+    }
+    double c = cos(q), sn = sin(q), q2 = q * q;
+    return 4.0 * kPi * (5.0 * q * sn - (q2 - 8.0) * c - 8.0) / (q2 * q2 * q2);
+}
+
+struct Quad {
+    static constexpr int NP = 20;
+    static constexpr double W = 0.5, QMAX = 4096.0;
+    double x[NP], w[NP];
+    std::vector<double> tailI, tailJ;  // int_{iW}^{QMAX}
+    Quad() {
+        for (int i = 0; i < NP; ++i) {
+            double z = cos(kPi * (i + 0.75) / (NP + 0.5)), dp = 1.0;
+            for (int it = 0; it < 200; ++it) {
+                double p0 = 1.0, p1 = z;
+                for (int k = 2; k <= NP; ++k) {
+                    double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                    p0 = p1;
+                    p1 = p2;
+                }
+                dp = NP * (p0 - z * p1) / (1.0 - z * z);
+                double step = p1 / dp;
+                z -= step;
+                if (fabs(step) < 1e-17) break;
+            }
+            x[i] = z;
+            w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+        }
+        int n = (int)(QMAX / W);
+        tailI.assign(n + 1, 0.0);
+        tailJ.assign(n + 1, 0.0);
+        for (int i = n - 1; i >= 0; --i) {
+            double a, b;
+            segment(i * W, (i + 1) * W, a, b);
+            tailI[i] = tailI[i + 1] + a;
+            tailJ[i] = tailJ[i + 1] + b;
+        }
+    }
+    void segment(double a, double b, double& vi, double& vj) const {
+        double m = 0.5 * (a + b), hw = 0.5 * (b - a);
+        vi = vj = 0.0;
+        for (int i = 0; i < NP; ++i) {
+            double q = m + hw * x[i], f = phit(q), f2 = f * f, q3 = q * q * q;
+            vi += w[i] * q3 * f2;
+            vj += w[i] * q3 * q3 * f2;
+        }
+        vi *= hw;
+        vj *= hw;
+    }
+    static double asymI(double Q) { return 2.0 * kPi * kPi / (Q * Q * Q * Q); }
+    static double asymJ(double Q) {
+        double p2 = kPi * kPi;
+        return 8.0 * p2 / Q - 4.0 * p2 * sin(2.0 * Q) / (Q * Q) + (24.0 - 36.0 * cos(2.0 * Q)) * p2 / (Q * Q * Q);
+    }
+    void IJ(double xq, double& I, double& J) const {
+        if (xq >= QMAX) {
+            I = asymI(xq);
+            J = asymJ(xq);
+            return;
+        }
+        int i = (int)floor(xq / W);
+        double vi = 0.0, vj = 0.0;
+        if ((i + 1) * W > xq) segment(xq, (i + 1) * W, vi, vj);
+        I = vi + tailI[i + 1] + asymI(QMAX);
+        J = vj + tailJ[i + 1] + asymJ(QMAX);
+    }
+    double I(double xq) const {
+        double a, b;
+        IJ(xq, a, b);
+        return a;
+    }
+    // G(x) = int_x^inf t^2 I(t) dt = (J6(x) - x^3 I(x)) / 3
+    double G(double xq) const {
+        double a, b;
+        IJ(xq, a, b);
+        return (b - xq * xq * xq * a) / 3.0;
+    }
+};
+
+const Quad& quad() {
+    static Quad q;
+    return q;
+}
+
+double M3() { return 2.0 * kPi * kPi / 105.0 * (9.0 - 8.0 * log(2.0)); }
+double M4() { return 8.0 * kPi * kPi * kPi / 105.0; }
+double M6() { return 8.0 * kPi * kPi * kPi / 5.0; }
+
+struct PWTables {
+    std::vector<double> cdf, shell;
+    double W_cube = 0, W_cont = 0, W_corner = 0, x_s = 0;
+};
+
+PWTables build_pw(double L, double lmax, int NL) {
+    const Quad& Q = quad();
+    PWTables t;
+    const int D = 2 * NL + 1;
+    const double ks = 2.0 * kPi / L;
+    std::vector<double> byl2(3 * NL * NL + 1);
+    for (size_t v = 0; v < byl2.size(); ++v) byl2[v] = Q.I(ks * sqrt((double)v) * lmax);
+    t.cdf.resize((size_t)D * D * D);
+    double run = 0.0, corner = 0.0, edge = (NL + 0.5) * (NL + 0.5);
+    size_t i = 0;
+    for (int a = -NL; a <= NL; ++a)
+        for (int b = -NL; b <= NL; ++b)
+            for (int c = -NL; c <= NL; ++c, ++i) {
+                int l2 = a * a + b * b + c * c;
+                run += byl2[l2];
+                t.cdf[i] = run;
+                if ((double)l2 > edge) corner += byl2[l2];
+            }
+    t.W_cube = run;
+    t.W_corner = corner;
+    t.x_s = ks * (NL + 0.5) * lmax;
+    double Lk = L / (2.0 * kPi);
+    t.W_cont = Lk * Lk * Lk * 4.0 * kPi / (lmax * lmax * lmax) * Q.G(t.x_s);
+    // shell: s = x_s / x at u = i/M where u = 1 - G(x)/G(x_s) (bisection on s)
+    const int M = 4096;
+    t.shell.assign(M + 1, 0.0);
+    t.shell[0] = 1.0;
+    double G0 = Q.G(t.x_s);
+    for (int k = 1; k < M; ++k) {
+        double want = (1.0 - (double)k / M) * G0, lo = 0.0, hi = t.shell[k - 1];
+        for (int it = 0; it < 60; ++it) {
+            double mid = 0.5 * (lo + hi);
+            if (mid <= 0.0 || Q.G(t.x_s / mid) < want) lo = mid; else hi = mid;
+        }
+        t.shell[k] = 0.5 * (lo + hi);
+    }
+    return t;
+}
+
+#define HIPCHK(c, expr)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            (c)->err = std::string("HIP error: ") + hipGetErrorString(e_) + " at " #expr; \
+            return WMC_EHIP;                                                             \
+        }                                                                                \
+    } while (0)
+
+struct Layout {
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        size_t off = (total + 255) & ~(size_t)255;
+        total = off + bytes;
+        return off;
+    }
+};
+
+// everything the arena holds, computed identically by wmc_arena_bytes and wmc_init
+struct Plan {
+    int64_t N = 0, total_fine = 0, slots = 0, slot_len = 0, pool_cube = 0, pool_shell = 0, n_chains = 0, bmap = 0;
+    int nsys = 0, total_levels = 0;
+    size_t off_x, off_xb, off_bond, off_sysid, off_tag, off_fcount, off_fstart, off_fidx, off_fcell, off_drift,
+        off_cnt, off_sysacc, off_trace, off_tracen, off_cube, off_shell, off_slotS, off_slotM, off_slotMX, off_pw,
+        off_igrid, off_sys, off_lev, off_bmap, off_choff, off_rg2;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+static int validate(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int64_t* so, const double* sL,
+                    const double* sl, int64_t n_chains, const int64_t* co) {
+    auto fail = [&](const char* m) {
+        if (c) c->err = m;
+        return WMC_EINVAL;
+    };
+    if (!p || !so || !co) return fail("null argument");
+    if (nsys < 1 || nsys > 4096) return fail("n_systems must be in 1..4096");
+    if (!(p->lambda_min > 0.0)) return fail("lambda_min must be positive");
+    if (!(p->band_ratio > 1.0 && p->band_ratio <= 2.0)) return fail("band_ratio must lie in (1, 2]");
+    if (!(p->A0 > 0.0) || !(p->kT > 0.0)) return fail("A0 and kT must be positive");
+    if (p->bond_type < 0 || p->bond_type > 2) return fail("bad bond_type");
+    if (p->bond_type == WMC_BOND_FENE && !(p->R0 > 0.0)) return fail("FENE needs R0 > 0");
+    if (p->bond_type == WMC_BOND_HARMONIC && !(p->r_int_harmonic > 0.0)) return fail("harmonic bonds need r_int_harmonic > 0");
+    if (p->wca && !(p->sigma > 0.0)) return fail("WCA needs sigma > 0");
+    if (p->retry_cap < 1 || p->retry_cap > 255) return fail("retry_cap must be in 1..255");
+    if (p->plane_waves && (p->n_layers < 1 || p->n_layers > 60)) return fail("n_layers must be in 1..60");
+    if (!p->periodic && nsys != 1) return fail("an infinite system runs as a single system");
+    if (so[0] != 0) return fail("sys_bead_offset[0] must be 0");
+    for (int s = 0; s < nsys; ++s) {
+        if (so[s + 1] <= so[s]) return fail("every system needs at least one bead");
+        double L = sL ? sL[s] : p->box_L, lm = sl ? sl[s] : p->lambda_max;
+        if (!(lm > p->lambda_min)) return fail("lambda_max must exceed lambda_min");
+        if (p->periodic && !(L > 0.0)) return fail("periodic box needs box_L > 0");
+        if (p->periodic && lm > 0.5 * L) return fail("lambda_max must not exceed L/2");
+    }
+    if (so[nsys] > 0x7FFFFFFF) return fail("too many beads");
+    if (!p->periodic && so[nsys] > 8192) return fail("an infinite system is limited to 8192 beads");
+    if (co[0] != 0 || co[n_chains] != so[nsys]) return fail("chain_offset must cover all beads");
+    int s = 0;
+    for (int64_t ch = 0; ch < n_chains; ++ch) {
+        if (co[ch + 1] <= co[ch]) return fail("empty chain");
+        while (co[ch] >= so[s + 1]) ++s;
+        if (co[ch + 1] > so[s + 1]) return fail("a chain crosses a system boundary");
+    }
+    return 0;
+}
+
+static double r_int_of(const wmc_params* p) {
+    double rc = p->wca ? pow(2.0, 1.0 / 6.0) * p->sigma : 0.0;
+    if (p->bond_type == WMC_BOND_FENE) return std::max(p->R0, rc);
+    if (p->bond_type == WMC_BOND_HARMONIC) return std::max(p->r_int_harmonic, rc);
+    return rc;
+}
+
+// per-system schedule (levels, neighbour grid, pw tables) and the arena plan
+static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int64_t* so, const double* sL,
+                        const double* sl, int64_t n_chains, int64_t trace_cap, Plan& pl,
+                        std::vector<SysDesc>* sys_out, std::vector<LevelDesc>* lev_out,
+                        std::vector<PWTables>* pw_pool, std::vector<int>* pw_index) {
+    pl.nsys = nsys;
+    pl.N = so[nsys];
+    pl.n_chains = n_chains;
+    const double r_int = r_int_of(p);
+    const double rc = p->wca ? pow(2.0, 1.0 / 6.0) * p->sigma : 0.0;
+    std::vector<SysDesc> sys(nsys);
+    std::vector<LevelDesc> lev;
+    std::map<double, int> pw_by_ratio;
+    int64_t fine = 0, slots = 0, cube_pool = 0, shell_pool = 0, slot_len = 0;
+    const double lam_a = 2.0 / kPi * M4() / M3();
+    for (int s = 0; s < nsys; ++s) {
+        SysDesc& d = sys[s];
+        memset(&d, 0, sizeof(d));
+        d.b0 = so[s];
+        d.b1 = so[s + 1];
+        d.N = (int32_t)(d.b1 - d.b0);
+        d.L = p->periodic ? (sL ? sL[s] : p->box_L) : 0.0;
+        d.invL = p->periodic ? 1.0 / d.L : 0.0;
+        d.lmax = sl ? sl[s] : p->lambda_max;
+        // plane-wave tables, shared by systems with equal L / lambda_max
+        double PF = 0.0;
+        if (p->periodic && p->plane_waves) {
+            double ratio = d.L / d.lmax;
+            int idx;
+            auto it = pw_by_ratio.find(ratio);
+            if (it == pw_by_ratio.end()) {
+                idx = pw_pool ? (int)pw_pool->size() : (int)pw_by_ratio.size();
+                if (pw_pool) pw_pool->push_back(build_pw(d.L, d.lmax, p->n_layers));
+                pw_by_ratio[ratio] = idx;
+            } else {
+                idx = it->second;
+            }
+            int64_t nm = (int64_t)(2 * p->n_layers + 1) * (2 * p->n_layers + 1) * (2 * p->n_layers + 1);
+            d.n_modes = (int32_t)nm;
+            d.n_shell = 4096;
+            d.cube_off = (int64_t)idx * nm;
+            d.shell_off = (int64_t)idx * 4097;
+            cube_pool = std::max(cube_pool, (int64_t)(idx + 1) * nm);
+            shell_pool = std::max(shell_pool, (int64_t)(idx + 1) * 4097);
+            if (pw_pool) {
+                const PWTables& t = (*pw_pool)[idx];
+                double Wtot = t.W_cube + t.W_cont - t.W_corner;
+                double Nk = 1.0 / Wtot;
+                double R = (d.L / d.lmax) * (d.L / d.lmax) * (d.L / d.lmax) * M6() * Nk / (6.0 * kPi * kPi);
+                double rat = d.lmax / p->lambda_min;
+                PF = 1.0 / (1.0 + R * (rat * rat * rat - 1.0));
+                d.P_cube = t.W_cube / Wtot;
+                d.W_cube = t.W_cube;
+                d.x_s = t.x_s;
+                if (pw_index) pw_index->push_back(idx);
+                if (c) c->pw_out.push_back({PF, R, Nk, d.P_cube, M3() * Nk, 0.0});
+            }
+            d.ks = 2.0 * kPi / d.L;
+            d.invks = d.L / (2.0 * kPi);
+        } else if (c) {
+            c->pw_out.push_back({0.0, 0.0, 0.0, 0.0, 0.0, 0.0});
+        }
+        d.PF = PF;
+        double dt = 6.0 * p->A0 * p->A0 * M4() * lam_a * lam_a / (8.0 * kPi * kPi * kPi * (double)d.N);
+        if (!(p->periodic && p->plane_waves)) {
+            double q = p->lambda_min / d.lmax;
+            dt *= (1.0 - q) / (1.0 - q * q * q);
+        }
+        d.dt = dt;
+        if (c) c->pw_out.back()[5] = dt;
+        // neighbour grid: cells of side >= max(r_cut, 1) + 0.4
+        if (p->periodic) {
+            double gmin = std::max(rc, 1.0) + 0.4;
+            int nf = std::max(1, (int)floor(d.L / gmin));
+            nf = std::min(nf, 512);
+            d.nf = nf;
+            d.g = d.L / nf;
+            d.invg = 1.0 / d.g;
+            d.fine_off = fine;
+            fine += (int64_t)nf * nf * nf;
+        }
+        // levels
+        d.lvl_off = (int32_t)lev.size();
+        double norm = 1.0 / (p->lambda_min * p->lambda_min * p->lambda_min) - 1.0 / (d.lmax * d.lmax * d.lmax);
+        double lo = p->lambda_min;
+        int nl = 0;
+        std::vector<double> lout;
+        while (nl < WMC_MAX_LEVELS) {
+            double hi = lo * p->band_ratio;
+            bool last = false;
+            if (hi > d.lmax || d.lmax - hi < 1e-9 * d.lmax) {
+                hi = d.lmax;
+                last = true;
+            }
+            LevelDesc L;
+            memset(&L, 0, sizeof(L));
+            L.lo = lo;
+            L.hi = hi;
+            L.p = (1.0 / (lo * lo * lo) - 1.0 / (hi * hi * hi)) / norm;
+            L.T = (double)d.N * (1.0 - PF) * L.p;
+            L.r_int = r_int;
+            int64_t cells_per_colour;
+            if (p->periodic) {
+                int n = (int)floor(d.L / ((2.0 * hi + r_int) * (1.0 + 1e-9)));
+                if (n % 2) n -= 1;
+                if (n < 2) n = 1;
+                L.n = n;
+                L.h = d.L / n;
+                cells_per_colour = n >= 2 ? (int64_t)(n / 2) * (n / 2) * (n / 2) : 1;
+                if ((int64_t)n * n * n > 0xFFFFFF) {
+                    if (c) c->err = "too many cells in one level";
+                    return WMC_EINVAL;
+                }
+            } else {
+                L.n = 0;
+                L.h = (2.0 * hi + r_int) * (1.0 + 1e-9);
+                cells_per_colour = 0;
+            }
+            L.invh = 1.0 / L.h;
+            L.half = 0.5 * L.h;
+            // kernel variant from the expected reach-list size
+            double region = p->periodic ? pow(L.h + 2.0 * hi, 3.0) : 0.0;
+            double expect = p->periodic ? std::min((double)d.N, (double)d.N / (d.L * d.L * d.L) * region) : (double)d.N;
+            if (p->periodic && L.n == 1) {
+                L.identity = 1;
+                L.use_global = 1;
+                L.variant = V1024;
+            } else if (p->periodic && (L.n == 2 || 2.0 * expect > 8192.0)) {
+                L.use_global = 1;
+                L.variant = V1024;
+            } else if (!p->periodic) {
+                L.variant = d.N <= 512 ? V64 : (d.N <= 4096 ? V256 : V1024);
+            } else if (std::min((double)d.N, 4.0 * expect) <= 512.0) {
+                L.variant = V64;
+            } else if (std::min((double)d.N, 2.5 * expect) <= 4096.0) {
+                L.variant = V256;
+            } else {
+                L.variant = V1024;
+            }
+            if (L.use_global) {
+                L.slot_base = slots;
+                slots += cells_per_colour;
+                slot_len = std::max(slot_len, (int64_t)d.N);
+            }
+            lev.push_back(L);
+            lout.insert(lout.end(), {L.lo, L.hi, L.p, L.T, L.h, (double)L.n});
+            ++nl;
+            if (last) break;
+            lo = hi;
+        }
+        if (nl == WMC_MAX_LEVELS && lev.back().hi < d.lmax) {
+            if (c) c->err = "too many levels: raise band_ratio";
+            return WMC_EINVAL;
+        }
+        d.n_levels = nl;
+        if (c) c->level_out.push_back(lout);
+    }
+    pl.total_fine = fine;
+    pl.slots = slots;
+    pl.slot_len = slot_len;
+    pl.pool_cube = cube_pool;
+    pl.pool_shell = shell_pool;
+    pl.total_levels = (int)lev.size();
+    // block maps: one entry (system, local cell) per workgroup of each (level, colour) launch
+    int64_t bm = 0;
+    for (int l = 0; l < WMC_MAX_LEVELS; ++l)
+        for (int col = 0; col < 8; ++col)
+            for (int s = 0; s < nsys; ++s)
+                if (p->periodic && l < sys[s].n_levels) {
+                    const LevelDesc& L = lev[sys[s].lvl_off + l];
+                    bm += L.n >= 2 ? (int64_t)(L.n / 2) * (L.n / 2) * (L.n / 2) : (col == 0 ? 1 : 0);
+                }
+    pl.bmap = bm;
+    // arena layout
+    Layout lay;
+    const int64_t N = pl.N;
+    pl.off_x = lay.add(3 * N * 8);
+    pl.off_xb = lay.add(3 * N * 8);
+    pl.off_bond = lay.add(N);
+    pl.off_sysid = lay.add(N * 4);
+    pl.off_tag = lay.add(N * 4);
+    pl.off_fcount = lay.add((fine + 1) * 4);
+    pl.off_fstart = lay.add((fine + 1) * 4);
+    pl.off_fidx = lay.add(N * 4);
+    pl.off_fcell = lay.add(N * 4);
+    pl.off_drift = lay.add(nsys * 8);
+    pl.off_cnt = lay.add(CNT_TOTAL * 8);
+    pl.off_sysacc = lay.add(nsys * 8);
+    pl.off_trace = lay.add(std::max<int64_t>(trace_cap, 0) * sizeof(wmc_trace_rec));
+    pl.off_tracen = lay.add(8);
+    pl.off_cube = lay.add(cube_pool * 8);
+    pl.off_shell = lay.add(shell_pool * 8);
+    pl.off_slotS = lay.add(slots * slot_len * 4);
+    pl.off_slotM = lay.add(slots * slot_len * 4);
+    pl.off_slotMX = lay.add(slots * slot_len * 3 * 8);
+    pl.off_pw = lay.add((p->periodic && p->plane_waves) ? 3 * N * 8 : 8);
+    pl.off_igrid = lay.add(8 * 8);
+    pl.off_sys = lay.add(nsys * sizeof(SysDesc));
+    pl.off_lev = lay.add(lev.size() * sizeof(LevelDesc));
+    pl.off_bmap = lay.add(std::max<int64_t>(bm, 1) * 2 * 4);
+    pl.off_choff = lay.add((n_chains + 1) * 8);
+    pl.off_rg2 = lay.add(std::max<int64_t>(n_chains, 1) * 8);
+    pl.bytes = lay.total + 256;
+    if (sys_out) *sys_out = sys;
+    if (lev_out) *lev_out = lev;
+    return 0;
+}
+
+extern "C" int wmc_arena_bytes(const wmc_params* p, int32_t n_systems, const int64_t* so, const double* sL,
+                               const double* sl, int64_t n_chains, const int64_t* co, int64_t trace_capacity,
+                               size_t* out_bytes) {
+    int rc = validate(nullptr, p, n_systems, so, sL, sl, n_chains, co);
+    if (rc) return rc;
+    Plan pl;
+    rc = plan_systems(nullptr, p, n_systems, so, sL, sl, n_chains, trace_capacity, pl, nullptr, nullptr, nullptr,
+                      nullptr);
+    if (rc) return rc;
+    *out_bytes = pl.bytes;
+    return 0;
+}
+
+extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const int64_t* so, const double* sL,
+                        const double* sl, int64_t n_chains, const int64_t* co, const double* pos, int64_t trace_cap,
+                        void* arena, size_t arena_bytes, void* stream) {
+    if (!out) return WMC_EINVAL;
+    wmc_ctx* c = new wmc_ctx();
+    *out = c;
+    int rc = validate(c, p, nsys, so, sL, sl, n_chains, co);
+    if (rc) return rc;
+    if (!pos) {
+        c->err = "null positions";
+        return WMC_EINVAL;
+    }
+    c->p = *p;
+    c->nsys = nsys;
+    c->N = so[nsys];
+    c->n_chains = n_chains;
+    c->sweep = 0;
+    Plan pl;
+    std::vector<PWTables> pool;
+    std::vector<int> pidx;
+    rc = plan_systems(c, p, nsys, so, sL, sl, n_chains, trace_cap, pl, &c->sys, &c->lev, &pool, &pidx);
+    if (rc) return rc;
+    if (!arena || arena_bytes < pl.bytes) {
+        c->err = "device arena missing or smaller than wmc_arena_bytes";
+        return WMC_EARENA;
+    }
+    char* base = (char*)(((uintptr_t)arena + 255) & ~(uintptr_t)255);
+    c->arena = base;
+    c->arena_bytes = arena_bytes;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = c->N;
+    // host-side checks of the initial state: bonds finite
+    std::vector<uint8_t> bond(N, 0);
+    for (int64_t ch = 0; ch < n_chains; ++ch)
+        for (int64_t i = co[ch]; i + 1 < co[ch + 1]; ++i) bond[i] = 1;
+    for (int s = 0; s < nsys; ++s)
+        for (int64_t i = so[s]; i + 1 < so[s + 1]; ++i) {
+            if (!bond[i] || p->bond_type != WMC_BOND_FENE) continue;
+            double d[3];
+            for (int a = 0; a < 3; ++a) {
+                d[a] = pos[3 * (i + 1) + a] - pos[3 * i + a];
+                if (p->periodic) d[a] -= c->sys[s].L * rint(d[a] * c->sys[s].invL);
+            }
+            if ((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2] >= p->R0 * p->R0) {
+                c->err = "initial FENE bond overstretched";
+                return WMC_ESTATE;
+            }
+        }
+    // device parameters
+    DevParams& P = c->P;
+    memset(&P, 0, sizeof(P));
+    P.periodic = p->periodic;
+    P.plane_waves = p->periodic ? p->plane_waves : 0;
+    P.wavelets = p->wavelets;
+    P.precision = p->precision;
+    P.bond_type = p->bond_type;
+    P.wca = p->wca;
+    P.retry_cap = p->retry_cap;
+    P.n_layers = p->n_layers;
+    P.A0 = p->A0;
+    P.kT = p->kT;
+    P.k_bond = p->k_bond;
+    P.R0 = p->R0;
+    P.R02 = p->R0 * p->R0;
+    P.sigma2 = p->sigma * p->sigma;
+    P.eps = p->eps;
+    P.rc2 = pow(2.0, 1.0 / 3.0) * p->sigma * p->sigma;
+    P.rc = p->wca ? pow(2.0, 1.0 / 6.0) * p->sigma : 0.0;
+    P.r_int = r_int_of(p);
+    P.seed_lo = (uint32_t)p->seed;
+    P.seed_hi = (uint32_t)(p->seed >> 32);
+    P.nsys = nsys;
+    // pointers
+    DevPtrs& D = c->D;
+    memset(&D, 0, sizeof(D));
+    D.x = (double*)(base + pl.off_x);
+    D.y = D.x + N;
+    D.z = D.x + 2 * N;
+    D.xb = (double*)(base + pl.off_xb);
+    D.yb = D.xb + N;
+    D.zb = D.xb + 2 * N;
+    D.bond_next = (uint8_t*)(base + pl.off_bond);
+    D.sys_id = (int32_t*)(base + pl.off_sysid);
+    D.tag = (int32_t*)(base + pl.off_tag);
+    D.fcount = (int32_t*)(base + pl.off_fcount);
+    D.fstart = (int32_t*)(base + pl.off_fstart);
+    D.fidx = (int32_t*)(base + pl.off_fidx);
+    D.fcell = (int32_t*)(base + pl.off_fcell);
+    D.drift = (unsigned long long*)(base + pl.off_drift);
+    D.cnt = (unsigned long long*)(base + pl.off_cnt);
+    D.sys_acc = (unsigned long long*)(base + pl.off_sysacc);
+    D.trace = trace_cap > 0 ? (wmc_trace_rec*)(base + pl.off_trace) : nullptr;
+    D.trace_n = (unsigned long long*)(base + pl.off_tracen);
+    D.trace_cap = trace_cap;
+    D.cube_cdf = (const double*)(base + pl.off_cube);
+    D.shell_s = (const double*)(base + pl.off_shell);
+    D.slot_S = (int32_t*)(base + pl.off_slotS);
+    D.slot_M = (int32_t*)(base + pl.off_slotM);
+    D.slot_MX = (double*)(base + pl.off_slotMX);
+    D.slot_len = pl.slot_len;
+    D.pw_new = (double*)(base + pl.off_pw);
+    D.igrid = (double*)(base + pl.off_igrid);
+    D.sys = (const SysDesc*)(base + pl.off_sys);
+    D.lev = (const LevelDesc*)(base + pl.off_lev);
+    D.total_fine = pl.total_fine;
+    c->bmap_dev = (int32_t*)(base + pl.off_bmap);
+    c->chain_off_dev = (int64_t*)(base + pl.off_choff);
+    c->rg2_dev = (double*)(base + pl.off_rg2);
+    // host staging
+    std::vector<double> soa(3 * N);
+    for (int64_t i = 0; i < N; ++i)
+        for (int a = 0; a < 3; ++a) soa[a * N + i] = pos[3 * i + a];
+    std::vector<int32_t> sysid(N), tag(N, -1);
+    for (int s = 0; s < nsys; ++s)
+        for (int64_t i = so[s]; i < so[s + 1]; ++i) sysid[i] = s;
+    std::vector<double> cube(pl.pool_cube), shell(pl.pool_shell);
+    for (size_t k = 0; k < pool.size(); ++k) {
+        std::copy(pool[k].cdf.begin(), pool[k].cdf.end(), cube.begin() + k * pool[k].cdf.size());
+        std::copy(pool[k].shell.begin(), pool[k].shell.end(), shell.begin() + k * 4097);
+    }
+    // block maps
+    c->max_levels = 0;
+    for (auto& s : c->sys) c->max_levels = std::max(c->max_levels, (int)s.n_levels);
+    c->bmap_host.clear();
+    for (int l = 0; l < WMC_MAX_LEVELS; ++l) {
+        c->phase_variant[l] = V64;
+        for (int col = 0; col < 8; ++col) {
+            c->bmap_off[l][col] = (int64_t)c->bmap_host.size() / 2;
+            int32_t cnt = 0;
+            for (int s = 0; s < nsys && p->periodic; ++s) {
+                if (l >= c->sys[s].n_levels) continue;
+                const LevelDesc& L = c->lev[c->sys[s].lvl_off + l];
+                c->phase_variant[l] = std::max(c->phase_variant[l], L.variant);
+                int64_t ncol = L.n >= 2 ? (int64_t)(L.n / 2) * (L.n / 2) * (L.n / 2) : (col == 0 ? 1 : 0);
+                for (int64_t k = 0; k < ncol; ++k) {
+                    c->bmap_host.push_back(s);
+                    c->bmap_host.push_back((int32_t)k);
+                    ++cnt;
+                }
+            }
+            c->bmap_n[l][col] = cnt;
+        }
+        if (!p->periodic && l < c->max_levels) c->phase_variant[l] = c->lev[l].variant;
+    }
+    HIPCHK(c, hipMemsetAsync(base, 0, pl.bytes - 256, st));
+    HIPCHK(c, hipMemcpyAsync(D.x, soa.data(), 3 * N * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(D.bond_next, bond.data(), N, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(D.sys_id, sysid.data(), N * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(D.tag, tag.data(), N * 4, hipMemcpyHostToDevice, st));
+    if (!cube.empty()) HIPCHK(c, hipMemcpyAsync((void*)D.cube_cdf, cube.data(), cube.size() * 8, hipMemcpyHostToDevice, st));
+    if (!shell.empty())
+        HIPCHK(c, hipMemcpyAsync((void*)D.shell_s, shell.data(), shell.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync((void*)D.sys, c->sys.data(), nsys * sizeof(SysDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync((void*)D.lev, c->lev.data(), c->lev.size() * sizeof(LevelDesc), hipMemcpyHostToDevice, st));
+    if (!c->bmap_host.empty())
+        HIPCHK(c, hipMemcpyAsync(c->bmap_dev, c->bmap_host.data(), c->bmap_host.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->chain_off_dev, co, (n_chains + 1) * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    return 0;
+}
+
+extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
+    if (!c) return WMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    for (int64_t k = 0; k < n_sweeps; ++k) {
+        const int64_t sw = c->sweep;
+        for (int l = 0; c->p.wavelets && l < c->max_levels; ++l) {
+            if (c->P.periodic) {
+                launch_fine_build(c->P, c->D, c->N, st);
+                for (int col = 0; col < 8; ++col)
+                    launch_phase(c->phase_variant[l], c->P, c->D, l, col, sw, c->bmap_dev + 2 * c->bmap_off[l][col],
+                                 c->bmap_n[l][col], st);
+            } else {
+                launch_bbox(c->P, c->D, l, sw, st);
+                for (int col = 0; col < 8; ++col)
+                    launch_phase(c->phase_variant[l], c->P, c->D, l, col, sw, nullptr, 64, st);
+            }
+        }
+        if (c->P.periodic && c->P.plane_waves) {
+            launch_fine_build(c->P, c->D, c->N, st);
+            launch_pw(c->P, c->D, sw, c->nsys, st);
+        }
+        c->sweep++;
+    }
+    HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
+extern "C" int wmc_positions(wmc_ctx* c, double* out, int32_t to_device, void* stream) {
+    if (!c || !out) return WMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = c->N;
+    if (to_device) {
+        // interleave SoA -> [N][3] with strided copies
+        for (int a = 0; a < 3; ++a)
+            HIPCHK(c, hipMemcpy2DAsync(out + a, 3 * sizeof(double), c->D.x + a * N, sizeof(double), sizeof(double), N,
+                                       hipMemcpyDeviceToDevice, st));
+        return 0;
+    }
+    std::vector<double> soa(3 * N);
+    HIPCHK(c, hipMemcpyAsync(soa.data(), c->D.x, 3 * N * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (int64_t i = 0; i < N; ++i)
+        for (int a = 0; a < 3; ++a) out[3 * i + a] = soa[a * N + i];
+    return 0;
+}
+
+extern "C" int wmc_set_state(wmc_ctx* c, const double* pos, int64_t sweep, void* stream) {
+    if (!c || !pos) return WMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = c->N;
+    std::vector<double> soa(3 * N);
+    for (int64_t i = 0; i < N; ++i)
+        for (int a = 0; a < 3; ++a) soa[a * N + i] = pos[3 * i + a];
+    HIPCHK(c, hipMemcpyAsync(c->D.x, soa.data(), 3 * N * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    c->sweep = sweep;
+    return 0;
+}
+
+extern "C" int wmc_observables(wmc_ctx* c, wmc_obs* o) {
+    if (!c || !o) return WMC_EINVAL;
+    HIPCHK(c, hipDeviceSynchronize());
+    std::vector<unsigned long long> cnt(CNT_TOTAL);
+    HIPCHK(c, hipMemcpy(cnt.data(), c->D.cnt, CNT_TOTAL * 8, hipMemcpyDeviceToHost));
+    memset(o, 0, sizeof(*o));
+    o->sweeps = c->sweep;
+    for (int l = 0; l < WMC_MAX_LEVELS; ++l) {
+        const unsigned long long* C = cnt.data() + CNT_LEVEL + l * 8;
+        o->trials[l] = C[0];
+        o->hits[l] = C[1];
+        o->attempts[l] = C[2];
+        o->accepts[l] = C[3];
+        o->caps[l] = C[4];
+        o->redraws[l] = C[5];
+        o->bead_updates[l] = C[6];
+    }
+    const unsigned long long* W = cnt.data() + CNT_PW;
+    o->pw_chains = W[0];
+    o->pw_attempts = W[1];
+    o->pw_accepts = W[2];
+    o->pw_k0 = W[3];
+    o->pw_caps = W[4];
+    o->pw_bead_updates = W[5];
+    o->violations = cnt[CNT_VIOL];
+    o->overflows = cnt[CNT_OVERFLOW];
+    o->rechecks = cnt[CNT_RECHECK];
+    o->grid_rebuilds = cnt[CNT_REBUILD];
+    o->accepted_total = cnt[CNT_ACCEPTED];
+    return 0;
+}
+
+extern "C" int wmc_system_tau(wmc_ctx* c, double* out) {
+    if (!c || !out) return WMC_EINVAL;
+    HIPCHK(c, hipDeviceSynchronize());
+    std::vector<unsigned long long> acc(c->nsys);
+    HIPCHK(c, hipMemcpy(acc.data(), c->D.sys_acc, c->nsys * 8, hipMemcpyDeviceToHost));
+    for (int s = 0; s < c->nsys; ++s) out[s] = c->sys[s].dt * (double)acc[s];
+    return 0;
+}
+
+extern "C" int wmc_chain_rg2(wmc_ctx* c, double* out) {
+    if (!c || !out) return WMC_EINVAL;
+    HIPCHK(c, hipDeviceSynchronize());
+    launch_rg2(c->D, c->chain_off_dev, c->n_chains, c->rg2_dev, nullptr);
+    HIPCHK(c, hipMemcpy(out, c->rg2_dev, c->n_chains * 8, hipMemcpyDeviceToHost));
+    return 0;
+}
+
+extern "C" int wmc_trace(wmc_ctx* c, wmc_trace_rec* out, int64_t max, int64_t* n_out) {
+    if (!c || !n_out) return WMC_EINVAL;
+    HIPCHK(c, hipDeviceSynchronize());
+    unsigned long long n = 0;
+    HIPCHK(c, hipMemcpy(&n, c->D.trace_n, 8, hipMemcpyDeviceToHost));
+    int64_t have = std::min<int64_t>((int64_t)n, c->D.trace_cap);
+    int64_t take = std::min<int64_t>(have, max);
+    if (take > 0) HIPCHK(c, hipMemcpy(out, c->D.trace, take * sizeof(wmc_trace_rec), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemset(c->D.trace_n, 0, 8));
+    *n_out = take;
+    if ((int64_t)n > c->D.trace_cap) {
+        c->err = "trace overflowed; records were dropped";
+        return WMC_ECAPACITY;
+    }
+    return 0;
+}
+
+extern "C" int wmc_system_info(wmc_ctx* c, int32_t system, double* levels_out, int32_t* n_levels, double* pw_out) {
+    if (!c || system < 0 || system >= c->nsys) return WMC_EINVAL;
+    const std::vector<double>& l = c->level_out[system];
+    if (levels_out) std::copy(l.begin(), l.end(), levels_out);
+    if (n_levels) *n_levels = (int32_t)(l.size() / 6);
+    if (pw_out) std::copy(c->pw_out[system].begin(), c->pw_out[system].end(), pw_out);
+    return 0;
+}
+
+extern "C" int wmc_cell_ids(wmc_ctx* c, int32_t system, int64_t sweep, int32_t level, int32_t* out) {
+    if (!c || !out || system < 0 || system >= c->nsys || level < 0 || level >= c->sys[system].n_levels)
+        return WMC_EINVAL;
+    if (!c->P.periodic) launch_bbox(c->P, c->D, level, sweep, nullptr);
+    int32_t* dev = c->D.fcell;  // reused as scratch: rebuilt at the next grid build
+    launch_cell_ids(c->P, c->D, system, level, sweep, c->sys[system].N, dev, nullptr);
+    HIPCHK(c, hipMemcpy(out, dev, c->sys[system].N * 4, hipMemcpyDeviceToHost));
+    return 0;
+}
+
+extern "C" int wmc_philox(const uint32_t ctr[4], const uint32_t key[2], int64_t n, uint32_t* out, void* scratch,
+                          size_t scratch_bytes, void* stream) {
+    if (!ctr || !key || !out || n <= 0 || !scratch || scratch_bytes < (size_t)n * 16) return WMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    launch_philox(ctr, key, n, (uint32_t*)scratch, st);
+    if (hipMemcpyAsync(out, scratch, n * 16, hipMemcpyDeviceToHost, st) != hipSuccess) return WMC_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return WMC_EHIP;
+    return 0;
+}
+
+extern "C" const char* wmc_last_error(const wmc_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+extern "C" void wmc_free(wmc_ctx* c) { delete c; }

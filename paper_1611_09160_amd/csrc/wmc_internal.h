@@ -1,0 +1,100 @@
+// Internal layout shared by the host and device translation units of libwmc.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "../../include/wmc.h"
+
+namespace wmc {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Philox stream tags (third counter word, high byte)
+constexpr int TAG_META = 16;     // + level: per-cell trial count draw
+constexpr int TAG_SHIFT = 32;    // + level: grid shift
+constexpr int TAG_PWCOUNT = 48;  // plane-wave chain count
+constexpr int TAG_PW = 49;       // plane-wave chains
+
+// counter slots (uint64)
+constexpr int CNT_LEVEL = 0;     // [level*8 + k], k: trials hits attempts accepts caps redraws beads
+constexpr int CNT_PW = 128;      // chains attempts accepts k0 caps beads
+constexpr int CNT_VIOL = 136;
+constexpr int CNT_OVERFLOW = 137;
+constexpr int CNT_RECHECK = 138;
+constexpr int CNT_REBUILD = 139;
+constexpr int CNT_ACCEPTED = 140;
+constexpr int CNT_TOTAL = 160;
+
+// kernel variants of the cell phase: threads per workgroup and LDS list capacities
+enum Variant { V64 = 0, V256 = 1, V1024 = 2 };
+
+struct SysDesc {
+    int64_t b0, b1;
+    int32_t N, n_levels;
+    double L, invL, lmax, dt;
+    // plane waves
+    double PF, P_cube, W_cube, x_s, ks, invks;
+    int64_t cube_off;      // offset of this system's cube CDF in the table pool
+    int64_t shell_off;     // offset of its shell table
+    int32_t n_modes, n_shell;
+    // neighbour grid
+    int32_t nf, pad0;
+    double g, invg;
+    int64_t fine_off;      // first fine cell of this system
+    int32_t lvl_off, pad1; // index of level 0 in the level table
+};
+
+struct LevelDesc {
+    double lo, hi, p, T, h, invh, half, r_int;
+    int32_t n;             // cells per axis (periodic)
+    int32_t variant;
+    int32_t identity;      // the cell holds every bead (n == 1)
+    int32_t use_global;    // reach and member lists in global slots
+    int64_t slot_base;     // first global slot of this (system, level)
+};
+
+struct DevParams {
+    int32_t periodic, plane_waves, wavelets, precision;
+    int32_t bond_type, wca, retry_cap, n_layers;
+    double A0, kT, k_bond, R0, R02, sigma2, eps, rc2, rc, r_int;
+    uint32_t seed_lo, seed_hi;
+    int32_t nsys, pad;
+};
+
+struct DevPtrs {
+    double *x, *y, *z;          // positions (unwrapped)
+    double *xb, *yb, *zb;       // positions at the last neighbour-grid build
+    uint8_t* bond_next;         // bead i bonded to bead i+1
+    int32_t* sys_id;            // system of each bead
+    int32_t* tag;               // member index of a bead during a test, else -1
+    const SysDesc* sys;
+    const LevelDesc* lev;
+    int32_t *fcount, *fstart, *fidx, *fcell;
+    unsigned long long* drift;  // per system, bits of the max drift since the grid build
+    unsigned long long* cnt;    // CNT_* counters
+    unsigned long long* sys_acc;// accepted chains per system
+    wmc_trace_rec* trace;
+    unsigned long long* trace_n;
+    int64_t trace_cap;
+    const double* cube_cdf;
+    const double* shell_s;
+    int32_t* slot_S;            // global reach lists, slot_len entries per slot
+    int32_t* slot_M;            // global member lists
+    double* slot_MX;            // global member positions (3 * slot_len per slot)
+    int64_t slot_len;
+    double* pw_new;             // plane-wave trial positions [3N]
+    double* igrid;              // infinite-system grid of the current level: o[3], n[3]
+    int64_t total_fine;
+};
+
+// kernel launchers (device translation unit)
+void launch_fine_build(const DevParams& P, const DevPtrs& D, int64_t N, hipStream_t st);
+void launch_bbox(const DevParams& P, const DevPtrs& D, int level, int64_t sweep, hipStream_t st);
+void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
+                  const int32_t* bmap, int nblocks, hipStream_t st);
+void launch_pw(const DevParams& P, const DevPtrs& D, int64_t sweep, int nsys, hipStream_t st);
+void launch_rg2(const DevPtrs& D, const int64_t* chain_off, int64_t n_chains, double* out, hipStream_t st);
+void launch_cell_ids(const DevParams& P, const DevPtrs& D, int sys, int level, int64_t sweep, int64_t n, int32_t* out,
+                     hipStream_t st);
+void launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out, hipStream_t st);
+
+}  // namespace wmc

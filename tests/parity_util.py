@@ -1,0 +1,59 @@
+"""Helpers shared by the GPU parity tests: run the HIP path and the oracle on the same seeded
+inputs and compare traces, counters and positions."""
+import numpy as np
+
+KEY = ("kind", "system", "sweep", "level", "cell", "trial", "retry")
+
+
+def build_pair(cfg, trace=1_000_000, precision="fp64", **over):
+    from oracle import oracle as O
+    from paper_1611_09160_amd import wmc
+
+    params = dict(cfg["params"], precision=precision, **over)
+    kw = {}
+    if "sys_box_L" in cfg:
+        kw = dict(sys_box_L=cfg["sys_box_L"], sys_lambda_max=cfg["sys_lambda_max"])
+    g = wmc.WMC(params, cfg["sys_offset"], cfg["chain_offset"], cfg["pos"], trace_capacity=trace, **kw)
+    o = O.Oracle(params, cfg["sys_offset"], cfg["chain_offset"], cfg["pos"], trace_capacity=trace, **kw)
+    return g, o
+
+
+def sort_trace(t):
+    order = np.lexsort(tuple(t[k] for k in reversed(KEY)))
+    return t[order]
+
+
+def compare_traces(tg, to, dU_rtol=1e-9, dU_atol=1e-8):
+    """Same records (keys, n, anchors, decisions); energies within tolerance. Returns stats."""
+    tg, to = sort_trace(tg), sort_trace(to)
+    assert len(tg) == len(to), (len(tg), len(to))
+    for k in KEY + ("n", "extra"):
+        bad = np.nonzero(tg[k] != to[k])[0]
+        assert len(bad) == 0, (k, bad[:5], tg[bad[:5]], to[bad[:5]])
+    moves = to["kind"] != 1
+    d = np.abs(tg["dU"][moves] - to["dU"][moves])
+    fin = np.isfinite(to["dU"][moves])
+    assert np.all(np.isfinite(tg["dU"][moves]) == fin)
+    tol = dU_atol + dU_rtol * np.abs(to["dU"][moves])
+    assert np.all(d[fin] <= tol[fin]), (d[fin].max(), np.argmax(d[fin] - tol[fin]))
+    thr = np.abs(tg["thr"][moves] - to["thr"][moves])
+    assert np.all(thr <= 1e-12 * (1 + np.abs(to["thr"][moves])))
+    acc_bad = np.nonzero(tg["accepted"] != to["accepted"])[0]
+    assert len(acc_bad) == 0, (acc_bad[:5], tg[acc_bad[:5]], to[acc_bad[:5]])
+    return dict(records=len(to), moves=int(moves.sum()), max_dU_diff=float(d.max()) if len(d) else 0.0)
+
+
+def compare_positions(pg, po, rtol=1e-10):
+    scale = 1.0 + np.abs(po)
+    err = np.abs(pg - po) / scale
+    assert err.max() <= rtol, (err.max(), np.unravel_index(np.argmax(err), err.shape))
+    return float(err.max())
+
+
+def compare_counters(og, oo):
+    for k in ("trials", "hits", "attempts", "accepts", "caps", "redraws", "bead_updates"):
+        np.testing.assert_array_equal(og[k], oo[k], err_msg=k)
+    for k in ("pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates", "violations",
+              "accepted_total"):
+        assert og[k] == oo[k], (k, og[k], oo[k])
+    assert og["overflows"] == 0

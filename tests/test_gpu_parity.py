@@ -1,0 +1,97 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded
+inputs. Bar: identical integer schedule (cells, reach-list sizes, trial counts, anchors, member
+counts, accept decisions, counters), energies within 1e-9 relative + 1e-8 absolute, positions
+within 1e-10 relative per sweep (transcendentals and summation order differ by a few ulp)."""
+import numpy as np
+import pytest
+
+from tests.parity_util import build_pair, compare_counters, compare_positions, compare_traces
+
+pytestmark = pytest.mark.gpu
+
+
+def _workload(index, scale, seed=None):
+    from paper_1611_09160_amd import workloads as W
+
+    return W.config(index, scale=scale, seed=seed)
+
+
+def test_philox_bit_exact(oracle_mod):
+    from paper_1611_09160_amd import wmc
+
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        ctr = [int(v) for v in rng.integers(0, 2 ** 32, 4)]
+        key = [int(v) for v in rng.integers(0, 2 ** 32, 2)]
+        g = wmc.philox(ctr, key, 4096)
+        for i in (0, 1, 777, 4095):
+            c = [(ctr[0] + i) & 0xFFFFFFFF] + ctr[1:]
+            assert list(g[i]) == oracle_mod.philox(c, key)
+    assert list(wmc.philox([0, 0, 0, 0], [0, 0], 1)[0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+
+
+@pytest.mark.parametrize("index,scale", [(1, 1.0), (2, 0.25), (3, 0.0625), (4, 0.01)])
+def test_schedule_constants_match(index, scale):
+    cfg = _workload(index, scale)
+    g, o = build_pair(cfg, trace=0)
+    for s in range(min(3, g.n_systems)):
+        gi, oi = g.system_info(s), o.system_info(s)
+        ol = o.level_info(s)
+        assert len(gi["levels"]) == len(ol)
+        for a, b in zip(gi["levels"], ol):
+            for k in ("lo", "hi", "p", "T", "h"):
+                assert a[k] == pytest.approx(b[k], rel=1e-12), k
+            if cfg["params"]["periodic"]:
+                assert int(a["ncell"]) == b["ncell"]
+        for k in ("P_F", "dt"):
+            assert gi[k] == pytest.approx(oi[k], rel=1e-11, abs=1e-300), k
+
+
+@pytest.mark.parametrize("index,scale", [(1, 1.0), (2, 0.25), (3, 0.0625), (4, 0.01)])
+def test_cell_ids_bit_exact(index, scale):
+    cfg = _workload(index, scale)
+    g, o = build_pair(cfg, trace=0)
+    for s in range(min(3, g.n_systems)):
+        nl = len(o.level_info(s))
+        for sweep in (0, 7, 123456):
+            for level in range(nl):
+                np.testing.assert_array_equal(g.cell_ids(s, sweep, level), o.cell_ids(s, sweep, level))
+
+
+@pytest.mark.parametrize("index,scale,sweeps", [(1, 1.0, 3), (2, 0.25, 2), (3, 0.0625, 2), (4, 0.01, 1)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sweep_parity(index, scale, sweeps, precision):
+    cfg = _workload(index, scale)
+    g, o = build_pair(cfg, precision=precision)
+    for s in range(sweeps):
+        start = o.positions()
+        g.set_state(start, s)
+        o.set_sweep(s)
+        g.sweep(1)
+        o.sweep(1)
+        stats = compare_traces(g.trace(), o.trace())
+        assert stats["moves"] > 0
+        compare_positions(g.positions(), o.positions())
+    compare_counters(g.observables(), o.observables())
+    np.testing.assert_allclose(g.tau(), o.tau(), rtol=1e-12)
+    np.testing.assert_allclose(g.chain_rg2(), o.chain_rg2(), rtol=1e-10)
+
+
+def test_mixed_rechecks_near_threshold():
+    cfg = _workload(3, 0.0625)
+    g, _ = build_pair(cfg, precision="mixed", trace=0)
+    g.sweep(3)
+    ob = g.observables()
+    assert ob["overflows"] == 0
+    assert ob["rechecks"] >= 0 and ob["rechecks"] < 0.2 * ob["attempts"].sum()
+
+
+def test_full_size_semidilute_one_sweep():
+    """The benchmark workload (256 x 128 beads, L = 84) for one sweep against the oracle."""
+    cfg = _workload(3, 1.0)
+    g, o = build_pair(cfg, trace=4_000_000)
+    g.sweep(1)
+    o.sweep(1)
+    compare_traces(g.trace(4_000_000), o.trace(4_000_000))
+    compare_positions(g.positions(), o.positions())
+    compare_counters(g.observables(), o.observables())
