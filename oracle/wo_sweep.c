@@ -285,7 +285,7 @@ static void pair_nonmember(wo_ctx* c, wo_system* s, int64_t m, void* vp) {
 
 /* one Metropolis test of a wavelet move; returns 1 if accepted (positions updated) */
 static int wavelet_attempt(wo_ctx* c, wo_system* s, int sysid, int level, int64_t cell,
-                           int64_t t, int r, int64_t nS, int64_t nH, double lam, int64_t anchor,
+                           int64_t t, int r, int64_t nS, double lam, int64_t anchor,
                            const double b[3], const double p[3], double u_acc) {
     double L = s->L, invL = c->p.periodic ? 1.0 / s->L : 0.0;
     int per = c->p.periodic;
@@ -381,13 +381,10 @@ static int wavelet_attempt(wo_ctx* c, wo_system* s, int sysid, int level, int64_
 static void process_cell(wo_ctx* c, wo_system* s, int sysid, int level, const grid_t* g,
                          int64_t cell, const int64_t ic[3]) {
     const wo_level_info* lv = &s->lev[level];
-    int64_t nS = 0, nH = 0;
-    double hi2 = g->hi * g->hi, rh2 = g->rh * g->rh;
-    for (int64_t j = s->b0; j < s->b1; ++j) {
-        double d2 = dist2_cell(g, ic, c->x[j], c->y[j], c->z[j]);
-        if (d2 <= hi2) c->S[nS++] = j;
-        if (d2 <= rh2) c->H[nH++] = j;
-    }
+    int64_t nS = 0;
+    double hi2 = g->hi * g->hi;
+    for (int64_t j = s->b0; j < s->b1; ++j)
+        if (dist2_cell(g, ic, c->x[j], c->y[j], c->z[j]) <= hi2) c->S[nS++] = j;
     /* number of trials: stochastic rounding of T_l |S_c| / N */
     double mu = (lv->T * (double)nS) / (double)s->N;
     int64_t K = (int64_t)floor(mu);
@@ -410,7 +407,7 @@ static void process_cell(wo_ctx* c, wo_system* s, int sysid, int level, const gr
             double p[3];
             draw_direction(&st, p);
             double u_acc = wo_next_oc(&st);
-            if (wavelet_attempt(c, s, sysid, level, cell, t, r, nS, nH, lam, anchor, b, p, u_acc)) {
+            if (wavelet_attempt(c, s, sysid, level, cell, t, r, nS, lam, anchor, b, p, u_acc)) {
                 s->accepted++;
                 c->obs.accepted_total++;
                 break;
@@ -425,7 +422,7 @@ static void process_cell(wo_ctx* c, wo_system* s, int sysid, int level, const gr
             if (!found) { c->obs.caps[level]++; break; }
         }
     }
-    trace_push(c, 1, sysid, level, cell, K, (int)nS, nH, (int)hits, 0, 0.0, 0.0);
+    trace_push(c, 1, sysid, level, cell, K, (int)nS, 0, (int)hits, 0, 0.0, 0.0);
 }
 
 /* ------------------------------------------------------------- plane waves -------- */

@@ -685,6 +685,8 @@ __device__ void process_cell(const DevParams& P, const DevPtrs& D, PhaseShared<W
                 if (f && (glob || n + before < CAPM)) Ml[n + before] = j;
                 n += tot;
             }
+            // members written by lanes of other waves must land before any lane reads them
+            __syncthreads();
             if (!glob && n > CAPM) {
                 if (tid == 0) atomicAdd(&D.cnt[CNT_OVERFLOW], 1ull);
                 __syncthreads();

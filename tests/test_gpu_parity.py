@@ -69,7 +69,10 @@ def test_sweep_parity(index, scale, sweeps, precision):
         o.set_sweep(s)
         g.sweep(1)
         o.sweep(1)
-        stats = compare_traces(g.trace(), o.trace())
+        # mixed mode reports FP32-accurate energies; its decisions are rechecked in FP64 near
+        # the threshold, so they must still match exactly
+        tol = dict(dU_rtol=1e-5, dU_atol=1e-4) if precision == "mixed" else {}
+        stats = compare_traces(g.trace(), o.trace(), **tol)
         assert stats["moves"] > 0
         compare_positions(g.positions(), o.positions())
     compare_counters(g.observables(), o.observables())
