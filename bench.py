@@ -1,0 +1,164 @@
+"""Benchmark: Wavelet Monte Carlo dynamics sweeps on one MI355X.
+
+Workload: semi-dilute periodic solution, 256 chains x 128 beads (32,768 beads), FENE + WCA,
+box L = 84 (c/c* ~ 1), wavelet levels lambda = 1 .. L/4 in octave bands plus plane waves,
+A0 = 0.5, synthetic self-avoiding random-walk start, 200 equilibration sweeps.
+
+A step is one sweep. Prints one JSON line:
+  value         bead-updates/s of the timed sweeps (beads displaced per Metropolis test,
+                wavelet and plane wave, accepted or not, summed; inputs resident in HBM)
+  tau_per_wall_s  physical time (units of tau) advanced per wall-clock second
+  roofline      the dominant kernel class, timed with HIP events on the library's stream
+  cpu_baseline  the FP64 oracle on the host, on a bounded sample of sweeps of the same state
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(cls: str, N: int, n_fine: int, pw_attempts_per_launch: float) -> float:
+    """Bytes one launch of a kernel class must move at minimum.
+
+    level phases: each of the 8 colour phases of a level reads and writes the positions of
+      its share of the beads once and re-reads the neighbour-grid entries (4 B index + 4 B
+      cell start): N (24 + 24 + 8) / 8 per launch.
+    grid: read positions, write the reference copy and the cell of every bead, count, scan,
+      scatter and sort: N (24 + 24 + 4 + 4 + 8 + 8) + 12 n_fine.
+    plane waves: per test read positions, write and re-read trial positions, read the
+      neighbour grid and write accepted positions: N (24 + 24 + 24 + 8 + 24).
+    """
+    if cls.startswith("level"):
+        return N * (24 + 24 + 8) / 8.0
+    if cls == "grid":
+        return N * (24 + 24 + 4 + 4 + 8 + 8) + 12.0 * n_fine
+    if cls == "plane_waves":
+        return N * (24 + 24 + 24 + 8 + 24) * pw_attempts_per_launch
+    return 0.0
+
+
+def run_gpu(cfg, precision: str, equilibrate: int, warmup: int, steps: int, start=None):
+    import numpy as np
+    import torch
+
+    from paper_1611_09160_amd import wmc
+
+    g = wmc.WMC(dict(cfg["params"], precision=precision), cfg["sys_offset"], cfg["chain_offset"],
+                cfg["pos"] if start is None else start)
+    if start is None:
+        g.sweep(equilibrate)
+    g.sweep(warmup)
+    torch.cuda.synchronize()
+    o0 = g.observables()
+    tau0 = g.tau().sum()
+    g.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.sweep(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = g.kernel_times()
+    o1 = g.observables()
+    tau1 = g.tau().sum()
+    beads = int(o1["bead_updates"].sum() - o0["bead_updates"].sum() + o1["pw_bead_updates"] - o0["pw_bead_updates"])
+    res = dict(
+        seconds=dt, steps=steps, bead_updates=beads, bead_updates_per_s=beads / dt, ms_per_step=1000.0 * dt / steps,
+        tau_per_wall_s=(tau1 - tau0) / dt, sweeps_per_s=steps / dt,
+        acceptance=[round(float(a) / max(1, b), 4) for a, b in
+                    zip(o1["accepts"] - o0["accepts"], o1["attempts"] - o0["attempts"]) if b > 0],
+        pw_attempts=int(o1["pw_attempts"] - o0["pw_attempts"]), overflows=int(o1["overflows"]),
+        violations=int(o1["violations"]), rechecks=int(o1["rechecks"] - o0["rechecks"]), kernel_ms=kt,
+    )
+    return g, res
+
+
+def run_oracle(cfg, start, sweep0: int, budget_s: float):
+    from oracle import oracle as O
+
+    o = O.Oracle(cfg["params"], cfg["sys_offset"], cfg["chain_offset"], start)
+    o.set_sweep(sweep0)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        o.sweep(1)
+        n += 1
+        if time.perf_counter() - t0 > budget_s or n >= 50:
+            break
+    dt = time.perf_counter() - t0
+    ob = o.observables()
+    beads = int(ob["bead_updates"].sum() + ob["pw_bead_updates"])
+    return dict(value=beads / dt, unit="bead-updates/s", cores=1, kind="oracle",
+                sample=f"{n} sweeps of the equilibrated workload state, single-threaded FP64 C (gcc -O2)",
+                seconds=round(dt, 2), tau_per_wall_s=float(o.tau().sum()) / dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--equilibrate", type=int, default=200)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_1611_09160_amd import workloads as W
+
+    cfg = W.config(3)
+    N = int(cfg["sys_offset"][-1])
+    g64, r64 = run_gpu(cfg, "fp64", args.equilibrate, args.warmup, args.steps)
+    start = g64.positions()
+    sweep0 = args.equilibrate + args.warmup + args.steps
+    gm, rmix = run_gpu(cfg, "mixed", 0, args.warmup, args.steps, start=start)
+    # roofline of the dominant kernel class of the FP64 run
+    kt = r64["kernel_ms"]
+    n_fine = 55 ** 3
+    pw_per_launch = r64["pw_attempts"] / max(1, kt.get("plane_waves", (0, 1))[1])
+    dom = max(kt, key=lambda k: kt[k][0])
+    ms, launches = kt[dom]
+    avg_s = ms / 1000.0 / launches
+    alg = algorithmic_bytes(dom, N, n_fine, pw_per_launch)
+    achieved = alg / avg_s / 1e9
+    roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 3), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=achieved / HBM_PEAK_GBS, traffic=None, avg_launch_us=round(avg_s * 1e6, 2),
+                launches=launches, algorithmic_bytes_per_launch=int(alg),
+                share_of_step=round(ms / (r64["seconds"] * 1000.0), 3))
+    cpu = None
+    if not args.no_cpu:
+        cpu = run_oracle(cfg, start, sweep0, args.cpu_budget)
+    line = dict(
+        metric="bead-updates/s + physical time/wall-s at 32k beads; mixed vs FP64 same GPU",
+        value=round(r64["bead_updates_per_s"], 1), unit="bead-updates/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(r64["ms_per_step"], 3), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload="semi-dilute periodic solution 256 chains x 128 beads (32768), FENE k=30 R0=1.5 + WCA, "
+                             "L=84 (c/c*~1), lambda 1..21 octave levels + plane waves, A0=0.5, plain FP64 GPU path",
+                    n_beads=N, box_L=84.0, equilibration_sweeps=args.equilibrate),
+        tau_per_wall_s=round(r64["tau_per_wall_s"], 4), sweeps_per_s=round(r64["sweeps_per_s"], 2),
+        acceptance_per_level=r64["acceptance"], roofline=roof, cpu_baseline=cpu,
+        mixed=dict(value=round(rmix["bead_updates_per_s"], 1), ms_per_step=round(rmix["ms_per_step"], 3),
+                   tau_per_wall_s=round(rmix["tau_per_wall_s"], 4), rechecks=rmix["rechecks"],
+                   ratio_vs_fp64=round(rmix["bead_updates_per_s"] / r64["bead_updates_per_s"], 3)),
+        kernel_ms_fp64={k: [round(v[0], 3), v[1]] for k, v in kt.items()},
+        checks=dict(overflows=r64["overflows"] + rmix["overflows"], violations=r64["violations"]),
+    )
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

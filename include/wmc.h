@@ -166,6 +166,14 @@ int wmc_cell_ids(wmc_ctx* c, int32_t system, int64_t sweep, int32_t level, int32
 int wmc_philox(const uint32_t ctr[4], const uint32_t key[2], int64_t n, uint32_t* out,
                void* device_scratch, size_t scratch_bytes, void* hip_stream);
 
+/* Kernel timing. With timing on, wmc_sweep records HIP events on its stream around every
+ * kernel class; wmc_kernel_times synchronises and returns, per class, the summed duration
+ * (ms) and the number of launches since timing was switched on. Classes: 0 neighbour-grid
+ * build (4 kernels), 1 + l the colour phases of level l (l < WMC_MAX_LEVELS), 17 plane waves. */
+#define WMC_TIMING_CLASSES 18
+int wmc_set_timing(wmc_ctx* c, int32_t enable);
+int wmc_kernel_times(wmc_ctx* c, double* ms_out, int64_t* launches_out);
+
 const char* wmc_last_error(const wmc_ctx* c);
 void wmc_free(wmc_ctx* c);
 

@@ -44,6 +44,12 @@ struct wmc_ctx {
     int64_t* chain_off_dev;
     double* rg2_dev;
     int64_t sweep;
+    // kernel timing: event pairs per class, summed lazily
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    double t_ms[WMC_TIMING_CLASSES] = {0};
+    int64_t t_n[WMC_TIMING_CLASSES] = {0};
     char* arena;
     size_t arena_bytes;
     std::string err;
@@ -654,6 +660,49 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     return 0;
 }
 
+static hipEvent_t take_event(wmc_ctx* c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// record an event pair around the launches of one kernel class when timing is on
+struct Timed {
+    wmc_ctx* c;
+    int cls;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    Timed(wmc_ctx* c_, int cls_, hipStream_t st_) : c(c_), cls(cls_), st(st_) {
+        if (c->timing && (a = take_event(c))) hipEventRecord(a, st);
+    }
+    ~Timed() {
+        if (!a) return;
+        hipEvent_t b = take_event(c);
+        if (!b) return;
+        hipEventRecord(b, st);
+        c->ev_pending.push_back({cls, {a, b}});
+    }
+};
+
+static void drain_events(wmc_ctx* c) {
+    for (auto& p : c->ev_pending) {
+        float ms = 0.0f;
+        hipEventSynchronize(p.second.second);
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            c->t_ms[p.first] += ms;
+            c->t_n[p.first] += 1;
+        }
+        c->ev_pool.push_back(p.second.first);
+        c->ev_pool.push_back(p.second.second);
+    }
+    c->ev_pending.clear();
+}
+
 extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
     if (!c) return WMC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
@@ -661,23 +710,57 @@ extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
         const int64_t sw = c->sweep;
         for (int l = 0; c->p.wavelets && l < c->max_levels; ++l) {
             if (c->P.periodic) {
-                launch_fine_build(c->P, c->D, c->N, st);
-                for (int col = 0; col < 8; ++col)
+                {
+                    Timed t(c, 0, st);
+                    launch_fine_build(c->P, c->D, c->N, st);
+                }
+                for (int col = 0; col < 8; ++col) {
+                    if (c->bmap_n[l][col] <= 0) continue;
+                    Timed t(c, 1 + l, st);
                     launch_phase(c->phase_variant[l], c->P, c->D, l, col, sw, c->bmap_dev + 2 * c->bmap_off[l][col],
                                  c->bmap_n[l][col], st);
+                }
             } else {
                 launch_bbox(c->P, c->D, l, sw, st);
-                for (int col = 0; col < 8; ++col)
+                for (int col = 0; col < 8; ++col) {
+                    Timed t(c, 1 + l, st);
                     launch_phase(c->phase_variant[l], c->P, c->D, l, col, sw, nullptr, 64, st);
+                }
             }
         }
         if (c->P.periodic && c->P.plane_waves) {
-            launch_fine_build(c->P, c->D, c->N, st);
+            {
+                Timed t(c, 0, st);
+                launch_fine_build(c->P, c->D, c->N, st);
+            }
+            Timed t(c, 17, st);
             launch_pw(c->P, c->D, sw, c->nsys, st);
         }
         c->sweep++;
+        if (c->ev_pending.size() > 4096) drain_events(c);
     }
     HIPCHK(c, hipGetLastError());
+    return 0;
+}
+
+extern "C" int wmc_set_timing(wmc_ctx* c, int32_t enable) {
+    if (!c) return WMC_EINVAL;
+    drain_events(c);
+    c->timing = enable != 0;
+    for (int i = 0; i < WMC_TIMING_CLASSES; ++i) {
+        c->t_ms[i] = 0.0;
+        c->t_n[i] = 0;
+    }
+    return 0;
+}
+
+extern "C" int wmc_kernel_times(wmc_ctx* c, double* ms_out, int64_t* n_out) {
+    if (!c) return WMC_EINVAL;
+    drain_events(c);
+    for (int i = 0; i < WMC_TIMING_CLASSES; ++i) {
+        if (ms_out) ms_out[i] = c->t_ms[i];
+        if (n_out) n_out[i] = c->t_n[i];
+    }
     return 0;
 }
 
@@ -810,4 +893,9 @@ extern "C" int wmc_philox(const uint32_t ctr[4], const uint32_t key[2], int64_t 
 
 extern "C" const char* wmc_last_error(const wmc_ctx* c) { return c ? c->err.c_str() : "no context"; }
 
-extern "C" void wmc_free(wmc_ctx* c) { delete c; }
+extern "C" void wmc_free(wmc_ctx* c) {
+    if (!c) return;
+    drain_events(c);
+    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    delete c;
+}

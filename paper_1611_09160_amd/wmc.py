@@ -71,11 +71,14 @@ def lib():
         L.wmc_cell_ids.argtypes = [vp, i32, i64, i32, C.POINTER(C.c_int32)]
         L.wmc_philox.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), i64, C.POINTER(C.c_uint32), vp,
                                  C.c_size_t, vp]
+        L.wmc_set_timing.argtypes = [vp, i32]
+        L.wmc_kernel_times.argtypes = [vp, dp, lp]
         L.wmc_last_error.argtypes = [vp]
         L.wmc_last_error.restype = C.c_char_p
         L.wmc_free.argtypes = [vp]
         for f in ("wmc_arena_bytes", "wmc_init", "wmc_sweep", "wmc_positions", "wmc_set_state", "wmc_observables",
-                  "wmc_system_tau", "wmc_chain_rg2", "wmc_trace", "wmc_system_info", "wmc_cell_ids", "wmc_philox"):
+                  "wmc_system_tau", "wmc_chain_rg2", "wmc_trace", "wmc_system_info", "wmc_cell_ids", "wmc_philox",
+                  "wmc_set_timing", "wmc_kernel_times"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -225,6 +228,17 @@ class WMC:
         self._check(lib().wmc_system_info(self._h, system, _dp(lv), C.byref(n), _dp(pw)), "wmc_system_info")
         levels = [dict(zip(("lo", "hi", "p", "T", "h", "ncell"), lv[6 * i: 6 * i + 6])) for i in range(n.value)]
         return {"levels": levels, **dict(zip(("P_F", "R", "N_k", "P_cube", "P_k0", "dt"), pw))}
+
+    def set_timing(self, enable: bool = True):
+        self._check(lib().wmc_set_timing(self._h, int(enable)), "wmc_set_timing")
+
+    def kernel_times(self) -> dict:
+        """Per kernel class: summed milliseconds and launch count since timing was switched on."""
+        ms = np.zeros(18)
+        n = np.zeros(18, dtype=np.int64)
+        self._check(lib().wmc_kernel_times(self._h, _dp(ms), _lp(n)), "wmc_kernel_times")
+        names = ["grid"] + [f"level{l}" for l in range(MAX_LEVELS)] + ["plane_waves"]
+        return {names[i]: (float(ms[i]), int(n[i])) for i in range(18) if n[i] > 0}
 
     def cell_ids(self, system: int, sweep: int, level: int) -> np.ndarray:
         n = int(self.sys_off[system + 1] - self.sys_off[system])
