@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <math.h>
+#include <algorithm>
 #include "wmc_internal.h"
 
 namespace wmc {
@@ -364,36 +365,66 @@ __global__ void k_fine_count(DevPtrs D, int64_t N) {
     atomicAdd(&D.fcount[fc], 1);
 }
 
-// exclusive scan of the counts by one workgroup; also clears the per-system drift
-__global__ __launch_bounds__(1024) void k_fine_scan(DevPtrs D, int nsys) {
-    __shared__ int part[1024];
-    const int64_t T = D.total_fine;
-    const int tid = threadIdx.x;
-    const int64_t per = (T + 1023) / 1024;
-    const int64_t a = tid * per, b = min(T, a + per);
+// exclusive scan of the neighbour-grid counts in chunks of 4096 cells: per-chunk sums, then
+// each workgroup adds the sums of the chunks before it and scans its own chunk
+constexpr int SCAN_CHUNK = 4096;
+
+__global__ __launch_bounds__(1024) void k_scan_sums(DevPtrs D) {
+    __shared__ int red[16];
+    const int64_t a = (int64_t)blockIdx.x * SCAN_CHUNK;
     int acc = 0;
-    for (int64_t i = a; i < b; ++i) acc += D.fcount[i];
-    part[tid] = acc;
+    for (int k = threadIdx.x; k < SCAN_CHUNK; k += 1024) {
+        int64_t i = a + k;
+        if (i < D.total_fine) acc += D.fcount[i];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < 16; ++w) t += red[w];
+        D.fblock[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_apply(DevPtrs D, int nsys, int nchunks) {
+    __shared__ int part[1024];
+    __shared__ int base;
+    const int tid = threadIdx.x;
     if (tid == 0) {
-        int run = 0;
-        for (int i = 0; i < 1024; ++i) {
-            int v = part[i];
-            part[i] = run;
-            run += v;
-        }
+        int b = 0;
+        for (int c = 0; c < (int)blockIdx.x; ++c) b += D.fblock[c];
+        base = b;
     }
+    // each thread owns 4 consecutive cells of the chunk
+    const int64_t a = (int64_t)blockIdx.x * SCAN_CHUNK + 4 * tid;
+    int v[4], sum = 0;
+    for (int q = 0; q < 4; ++q) {
+        v[q] = (a + q < D.total_fine) ? D.fcount[a + q] : 0;
+        sum += v[q];
+    }
+    part[tid] = sum;
     __syncthreads();
-    int run = part[tid];
-    for (int64_t i = a; i < b; ++i) {
-        int v = D.fcount[i];
-        D.fstart[i] = run;
-        D.fcount[i] = 0;
-        run += v;
+    // Hillis-Steele inclusive scan of the 1024 per-thread sums
+    for (int o = 1; o < 1024; o <<= 1) {
+        int t = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += t;
+        __syncthreads();
     }
-    if (tid == 1023) D.fstart[T] = run;
-    for (int s = tid; s < nsys; s += 1024) D.drift[s] = 0ull;
-    if (tid == 0) atomicAdd(&D.cnt[CNT_REBUILD], 1ull);
+    int run = base + part[tid] - sum;
+    for (int q = 0; q < 4; ++q) {
+        if (a + q < D.total_fine) {
+            D.fstart[a + q] = run;
+            D.fcount[a + q] = 0;
+        }
+        run += v[q];
+    }
+    if ((int)blockIdx.x == nchunks - 1 && tid == 1023) D.fstart[D.total_fine] = base + part[1023];
+    if (blockIdx.x == 0) {
+        for (int s = tid; s < nsys; s += 1024) D.drift[s] = 0ull;
+        if (tid == 0) atomicAdd(&D.cnt[CNT_REBUILD], 1ull);
+    }
 }
 
 __global__ void k_fine_scatter(DevPtrs D, int64_t N) {
@@ -425,7 +456,9 @@ void launch_fine_build(const DevParams& P, const DevPtrs& D, int64_t N, hipStrea
     if (N == 0) return;
     int nb = (int)((N + 255) / 256);
     hipLaunchKernelGGL(k_fine_count, dim3(nb), dim3(256), 0, st, D, N);
-    hipLaunchKernelGGL(k_fine_scan, dim3(1), dim3(1024), 0, st, D, P.nsys);
+    int nchunks = (int)((D.total_fine + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nchunks), dim3(1024), 0, st, D);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nchunks), dim3(1024), 0, st, D, P.nsys, nchunks);
     hipLaunchKernelGGL(k_fine_scatter, dim3(nb), dim3(256), 0, st, D, N);
     int nc = (int)((D.total_fine + 255) / 256);
     hipLaunchKernelGGL(k_fine_sort, dim3(nc), dim3(256), 0, st, D);
@@ -490,7 +523,8 @@ struct PhaseShared {
 };
 
 template <int W, int CAPS, int CAPM>
-__device__ void process_cell(const DevParams& P, const DevPtrs& D, PhaseShared<W, CAPS, CAPM>& sh, int sys,
+__device__ __attribute__((noinline)) void process_cell(const DevParams& P, const DevPtrs& D,
+                                                       PhaseShared<W, CAPS, CAPM>& sh, int sys,
                              int level, int colour, int64_t local, int64_t sweep, const Grid& g) {
     const SysDesc& s = D.sys[sys];
     const LevelDesc& lv = D.lev[s.lvl_off + level];
@@ -941,17 +975,463 @@ __device__ void process_cell(const DevParams& P, const DevPtrs& D, PhaseShared<W
     __syncthreads();
 }
 
-template <int W, int CAPS, int CAPM>
+// ------------------------------------------------------------- cell phase, LDS tile
+// The cell's interaction halo -- every bead within lambda_hi + r_int of the cell -- is staged
+// in LDS once per phase, sorted by bead index, with FP64 positions and its bond flags. Beads of
+// the halo move only through this cell's own moves during the phase, and every bead within the
+// pair cut-off or the bond length of a member lies in it, so trials, member tests,
+// displacements and dU run from LDS; accepted moves are also written through to HBM.
+constexpr int32_t ID_MASK = 0x3FFFFFFF;
+constexpr int32_t ID_NEXT = 0x40000000;  // bonded to bead id + 1
+constexpr uint32_t ID_PREV = 0x80000000u;  // bonded to bead id - 1
+
+template <int W, int CAPH, int CAPM>
+struct TileShared {
+    double x[CAPH], y[CAPH], z[CAPH];
+    int32_t id[CAPH];
+    int16_t tag[CAPH];
+    int16_t S[CAPH];
+    int16_t M[CAPM];
+    double MX[CAPM], MY[CAPM], MZ[CAPM];
+    double red[W / 64 > 0 ? W / 64 : 1];
+    int redi[W / 64 > 0 ? W / 64 : 1];
+    int count;
+    double pub_b[3];
+    double pub_lam;
+    int32_t pub_a;
+    uint32_t pub_next;
+};
+
+template <int W, int CAPS, int CAPM, int CAPH, int CAPMT>
+union PhaseLDS {
+    PhaseShared<W, CAPS, CAPM> g;
+    TileShared<W, CAPH, CAPMT> t;
+};
+
+// slot of bead j in the sorted tile, or -1
+template <int W, int CAPH, int CAPM>
+__device__ __forceinline__ int tile_find(const TileShared<W, CAPH, CAPM>& sh, int nH, int32_t j) {
+    int lo = 0, hi = nH - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int32_t v = sh.id[mid] & ID_MASK;
+        if (v == j) return mid;
+        if (v < j) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ void cell_coords(const DevParams& P, const LevelDesc& lv, const Grid& g, int colour,
+                                            int64_t local, int64_t ic[3]) {
+    if (P.periodic) {
+        int64_t m = lv.n >= 2 ? lv.n / 2 : 1;
+        ic[0] = 2 * (local % m) + (lv.n >= 2 ? (colour & 1) : 0);
+        ic[1] = 2 * ((local / m) % m) + (lv.n >= 2 ? ((colour >> 1) & 1) : 0);
+        ic[2] = 2 * (local / (m * m)) + (lv.n >= 2 ? ((colour >> 2) & 1) : 0);
+    } else {
+        int64_t mx = (g.n[0] - (colour & 1) + 1) / 2, my = (g.n[1] - ((colour >> 1) & 1) + 1) / 2;
+        ic[0] = 2 * (local % mx) + (colour & 1);
+        ic[1] = 2 * ((local / mx) % my) + ((colour >> 1) & 1);
+        ic[2] = 2 * (local / (mx * my)) + ((colour >> 2) & 1);
+    }
+}
+
+// energy change of the current test over the tile: bonds and WCA pairs with >= 1 member, each
+// once; members are tile slots sh.M[0..n) with trial positions sh.MX/MY/MZ and tags set.
+// mode 0: FP64; mode 1: FP32 terms (acc) with their sensitivity (sens).
+template <int W, int CAPH, int CAPM>
+__device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, const TileShared<W, CAPH, CAPM>& sh,
+                        int nH, int n, int mode, double& acc, double& sens, unsigned long long& viol) {
+    const int tid = threadIdx.x;
+    const double L = s.L, invL = s.invL;
+    if (P.bond_type != WMC_BOND_NONE) {
+        for (int k = tid; k < n; k += W) {
+            const int sl = sh.M[k];
+            const int32_t raw = sh.id[sl];
+            const int32_t j = raw & ID_MASK;
+            const double jx = sh.x[sl], jy = sh.y[sl], jz = sh.z[sl];
+            const double kx = sh.MX[k], ky = sh.MY[k], kz = sh.MZ[k];
+            for (int e = 0; e < 2; ++e) {
+                bool bonded = e == 0 ? (raw & ID_NEXT) != 0 : ((uint32_t)raw & ID_PREV) != 0;
+                if (!bonded) continue;
+                const int32_t m = e == 0 ? j + 1 : j - 1;
+                int ps = e == 0 ? sl + 1 : sl - 1;
+                if (ps < 0 || ps >= nH || (sh.id[ps] & ID_MASK) != m) ps = tile_find(sh, nH, m);
+                double mx, my, mz, nx, ny, nz;
+                if (ps >= 0) {
+                    const int tm = sh.tag[ps];
+                    if (tm >= 0 && ps < sl) continue;
+                    mx = sh.x[ps];
+                    my = sh.y[ps];
+                    mz = sh.z[ps];
+                    nx = tm >= 0 ? sh.MX[tm] : mx;
+                    ny = tm >= 0 ? sh.MY[tm] : my;
+                    nz = tm >= 0 ? sh.MZ[tm] : mz;
+                } else {
+                    // partner beyond the halo: only a bond longer than r_int can do this
+                    mx = nx = D.x[m];
+                    my = ny = D.y[m];
+                    mz = nz = D.z[m];
+                }
+                double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
+                double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
+                if (r2o > P.r_int * P.r_int) ++viol;
+                if (mode) {
+                    acc += (double)(u_bond_f(P, (float)r2n) - u_bond_f(P, (float)r2o));
+                    sens += sens_bond(P, r2n) + sens_bond(P, r2o);
+                } else {
+                    acc += u_bond(P, r2n) - u_bond(P, r2o);
+                }
+            }
+        }
+    }
+    if (P.wca) {
+        for (int k = 0; k < n; ++k) {
+            const int sl = sh.M[k];
+            const double jx = sh.x[sl], jy = sh.y[sl], jz = sh.z[sl];
+            const double kx = sh.MX[k], ky = sh.MY[k], kz = sh.MZ[k];
+            for (int m = tid; m < nH; m += W) {
+                if (m == sl) continue;
+                const int tm = sh.tag[m];
+                if (tm >= 0 && m < sl) continue;
+                const double mx = sh.x[m], my = sh.y[m], mz = sh.z[m];
+                double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
+                double r2n = tm >= 0 ? pair_r2(P, invL, L, kx, ky, kz, sh.MX[tm], sh.MY[tm], sh.MZ[tm])
+                                     : pair_r2(P, invL, L, kx, ky, kz, mx, my, mz);
+                if (r2o < P.rc2 || r2n < P.rc2) {
+                    if (mode) {
+                        acc += (double)(u_pair_f(P, (float)r2n) - u_pair_f(P, (float)r2o));
+                        sens += sens_pair(P, r2n) + sens_pair(P, r2o);
+                    } else {
+                        acc += u_pair(P, r2n) - u_pair(P, r2o);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// returns false (before any move) when the halo does not fit; the caller then uses the
+// global path for this cell
+template <int W, int CAPH, int CAPM>
+__device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShared<W, CAPH, CAPM>& sh, int sys,
+                                  int level, int colour, int64_t local, int64_t sweep, const Grid& g) {
+    const SysDesc& s = D.sys[sys];
+    const LevelDesc& lv = D.lev[s.lvl_off + level];
+    const int tid = threadIdx.x;
+    int64_t ic[3];
+    cell_coords(P, lv, g, colour, local, ic);
+    const int64_t cell = ic[0] + g.n[0] * (ic[1] + g.n[1] * ic[2]);
+    const double hi2 = lv.hi * lv.hi;
+    const double rh = lv.hi + lv.r_int, rh2 = rh * rh;
+    const double Dg = __longlong_as_double((long long)D.drift[sys]);
+    const double L = s.L, invL = s.invL;
+
+    // ---- 1. halo gather from the neighbour grid
+    if (tid == 0) sh.count = 0;
+    __syncthreads();
+    {
+        double R = rh + Dg + 1e-9 * L;
+        int f0[3], cn[3];
+        for (int a = 0; a < 3; ++a) {
+            double lo = g.o[a] + (double)ic[a] * g.h - R;
+            fine_range(lo, lo + g.h + 2.0 * R, s.invg, s.nf, f0[a], cn[a]);
+        }
+        const int total = cn[0] * cn[1] * cn[2];
+        for (int q = tid; q < total; q += W) {
+            int qx = q % cn[0], qy = (q / cn[0]) % cn[1], qz = q / (cn[0] * cn[1]);
+            int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
+            int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
+            for (int k = D.fstart[fc]; k < D.fstart[fc + 1]; ++k) {
+                int32_t j = D.fidx[k];
+                if (dist2_cell(g, ic, D.x[j], D.y[j], D.z[j]) <= rh2) {
+                    int idx = atomicAdd(&sh.count, 1);
+                    if (idx < CAPH) sh.id[idx] = j;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int nH = sh.count;
+    if (nH > CAPH) return false;
+    // ---- 2. sort by bead index (bitonic), then positions, bond flags and the reach list
+    {
+        int np2 = 1;
+        while (np2 < nH) np2 <<= 1;
+        for (int i = nH + tid; i < np2; i += W) sh.id[i] = 0x7FFFFFFF;
+        __syncthreads();
+        for (int k = 2; k <= np2; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int i = tid; i < np2; i += W) {
+                    int l = i ^ jj;
+                    if (l > i) {
+                        int32_t a = sh.id[i], b = sh.id[l];
+                        bool up = (i & k) == 0;
+                        if ((a > b) == up) {
+                            sh.id[i] = b;
+                            sh.id[l] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    int nS = 0;
+    for (int c0 = 0; c0 < nH; c0 += W) {
+        int i = c0 + tid;
+        bool f = false;
+        if (i < nH) {
+            int32_t j = sh.id[i];
+            double x = D.x[j], y = D.y[j], z = D.z[j];
+            sh.x[i] = x;
+            sh.y[i] = y;
+            sh.z[i] = z;
+            sh.tag[i] = -1;
+            int32_t fl = j;
+            if (j + 1 < s.b1 && D.bond_next[j]) fl |= ID_NEXT;
+            if (j > s.b0 && D.bond_next[j - 1]) fl = (int32_t)((uint32_t)fl | ID_PREV);
+            sh.id[i] = fl;
+            f = dist2_cell(g, ic, x, y, z) <= hi2;
+        }
+        int before;
+        int tot = block_scan_flag<W>(f, before, sh.redi);
+        if (f) sh.S[nS + before] = (int16_t)i;
+        nS += tot;
+    }
+    __syncthreads();
+
+    // ---- 3. trials and chains (as the global path, on LDS)
+    double mu = (lv.T * (double)nS) / (double)s.N;
+    int64_t K = (int64_t)floor(mu);
+    {
+        Stream ms;
+        ms.init(P, sys, sweep, TAG_META + level, cell, 0, 0, 0);
+        if (ms.co() < mu - (double)K) K += 1;
+    }
+    if (K > 0xFFFFF) {
+        K = 0xFFFFF;
+        if (tid == 0) atomicAdd(&D.cnt[CNT_VIOL], 1ull);
+    }
+    unsigned long long c_hits = 0, c_att = 0, c_acc = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0;
+    double d_local = 0.0;
+    const bool mixed = P.precision == WMC_MIXED;
+    for (int64_t t0 = 0; t0 < K;) {
+        int64_t t = t0 + tid;
+        bool hit = false;
+        double lam = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
+        int as = 0;
+        Stream st;
+        if (t < K && nS > 0) {
+            st.init(P, sys, sweep, level, cell, t, 0, 0);
+            lam = draw_lambda(st.co(), lv.lo, lv.hi);
+            as = sh.S[st.index(nS)];
+            double vx, vy, vz;
+            ball(st, vx, vy, vz);
+            bx = sh.x[as] + lam * vx;
+            by = sh.y[as] + lam * vy;
+            bz = sh.z[as] + lam * vz;
+            hit = cell_of_point(g, bx, by, bz) == cell;
+        }
+        int first = block_min_int<W>(hit ? (int)(t - t0) : 0x7FFFFFFF, sh.redi);
+        if (first == 0x7FFFFFFF) {
+            t0 += W;
+            continue;
+        }
+        if (tid == first) {
+            sh.pub_lam = lam;
+            sh.pub_a = as;
+            sh.pub_b[0] = bx;
+            sh.pub_b[1] = by;
+            sh.pub_b[2] = bz;
+            sh.pub_next = st.next;
+        }
+        __syncthreads();
+        const int64_t tc = t0 + first;
+        lam = sh.pub_lam;
+        as = sh.pub_a;
+        double b[3] = {sh.pub_b[0], sh.pub_b[1], sh.pub_b[2]};
+        uint32_t nxt = sh.pub_next;
+        int jtry = 0;
+        ++c_hits;
+        const double lam2 = lam * lam;
+        for (int r = 0;;) {
+            Stream cs;
+            cs.init(P, sys, sweep, level, cell, tc, r, jtry);
+            cs.next = nxt;
+            double px, py, pz;
+            direction(cs, px, py, pz);
+            const double u_acc = cs.oc();
+            __syncthreads();
+            int n = 0;
+            for (int c0 = 0; c0 < nS; c0 += W) {
+                int i = c0 + tid;
+                bool f = false;
+                int sl = 0;
+                if (i < nS) {
+                    sl = sh.S[i];
+                    double dx = minimg(g, sh.x[sl] - b[0]), dy = minimg(g, sh.y[sl] - b[1]),
+                           dz = minimg(g, sh.z[sl] - b[2]);
+                    double d2 = (dx * dx + dy * dy) + dz * dz;
+                    f = d2 <= lam2 || sl == as;
+                }
+                int before;
+                int tot = block_scan_flag<W>(f, before, sh.redi);
+                if (f && n + before < CAPM) sh.M[n + before] = (int16_t)sl;
+                n += tot;
+            }
+            __syncthreads();
+            if (n > CAPM) {
+                if (tid == 0) atomicAdd(&D.cnt[CNT_OVERFLOW], 1ull);
+                __syncthreads();
+                return true;
+            }
+            const double A = P.A0 * lam / sqrt((double)n);
+            double dmax_l = 0.0;
+            for (int k = tid; k < n; k += W) {
+                const int sl = sh.M[k];
+                double xr0 = minimg(g, sh.x[sl] - b[0]) / lam;
+                double xr1 = minimg(g, sh.y[sl] - b[1]) / lam;
+                double xr2 = minimg(g, sh.z[sl] - b[2]) / lam;
+                double rr = sqrt((xr0 * xr0 + xr1 * xr1) + xr2 * xr2);
+                double f = rr < 1.0 ? A * (1.0 - rr) : 0.0;
+                double w0 = f * (py * xr2 - pz * xr1);
+                double w1 = f * (pz * xr0 - px * xr2);
+                double w2 = f * (px * xr1 - py * xr0);
+                sh.MX[k] = sh.x[sl] + w0;
+                sh.MY[k] = sh.y[sl] + w1;
+                sh.MZ[k] = sh.z[sl] + w2;
+                sh.tag[sl] = (int16_t)k;
+                dmax_l = fmax(dmax_l, sqrt((w0 * w0 + w1 * w1) + w2 * w2));
+            }
+            block_max<W>(dmax_l, sh.red);  // barrier: trial positions and tags visible
+            double acc = 0.0, sens = 0.0;
+            tile_dU<W, CAPH, CAPM>(P, D, s, sh, nH, n, mixed ? 1 : 0, acc, sens, c_viol);
+            const double thr = -P.kT * log(u_acc);
+            double dU = block_sum<W>(acc, sh.red);
+            if (mixed) {
+                double bound = 64.0 * 0x1.0p-23 * block_sum<W>(sens, sh.red) + 1e-12;
+                if (!(isfinite(dU) && fabs(dU - thr) > bound)) {
+                    double a64 = 0.0, s64 = 0.0;
+                    unsigned long long v64 = 0;
+                    tile_dU<W, CAPH, CAPM>(P, D, s, sh, nH, n, 0, a64, s64, v64);
+                    dU = block_sum<W>(a64, sh.red);
+                    if (tid == 0) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
+                }
+            }
+            const bool accept = dU <= thr;
+            if (tid == 0)
+                trace_push(D, 0, sys, sweep, level, cell, tc, r, n, accept ? 1 : 0, sh.id[as] & ID_MASK, dU, thr);
+            ++c_att;
+            c_beads += n;
+            for (int k = tid; k < n; k += W) {
+                const int sl = sh.M[k];
+                if (accept) {
+                    const int32_t j = sh.id[sl] & ID_MASK;
+                    double nx = sh.MX[k], ny = sh.MY[k], nz = sh.MZ[k];
+                    sh.x[sl] = nx;
+                    sh.y[sl] = ny;
+                    sh.z[sl] = nz;
+                    D.x[j] = nx;
+                    D.y[j] = ny;
+                    D.z[j] = nz;
+                    double dd = fmax(fabs(nx - D.xb[j]), fmax(fabs(ny - D.yb[j]), fabs(nz - D.zb[j])));
+                    d_local = fmax(d_local, dd);
+                }
+                sh.tag[sl] = -1;
+            }
+            __syncthreads();
+            if (accept) {
+                ++c_acc;
+                break;
+            }
+            if (++r >= P.retry_cap) {
+                ++c_caps;
+                break;
+            }
+            int found = -1;
+            for (int j0 = 0; j0 < 4096 && found < 0; j0 += W) {
+                int jj = j0 + tid;
+                bool h2 = false;
+                double ex = 0, ey = 0, ez = 0;
+                int a2 = 0;
+                Stream rs;
+                if (jj < 4096) {
+                    rs.init(P, sys, sweep, level, cell, tc, r, jj);
+                    a2 = sh.S[rs.index(nS)];
+                    double vx, vy, vz;
+                    ball(rs, vx, vy, vz);
+                    ex = sh.x[a2] + lam * vx;
+                    ey = sh.y[a2] + lam * vy;
+                    ez = sh.z[a2] + lam * vz;
+                    h2 = cell_of_point(g, ex, ey, ez) == cell;
+                }
+                int fj = block_min_int<W>(h2 ? jj : 0x7FFFFFFF, sh.redi);
+                if (fj != 0x7FFFFFFF) {
+                    if (jj == fj) {
+                        sh.pub_a = a2;
+                        sh.pub_b[0] = ex;
+                        sh.pub_b[1] = ey;
+                        sh.pub_b[2] = ez;
+                        sh.pub_next = rs.next;
+                    }
+                    found = fj;
+                }
+            }
+            __syncthreads();
+            if (found < 0) {
+                c_redraw += 4096;
+                ++c_caps;
+                break;
+            }
+            c_redraw += (unsigned long long)found;
+            as = sh.pub_a;
+            b[0] = sh.pub_b[0];
+            b[1] = sh.pub_b[1];
+            b[2] = sh.pub_b[2];
+            nxt = sh.pub_next;
+            jtry = found;
+            __syncthreads();
+        }
+        t0 = tc + 1;
+    }
+    d_local = block_max<W>(d_local, sh.red);
+    unsigned long long viol_all = (unsigned long long)block_sum<W>((double)c_viol, sh.red);
+    if (tid == 0) {
+        unsigned long long* C = D.cnt + CNT_LEVEL + level * 8;
+        atomicAdd(&C[0], (unsigned long long)K);
+        atomicAdd(&C[1], c_hits);
+        atomicAdd(&C[2], c_att);
+        atomicAdd(&C[3], c_acc);
+        atomicAdd(&C[4], c_caps);
+        atomicAdd(&C[5], c_redraw);
+        atomicAdd(&C[6], c_beads);
+        if (viol_all) atomicAdd(&D.cnt[CNT_VIOL], viol_all);
+        if (c_acc) {
+            atomicAdd(&D.cnt[CNT_ACCEPTED], c_acc);
+            atomicAdd(&D.sys_acc[sys], c_acc);
+        }
+        if (d_local > 0.0) atomic_max_double(&D.drift[sys], d_local);
+        trace_push(D, 1, sys, sweep, level, cell, K, nS, 0, (int)c_hits, 0, 0.0, 0.0);
+    }
+    __syncthreads();
+    return true;
+}
+
+template <int W, int CAPS, int CAPM, int CAPH, int CAPMT>
 __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, int colour, int64_t sweep,
                                              const int32_t* bmap, int nblocks) {
-    __shared__ PhaseShared<W, CAPS, CAPM> sh;
+    __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT> sh;
     if (P.periodic) {
         const int sys = bmap[2 * blockIdx.x], local = bmap[2 * blockIdx.x + 1];
         const SysDesc& s = D.sys[sys];
         const LevelDesc& lv = D.lev[s.lvl_off + level];
         Grid g;
         make_grid(P, D, s, lv, sys, level, sweep, g);
-        process_cell<W, CAPS, CAPM>(P, D, sh, sys, level, colour, local, sweep, g);
+        if (lv.use_global || !process_cell_tile<W, CAPH, CAPMT>(P, D, sh.t, sys, level, colour, local, sweep, g)) {
+            __syncthreads();
+            process_cell<W, CAPS, CAPM>(P, D, sh.g, sys, level, colour, local, sweep, g);
+        }
     } else {
         const SysDesc& s = D.sys[0];
         const LevelDesc& lv = D.lev[s.lvl_off + level];
@@ -961,7 +1441,7 @@ __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, 
                 mz = (g.n[2] - ((colour >> 2) & 1) + 1) / 2;
         int64_t cells = mx * my * mz;
         for (int64_t local = blockIdx.x; local < cells; local += gridDim.x)
-            process_cell<W, CAPS, CAPM>(P, D, sh, 0, level, colour, local, sweep, g);
+            process_cell<W, CAPS, CAPM>(P, D, sh.g, 0, level, colour, local, sweep, g);
     }
 }
 
@@ -969,14 +1449,14 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
                   const int32_t* bmap, int nblocks, hipStream_t st) {
     if (nblocks <= 0) return;
     if (variant == V64)
-        hipLaunchKernelGGL((k_phase<64, 512, 128>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour, sweep, bmap,
-                           nblocks);
+        hipLaunchKernelGGL((k_phase<64, 512, 128, 512, 128>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour,
+                           sweep, bmap, nblocks);
     else if (variant == V256)
-        hipLaunchKernelGGL((k_phase<256, 4096, 1024>), dim3(nblocks), dim3(256), 0, st, P, D, level, colour, sweep,
-                           bmap, nblocks);
+        hipLaunchKernelGGL((k_phase<256, 4096, 1024, 1024, 512>), dim3(nblocks), dim3(256), 0, st, P, D, level,
+                           colour, sweep, bmap, nblocks);
     else
-        hipLaunchKernelGGL((k_phase<1024, 8192, 1024>), dim3(nblocks), dim3(1024), 0, st, P, D, level, colour, sweep,
-                           bmap, nblocks);
+        hipLaunchKernelGGL((k_phase<1024, 8192, 1024, 4096, 768>), dim3(nblocks), dim3(1024), 0, st, P, D, level,
+                           colour, sweep, bmap, nblocks);
 }
 
 // ------------------------------------------------------------------- plane waves
@@ -1163,6 +1643,201 @@ __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t swe
         }
         atomic_max_double(&D.drift[sys], Dg);
     }
+}
+
+// Plane waves of one large system on many workgroups (cooperative launch: all co-resident).
+// Beads are strided over the grid; each test takes two grid barriers (trial positions written;
+// per-workgroup dU partial sums written) and a third after an accepted move. Every workgroup
+// sums the partial sums in the same order, so all take the same decision.
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned g = gen;
+        unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (arrived == nblocks) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    gen = gen + 1u;
+    __syncthreads();
+    __threadfence();
+}
+
+__global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t sweep) {
+    __shared__ double red[4];
+    const int sys = 0;
+    const SysDesc& s = D.sys[sys];
+    const int tid = threadIdx.x;
+    const unsigned G = gridDim.x;
+    const int64_t stride = (int64_t)G * 256;
+    const int64_t g0 = s.b0 + (int64_t)blockIdx.x * 256 + tid;
+    const double L = s.L, invL = s.invL;
+    unsigned gen = __hip_atomic_load(&D.gbar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    Stream cs;
+    cs.init(P, sys, sweep, TAG_PWCOUNT, 0, 0, 0, 0);
+    double mu = (double)s.N * s.PF;
+    int64_t HF = (int64_t)floor(mu);
+    if (cs.co() < mu - (double)HF) HF += 1;
+    double Dg = __longlong_as_double((long long)D.drift[sys]);
+    unsigned long long c_att = 0, c_acc = 0, c_k0 = 0, c_caps = 0, c_beads = 0;
+    const int64_t NN = (int64_t)(D.sys[P.nsys - 1].b1);
+    double* NX = D.pw_new;
+    double* NY = D.pw_new + NN;
+    double* NZ = D.pw_new + 2 * NN;
+    int parity = 0;
+    for (int64_t h = 0; h < HF; ++h) {
+        Stream st;
+        st.init(P, sys, sweep, TAG_PW, 0, h, 0, 0);
+        int l[3];
+        sample_k(P, s, D, st, l);
+        for (int r = 0;;) {
+            const double Phi = 2.0 * kPi * st.co();
+            const double psi = 2.0 * kPi * st.co();
+            const double u_acc = st.oc();
+            const double thr = -P.kT * log(u_acc);
+            if (l[0] == 0 && l[1] == 0 && l[2] == 0) {
+                ++c_k0;
+                ++c_acc;
+                if (blockIdx.x == 0 && tid == 0)
+                    trace_push(D, 2, sys, sweep, -1, h, 0, r, 0, 1, (int)((512u << 20) | (512u << 10) | 512u), 0.0,
+                               thr);
+                break;
+            }
+            double k[3] = {s.ks * (double)l[0], s.ks * (double)l[1], s.ks * (double)l[2]};
+            double kmag = sqrt((k[0] * k[0] + k[1] * k[1]) + k[2] * k[2]);
+            double kh[3] = {k[0] / kmag, k[1] / kmag, k[2] / kmag};
+            int ax = 0;
+            for (int q = 1; q < 3; ++q)
+                if (fabs(kh[q]) < fabs(kh[ax])) ax = q;
+            double ref[3] = {0.0, 0.0, 0.0};
+            ref[ax] = 1.0;
+            double e1[3] = {kh[1] * ref[2] - kh[2] * ref[1], kh[2] * ref[0] - kh[0] * ref[2],
+                            kh[0] * ref[1] - kh[1] * ref[0]};
+            double n1 = sqrt((e1[0] * e1[0] + e1[1] * e1[1]) + e1[2] * e1[2]);
+            for (int q = 0; q < 3; ++q) e1[q] = e1[q] / n1;
+            double e2[3] = {kh[1] * e1[2] - kh[2] * e1[1], kh[2] * e1[0] - kh[0] * e1[2],
+                            kh[0] * e1[1] - kh[1] * e1[0]};
+            double cp = cos(psi), sp = sin(psi);
+            double e[3] = {cp * e1[0] + sp * e2[0], cp * e1[1] + sp * e2[1], cp * e1[2] + sp * e2[2]};
+            const double AF = 2.0 * P.A0 / (kmag * sqrt(5.0 * (double)s.N));
+            for (int64_t j = g0; j < s.b1; j += stride) {
+                double ph = ((k[0] * D.x[j] + k[1] * D.y[j]) + k[2] * D.z[j]) + Phi;
+                double f = AF * cos(ph);
+                NX[j] = D.x[j] + f * e[0];
+                NY[j] = D.y[j] + f * e[1];
+                NZ[j] = D.z[j] + f * e[2];
+            }
+            grid_barrier(D.gbar, G, gen);
+            double acc = 0.0;
+            const double R = P.rc + 2.0 * AF + Dg + 1e-9 * L;
+            for (int64_t j = g0; j < s.b1; j += stride) {
+                double jx = D.x[j], jy = D.y[j], jz = D.z[j];
+                if (P.bond_type != WMC_BOND_NONE && j + 1 < s.b1 && D.bond_next[j]) {
+                    double r2o = pair_r2(P, invL, L, jx, jy, jz, D.x[j + 1], D.y[j + 1], D.z[j + 1]);
+                    double r2n = pair_r2(P, invL, L, NX[j], NY[j], NZ[j], NX[j + 1], NY[j + 1], NZ[j + 1]);
+                    acc += u_bond(P, r2n) - u_bond(P, r2o);
+                }
+                if (P.wca) {
+                    double cx = wrap01(jx, L, invL), cy = wrap01(jy, L, invL), cz = wrap01(jz, L, invL);
+                    int f0[3], cn[3];
+                    fine_range(cx - R, cx + R, s.invg, s.nf, f0[0], cn[0]);
+                    fine_range(cy - R, cy + R, s.invg, s.nf, f0[1], cn[1]);
+                    fine_range(cz - R, cz + R, s.invg, s.nf, f0[2], cn[2]);
+                    for (int qz = 0; qz < cn[2]; ++qz)
+                        for (int qy = 0; qy < cn[1]; ++qy)
+                            for (int qx = 0; qx < cn[0]; ++qx) {
+                                int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
+                                int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
+                                for (int q = D.fstart[fc]; q < D.fstart[fc + 1]; ++q) {
+                                    int32_t m = D.fidx[q];
+                                    if (m <= j) continue;
+                                    double r2o = pair_r2(P, invL, L, jx, jy, jz, D.x[m], D.y[m], D.z[m]);
+                                    double r2n = pair_r2(P, invL, L, NX[j], NY[j], NZ[j], NX[m], NY[m], NZ[m]);
+                                    if (r2o < P.rc2 || r2n < P.rc2) acc += u_pair(P, r2n) - u_pair(P, r2o);
+                                }
+                            }
+                }
+            }
+            double part = block_sum<256>(acc, red);
+            double* partials = D.pw_part + (parity ? G : 0);
+            if (tid == 0) partials[blockIdx.x] = part;
+            grid_barrier(D.gbar, G, gen);
+            double dU = 0.0;
+            for (unsigned b = 0; b < G; ++b) dU += partials[b];
+            parity ^= 1;
+            const bool accept = dU <= thr;
+            ++c_att;
+            c_beads += s.N;
+            if (blockIdx.x == 0 && tid == 0) {
+                int extra = (int)((((uint32_t)(l[0] + 512) & 0x3FFu) << 20) | (((uint32_t)(l[1] + 512) & 0x3FFu) << 10) |
+                                  ((uint32_t)(l[2] + 512) & 0x3FFu));
+                trace_push(D, 2, sys, sweep, -1, h, 0, r, s.N, accept ? 1 : 0, extra, dU, thr);
+            }
+            if (accept) {
+                for (int64_t j = g0; j < s.b1; j += stride) {
+                    D.x[j] = NX[j];
+                    D.y[j] = NY[j];
+                    D.z[j] = NZ[j];
+                }
+                Dg += AF;
+                ++c_acc;
+                grid_barrier(D.gbar, G, gen);
+                break;
+            }
+            if (++r >= P.retry_cap) {
+                ++c_caps;
+                break;
+            }
+            st.init(P, sys, sweep, TAG_PW, 0, h, r, 0);
+            int pi = (int)st.index(6);
+            static const int PERM[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+            int nl[3] = {l[PERM[pi][0]], l[PERM[pi][1]], l[PERM[pi][2]]};
+            for (int q = 0; q < 3; ++q) l[q] = st.co() < 0.5 ? -nl[q] : nl[q];
+        }
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+        unsigned long long* C = D.cnt + CNT_PW;
+        atomicAdd(&C[0], (unsigned long long)HF);
+        atomicAdd(&C[1], c_att);
+        atomicAdd(&C[2], c_acc);
+        atomicAdd(&C[3], c_k0);
+        atomicAdd(&C[4], c_caps);
+        atomicAdd(&C[5], c_beads);
+        if (c_acc) {
+            atomicAdd(&D.cnt[CNT_ACCEPTED], c_acc);
+            atomicAdd(&D.sys_acc[sys], c_acc);
+        }
+        atomic_max_double(&D.drift[sys], Dg);
+    }
+}
+
+int pw_coop_blocks() {
+    static int nb = -1;
+    if (nb < 0) {
+        int dev = 0, per_cu = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pw_coop, 256, 0) != hipSuccess || per_cu < 1)
+            nb = 0;
+        else
+            nb = std::min(per_cu * prop.multiProcessorCount, 1024);
+    }
+    return nb;
+}
+
+bool launch_pw_coop(const DevParams& P, const DevPtrs& D, int64_t sweep, int64_t N, hipStream_t st) {
+    int cap = pw_coop_blocks();
+    if (cap <= 0) return false;
+    int nb = (int)std::min<int64_t>(cap, (N + 255) / 256);
+    DevParams Pc = P;
+    DevPtrs Dc = D;
+    int64_t sw = sweep;
+    void* args[] = {&Pc, &Dc, &sw};
+    return hipLaunchCooperativeKernel((const void*)k_pw_coop, dim3(nb), dim3(256), args, 0, st) == hipSuccess;
 }
 
 void launch_pw(const DevParams& P, const DevPtrs& D, int64_t sweep, int nsys, hipStream_t st) {

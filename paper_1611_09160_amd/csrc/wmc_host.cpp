@@ -226,7 +226,7 @@ struct Plan {
     int64_t N = 0, total_fine = 0, slots = 0, slot_len = 0, pool_cube = 0, pool_shell = 0, n_chains = 0, bmap = 0;
     int nsys = 0, total_levels = 0;
     size_t off_x, off_xb, off_bond, off_sysid, off_tag, off_fcount, off_fstart, off_fidx, off_fcell, off_drift,
-        off_cnt, off_sysacc, off_trace, off_tracen, off_cube, off_shell, off_slotS, off_slotM, off_slotMX, off_pw,
+        off_cnt, off_sysacc, off_fblock, off_pwpart, off_gbar, off_trace, off_tracen, off_cube, off_shell, off_slotS, off_slotM, off_slotMX, off_pw,
         off_igrid, off_sys, off_lev, off_bmap, off_choff, off_rg2;
     size_t bytes = 0;
 };
@@ -259,7 +259,7 @@ static int validate(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int64_t
         if (p->periodic && !(L > 0.0)) return fail("periodic box needs box_L > 0");
         if (p->periodic && lm > 0.5 * L) return fail("lambda_max must not exceed L/2");
     }
-    if (so[nsys] > 0x7FFFFFFF) return fail("too many beads");
+    if (so[nsys] > 0x3FFFFFFF) return fail("too many beads (at most 2^30 - 1)");
     if (!p->periodic && so[nsys] > 8192) return fail("an infinite system is limited to 8192 beads");
     if (co[0] != 0 || co[n_chains] != so[nsys]) return fail("chain_offset must cover all beads");
     int s = 0;
@@ -463,6 +463,7 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
     pl.off_fstart = lay.add((fine + 1) * 4);
     pl.off_fidx = lay.add(N * 4);
     pl.off_fcell = lay.add(N * 4);
+    pl.off_fblock = lay.add((fine / 4096 + 2) * 4);
     pl.off_drift = lay.add(nsys * 8);
     pl.off_cnt = lay.add(CNT_TOTAL * 8);
     pl.off_sysacc = lay.add(nsys * 8);
@@ -475,6 +476,8 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
     pl.off_slotMX = lay.add(slots * slot_len * 3 * 8);
     pl.off_pw = lay.add((p->periodic && p->plane_waves) ? 3 * N * 8 : 8);
     pl.off_igrid = lay.add(8 * 8);
+    pl.off_pwpart = lay.add(2 * 1024 * 8);
+    pl.off_gbar = lay.add(64);
     pl.off_sys = lay.add(nsys * sizeof(SysDesc));
     pl.off_lev = lay.add(lev.size() * sizeof(LevelDesc));
     pl.off_bmap = lay.add(std::max<int64_t>(bm, 1) * 2 * 4);
@@ -587,6 +590,7 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     D.fstart = (int32_t*)(base + pl.off_fstart);
     D.fidx = (int32_t*)(base + pl.off_fidx);
     D.fcell = (int32_t*)(base + pl.off_fcell);
+    D.fblock = (int32_t*)(base + pl.off_fblock);
     D.drift = (unsigned long long*)(base + pl.off_drift);
     D.cnt = (unsigned long long*)(base + pl.off_cnt);
     D.sys_acc = (unsigned long long*)(base + pl.off_sysacc);
@@ -601,6 +605,8 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     D.slot_len = pl.slot_len;
     D.pw_new = (double*)(base + pl.off_pw);
     D.igrid = (double*)(base + pl.off_igrid);
+    D.pw_part = (double*)(base + pl.off_pwpart);
+    D.gbar = (unsigned*)(base + pl.off_gbar);
     D.sys = (const SysDesc*)(base + pl.off_sys);
     D.lev = (const LevelDesc*)(base + pl.off_lev);
     D.total_fine = pl.total_fine;
@@ -734,7 +740,9 @@ extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
                 launch_fine_build(c->P, c->D, c->N, st);
             }
             Timed t(c, 17, st);
-            launch_pw(c->P, c->D, sw, c->nsys, st);
+            // one large system: all workgroups cooperate; otherwise one workgroup per system
+            if (!(c->nsys == 1 && c->N >= 8192 && launch_pw_coop(c->P, c->D, sw, c->N, st)))
+                launch_pw(c->P, c->D, sw, c->nsys, st);
         }
         c->sweep++;
         if (c->ev_pending.size() > 4096) drain_events(c);

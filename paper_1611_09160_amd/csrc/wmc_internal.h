@@ -69,6 +69,7 @@ struct DevPtrs {
     const SysDesc* sys;
     const LevelDesc* lev;
     int32_t *fcount, *fstart, *fidx, *fcell;
+    int32_t* fblock;            // per-chunk sums of the grid scan
     unsigned long long* drift;  // per system, bits of the max drift since the grid build
     unsigned long long* cnt;    // CNT_* counters
     unsigned long long* sys_acc;// accepted chains per system
@@ -82,6 +83,8 @@ struct DevPtrs {
     double* slot_MX;            // global member positions (3 * slot_len per slot)
     int64_t slot_len;
     double* pw_new;             // plane-wave trial positions [3N]
+    double* pw_part;            // per-workgroup dU partial sums, two buffers of 1024
+    unsigned* gbar;             // grid barrier: arrivals, generation
     double* igrid;              // infinite-system grid of the current level: o[3], n[3]
     int64_t total_fine;
 };
@@ -92,6 +95,7 @@ void launch_bbox(const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
 void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
                   const int32_t* bmap, int nblocks, hipStream_t st);
 void launch_pw(const DevParams& P, const DevPtrs& D, int64_t sweep, int nsys, hipStream_t st);
+bool launch_pw_coop(const DevParams& P, const DevPtrs& D, int64_t sweep, int64_t N, hipStream_t st);
 void launch_rg2(const DevPtrs& D, const int64_t* chain_off, int64_t n_chains, double* out, hipStream_t st);
 void launch_cell_ids(const DevParams& P, const DevPtrs& D, int sys, int level, int64_t sweep, int64_t n, int32_t* out,
                      hipStream_t st);
