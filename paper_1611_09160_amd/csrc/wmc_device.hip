@@ -321,6 +321,29 @@ __device__ __forceinline__ int block_scan_flag(bool f, int& before, int* redi) {
     return tot;
 }
 
+constexpr int SCAN_CH = 8;  // consecutive list entries per thread in the chunked scans
+
+// exclusive prefix of a non-negative count over the workgroup in thread order; returns the total
+template <int W>
+__device__ __forceinline__ int block_scan_count(int v, int& before, int* redi) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) redi[wv] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < W / 64; ++i) {
+        if (i < wv) off += redi[i];
+        tot += redi[i];
+    }
+    before = off + x - v;
+    return tot;
+}
+
 __device__ __forceinline__ void atomic_max_double(unsigned long long* p, double v) {
     // non-negative doubles order like their bit patterns
     atomicMax(p, (unsigned long long)__double_as_longlong(v));
@@ -522,6 +545,106 @@ struct PhaseShared {
     uint32_t pub_next;
 };
 
+// energy change of the current test, global-memory form: bonds and WCA pairs with >= 1
+// member, each once. Members Ml[0..n) with trial positions MXl/MYl/MZl (LDS or global) and
+// D.tag set. WCA partners come from the neighbour grid: every bead whose grid-build position
+// lies within R (per axis) of a member's current position, R covering the cut-off, both
+// displacements and the drift since the build. One work item is a (member, y-z row of grid
+// cells) pair; its x range is one or two contiguous runs of the grid's bead list.
+// mode 0: FP64; mode 1: FP32 terms (acc) with their sensitivity (sens).
+template <int W>
+__device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, const int32_t* Ml, const double* MXl,
+                        const double* MYl, const double* MZl, int n, double R, int mode, double& acc, double& sens,
+                        unsigned long long& viol) {
+    const int tid = threadIdx.x;
+    const double L = s.L, invL = s.invL;
+    auto term = [&](int32_t j, double jx, double jy, double jz, double kx, double ky, double kz, int32_t m) {
+        if (m == j) return;
+        const int km = D.tag[m];
+        if (km >= 0 && m < j) return;
+        const double mx = D.x[m], my = D.y[m], mz = D.z[m];
+        const double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my, nz = km >= 0 ? MZl[km] : mz;
+        const double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
+        const double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
+        if (r2o < P.rc2 || r2n < P.rc2) {
+            if (mode) {
+                acc += (double)(u_pair_f(P, (float)r2n) - u_pair_f(P, (float)r2o));
+                sens += sens_pair(P, r2n) + sens_pair(P, r2o);
+            } else {
+                acc += u_pair(P, r2n) - u_pair(P, r2o);
+            }
+        }
+    };
+    if (P.bond_type != WMC_BOND_NONE) {
+        for (int k = tid; k < n; k += W) {
+            const int32_t j = Ml[k];
+            const double jx = D.x[j], jy = D.y[j], jz = D.z[j];
+            const double kx = MXl[k], ky = MYl[k], kz = MZl[k];
+            int32_t part[2] = {-1, -1};
+            if (j + 1 < s.b1 && D.bond_next[j]) part[0] = j + 1;
+            if (j > s.b0 && D.bond_next[j - 1]) part[1] = j - 1;
+            for (int e = 0; e < 2; ++e) {
+                const int32_t m = part[e];
+                if (m < 0) continue;
+                const int km = D.tag[m];
+                if (km >= 0 && m < j) continue;
+                const double mx = D.x[m], my = D.y[m], mz = D.z[m];
+                const double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my, nz = km >= 0 ? MZl[km] : mz;
+                const double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
+                const double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
+                if (r2o > P.r_int * P.r_int) ++viol;
+                if (mode) {
+                    acc += (double)(u_bond_f(P, (float)r2n) - u_bond_f(P, (float)r2o));
+                    sens += sens_bond(P, r2n) + sens_bond(P, r2o);
+                } else {
+                    acc += u_bond(P, r2n) - u_bond(P, r2o);
+                }
+            }
+        }
+    }
+    if (!P.wca) return;
+    if (P.periodic) {
+        const int nf = s.nf;
+        const int NR = min(nf, (int)floor(2.0 * R * s.invg) + 2);
+        const int per = NR * NR;
+        for (int it = tid; it < n * per; it += W) {
+            const int k = it / per, q = it - k * per;
+            const int qy = q % NR, qz = q / NR;
+            const int32_t j = Ml[k];
+            const double jx = D.x[j], jy = D.y[j], jz = D.z[j];
+            int f0y, cny, f0z, cnz;
+            const double cy = wrap01(jy, L, invL), cz = wrap01(jz, L, invL);
+            fine_range(cy - R, cy + R, s.invg, nf, f0y, cny);
+            fine_range(cz - R, cz + R, s.invg, nf, f0z, cnz);
+            if (qy >= cny || qz >= cnz) continue;
+            int f0x, cnx;
+            const double cx = wrap01(jx, L, invL);
+            fine_range(cx - R, cx + R, s.invg, nf, f0x, cnx);
+            const int fy = (f0y + qy) % nf, fz = (f0z + qz) % nf;
+            const int64_t row = s.fine_off + (int64_t)nf * (fy + (int64_t)nf * fz);
+            const double kx = MXl[k], ky = MYl[k], kz = MZl[k];
+            const int xa = f0x, xe = min(f0x + cnx, nf);
+            for (int q2 = D.fstart[row + xa], q3 = D.fstart[row + xe]; q2 < q3; ++q2)
+                term(j, jx, jy, jz, kx, ky, kz, D.fidx[q2]);
+            if (f0x + cnx > nf)
+                for (int q2 = D.fstart[row], q3 = D.fstart[row + (f0x + cnx - nf)]; q2 < q3; ++q2)
+                    term(j, jx, jy, jz, kx, ky, kz, D.fidx[q2]);
+        }
+    } else {
+        // infinite system (at most 8192 beads): items are (member, 64-bead block)
+        const int64_t nb = s.b1 - s.b0;
+        const int nblk = (int)((nb + 63) / 64);
+        for (int it = tid; it < n * nblk; it += W) {
+            const int k = it / nblk, c = it - k * nblk;
+            const int32_t j = Ml[k];
+            const double jx = D.x[j], jy = D.y[j], jz = D.z[j];
+            const double kx = MXl[k], ky = MYl[k], kz = MZl[k];
+            const int64_t m0 = s.b0 + 64 * (int64_t)c, m1 = min(s.b1, m0 + 64);
+            for (int64_t m = m0; m < m1; ++m) term(j, jx, jy, jz, kx, ky, kz, (int32_t)m);
+        }
+    }
+}
+
 template <int W, int CAPS, int CAPM>
 __device__ __attribute__((noinline)) void process_cell(const DevParams& P, const DevPtrs& D,
                                                        PhaseShared<W, CAPS, CAPM>& sh, int sys,
@@ -557,17 +680,26 @@ __device__ __attribute__((noinline)) void process_cell(const DevParams& P, const
         nS = s.N;
     } else if (glob || !P.periodic) {
         // bead-order scan of the system, compacted in order
+        // each thread tests SCAN_CH consecutive beads (independent loads in flight), then one
+        // workgroup scan places its hits in bead order
         int32_t* dst = glob ? Sg : sh.S;
         int base = 0;
-        for (int64_t c0 = s.b0; c0 < s.b1; c0 += W) {
-            int64_t j = c0 + tid;
-            bool f = false;
-            if (j < s.b1) f = dist2_cell(g, ic, D.x[j], D.y[j], D.z[j]) <= hi2;
+        for (int64_t c0 = s.b0; c0 < s.b1; c0 += (int64_t)W * SCAN_CH) {
+            const int64_t j0 = c0 + (int64_t)tid * SCAN_CH;
+            uint32_t mask = 0;
+#pragma unroll
+            for (int u = 0; u < SCAN_CH; ++u) {
+                const int64_t j = j0 + u;
+                if (j < s.b1 && dist2_cell(g, ic, D.x[j], D.y[j], D.z[j]) <= hi2) mask |= 1u << u;
+            }
             int before;
-            int tot = block_scan_flag<W>(f, before, sh.redi);
-            if (f) {
-                int idx = base + before;
-                if (glob || idx < CAPS) dst[idx] = (int32_t)j;
+            const int tot = block_scan_count<W>(__popc(mask), before, sh.redi);
+            int idx = base + before;
+            for (int u = 0; u < SCAN_CH; ++u) {
+                if ((mask >> u) & 1u) {
+                    if (glob || idx < CAPS) dst[idx] = (int32_t)(j0 + u);
+                    ++idx;
+                }
             }
             base += tot;
         }
@@ -699,33 +831,47 @@ __device__ __attribute__((noinline)) void process_cell(const DevParams& P, const
             direction(cs, px, py, pz);
             const double u_acc = cs.oc();
             __syncthreads();
-            // members: reach-list beads within lambda of b, plus the anchor, in list order
-            int32_t* Ml = glob ? Mg : sh.M;
-            double *MXl = glob ? MXg : sh.MX, *MYl = glob ? MXg + D.slot_len : sh.MY,
-                   *MZl = glob ? MXg + 2 * D.slot_len : sh.MZ;
+            // members: reach-list beads within lambda of b, plus the anchor, in list order; kept
+            // in LDS when they fit, and also in the cell's global slot on global-list levels
             int n = 0;
-            for (int c0 = 0; c0 < nS; c0 += W) {
-                int i = c0 + tid;
-                bool f = false;
-                int32_t j = 0;
-                if (i < nS) {
-                    j = Sat(i);
-                    double dx = minimg(g, D.x[j] - b[0]), dy = minimg(g, D.y[j] - b[1]), dz = minimg(g, D.z[j] - b[2]);
-                    double d2 = (dx * dx + dy * dy) + dz * dz;
-                    f = d2 <= lam2 || j == a;
+            for (int c0 = 0; c0 < nS; c0 += W * SCAN_CH) {
+                const int i0 = c0 + tid * SCAN_CH;
+                uint32_t mask = 0;
+#pragma unroll
+                for (int u = 0; u < SCAN_CH; ++u) {
+                    const int i = i0 + u;
+                    if (i < nS) {
+                        const int32_t j = Sat(i);
+                        double dx = minimg(g, D.x[j] - b[0]), dy = minimg(g, D.y[j] - b[1]),
+                               dz = minimg(g, D.z[j] - b[2]);
+                        double d2 = (dx * dx + dy * dy) + dz * dz;
+                        if (d2 <= lam2 || j == a) mask |= 1u << u;
+                    }
                 }
                 int before;
-                int tot = block_scan_flag<W>(f, before, sh.redi);
-                if (f && (glob || n + before < CAPM)) Ml[n + before] = j;
+                const int tot = block_scan_count<W>(__popc(mask), before, sh.redi);
+                int idx = n + before;
+                for (int u = 0; u < SCAN_CH; ++u) {
+                    if ((mask >> u) & 1u) {
+                        const int32_t j = Sat(i0 + u);
+                        if (idx < CAPM) sh.M[idx] = j;
+                        if (glob) Mg[idx] = j;
+                        ++idx;
+                    }
+                }
                 n += tot;
             }
             // members written by lanes of other waves must land before any lane reads them
             __syncthreads();
-            if (!glob && n > CAPM) {
+            const bool inL = n <= CAPM;
+            if (!inL && !glob) {
                 if (tid == 0) atomicAdd(&D.cnt[CNT_OVERFLOW], 1ull);
                 __syncthreads();
                 return;
             }
+            const int32_t* Ml = inL ? sh.M : Mg;
+            double *MXl = inL ? sh.MX : MXg, *MYl = inL ? sh.MY : MXg + D.slot_len,
+                   *MZl = inL ? sh.MZ : MXg + 2 * D.slot_len;
             const double A = P.A0 * lam / sqrt((double)n);
             double dmax_l = 0.0;
             for (int k = tid; k < n; k += W) {
@@ -745,141 +891,25 @@ __device__ __attribute__((noinline)) void process_cell(const DevParams& P, const
                 dmax_l = fmax(dmax_l, sqrt((w0 * w0 + w1 * w1) + w2 * w2));
             }
             const double dmax = block_max<W>(dmax_l, sh.red);  // includes a barrier: tags visible
-            const double D_eff = fmax(Dg, d_local);
-            // energy change over bonds and WCA pairs touching the members, each once
-            double acc = 0.0, accf = 0.0, sens = 0.0;
-            for (int k = tid; k < n; k += W) {
-                int32_t j = Ml[k];
-                double jx = D.x[j], jy = D.y[j], jz = D.z[j];
-                double kx = MXl[k], ky = MYl[k], kz = MZl[k];
-                if (P.bond_type != WMC_BOND_NONE) {
-                    int32_t part[2] = {-1, -1};
-                    if (j + 1 < s.b1 && D.bond_next[j]) part[0] = j + 1;
-                    if (j > s.b0 && D.bond_next[j - 1]) part[1] = j - 1;
-                    for (int e = 0; e < 2; ++e) {
-                        int32_t m = part[e];
-                        if (m < 0) continue;
-                        int km = D.tag[m];
-                        if (km >= 0 && m < j) continue;
-                        double mx = D.x[m], my = D.y[m], mz = D.z[m];
-                        double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my, nz = km >= 0 ? MZl[km] : mz;
-                        double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
-                        double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
-                        if (r2o > P.r_int * P.r_int) ++c_viol;
-                        if (mixed) {
-                            accf += (double)(u_bond_f(P, (float)r2n) - u_bond_f(P, (float)r2o));
-                            sens += sens_bond(P, r2n) + sens_bond(P, r2o);
-                        } else {
-                            acc += u_bond(P, r2n) - u_bond(P, r2o);
-                        }
-                    }
-                }
-                if (P.wca) {
-                    auto pair_term = [&](int32_t m) {
-                        if (m == j) return;
-                        int km = D.tag[m];
-                        if (km >= 0 && m < j) return;
-                        double mx = D.x[m], my = D.y[m], mz = D.z[m];
-                        double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my, nz = km >= 0 ? MZl[km] : mz;
-                        double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
-                        double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
-                        if (r2o < P.rc2 || r2n < P.rc2) {
-                            if (mixed) {
-                                accf += (double)(u_pair_f(P, (float)r2n) - u_pair_f(P, (float)r2o));
-                                sens += sens_pair(P, r2n) + sens_pair(P, r2o);
-                            } else {
-                                acc += u_pair(P, r2n) - u_pair(P, r2o);
-                            }
-                        }
-                    };
-                    if (P.periodic) {
-                        double R = P.rc + 2.0 * dmax + D_eff + 1e-9 * L;
-                        double cx = wrap01(jx, L, invL), cy = wrap01(jy, L, invL), cz = wrap01(jz, L, invL);
-                        int f0[3], cn[3];
-                        fine_range(cx - R, cx + R, s.invg, s.nf, f0[0], cn[0]);
-                        fine_range(cy - R, cy + R, s.invg, s.nf, f0[1], cn[1]);
-                        fine_range(cz - R, cz + R, s.invg, s.nf, f0[2], cn[2]);
-                        for (int qz = 0; qz < cn[2]; ++qz)
-                            for (int qy = 0; qy < cn[1]; ++qy)
-                                for (int qx = 0; qx < cn[0]; ++qx) {
-                                    int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
-                                    int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
-                                    for (int q = D.fstart[fc]; q < D.fstart[fc + 1]; ++q) pair_term(D.fidx[q]);
-                                }
-                    } else {
-                        for (int64_t m = s.b0; m < s.b1; ++m) pair_term((int32_t)m);
-                    }
-                }
-            }
+            const double Rq = P.rc + 2.0 * dmax + fmax(Dg, d_local) + 1e-9 * L;
             double dU;
             const double thr = -P.kT * log(u_acc);
-            if (mixed) {
-                // FP32 terms summed in FP64; each FP32 term is within ~4 ulp of r2 and of the
-                // energy: re-evaluate in FP64 when the decision is within the bound
-                double dU32 = block_sum<W>(accf, sh.red);
-                double bound = 64.0 * 0x1.0p-23 * block_sum<W>(sens, sh.red) + 1e-12;
-                if (isfinite(dU32) && fabs(dU32 - thr) > bound) {
-                    dU = dU32;
-                } else {
-                    // FP64 re-evaluation, same loops
-                    double acc64 = 0.0;
-                    for (int k = tid; k < n; k += W) {
-                        int32_t j = Ml[k];
-                        double jx = D.x[j], jy = D.y[j], jz = D.z[j];
-                        double kx = MXl[k], ky = MYl[k], kz = MZl[k];
-                        if (P.bond_type != WMC_BOND_NONE) {
-                            int32_t part[2] = {-1, -1};
-                            if (j + 1 < s.b1 && D.bond_next[j]) part[0] = j + 1;
-                            if (j > s.b0 && D.bond_next[j - 1]) part[1] = j - 1;
-                            for (int e = 0; e < 2; ++e) {
-                                int32_t m = part[e];
-                                if (m < 0) continue;
-                                int km = D.tag[m];
-                                if (km >= 0 && m < j) continue;
-                                double mx = D.x[m], my = D.y[m], mz = D.z[m];
-                                double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my,
-                                       nz = km >= 0 ? MZl[km] : mz;
-                                acc64 += u_bond(P, pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz)) -
-                                         u_bond(P, pair_r2(P, invL, L, jx, jy, jz, mx, my, mz));
-                            }
-                        }
-                        if (P.wca) {
-                            auto pair64 = [&](int32_t m) {
-                                if (m == j) return;
-                                int km = D.tag[m];
-                                if (km >= 0 && m < j) return;
-                                double mx = D.x[m], my = D.y[m], mz = D.z[m];
-                                double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my,
-                                       nz = km >= 0 ? MZl[km] : mz;
-                                double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
-                                double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
-                                if (r2o < P.rc2 || r2n < P.rc2) acc64 += u_pair(P, r2n) - u_pair(P, r2o);
-                            };
-                            if (P.periodic) {
-                                double R = P.rc + 2.0 * dmax + D_eff + 1e-9 * L;
-                                double cx = wrap01(jx, L, invL), cy = wrap01(jy, L, invL), cz = wrap01(jz, L, invL);
-                                int f0[3], cn[3];
-                                fine_range(cx - R, cx + R, s.invg, s.nf, f0[0], cn[0]);
-                                fine_range(cy - R, cy + R, s.invg, s.nf, f0[1], cn[1]);
-                                fine_range(cz - R, cz + R, s.invg, s.nf, f0[2], cn[2]);
-                                for (int qz = 0; qz < cn[2]; ++qz)
-                                    for (int qy = 0; qy < cn[1]; ++qy)
-                                        for (int qx = 0; qx < cn[0]; ++qx) {
-                                            int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf,
-                                                fz = (f0[2] + qz) % s.nf;
-                                            int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
-                                            for (int q = D.fstart[fc]; q < D.fstart[fc + 1]; ++q) pair64(D.fidx[q]);
-                                        }
-                            } else {
-                                for (int64_t m = s.b0; m < s.b1; ++m) pair64((int32_t)m);
-                            }
-                        }
-                    }
-                    dU = block_sum<W>(acc64, sh.red);
-                    if (tid == 0) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
-                }
-            } else {
+            {
+                double acc = 0.0, sens = 0.0;
+                glob_dU<W>(P, D, s, Ml, MXl, MYl, MZl, n, Rq, mixed ? 1 : 0, acc, sens, c_viol);
                 dU = block_sum<W>(acc, sh.red);
+                if (mixed) {
+                    // FP32 terms summed in FP64; each FP32 term is within ~4 ulp of r2 and of the
+                    // energy: re-evaluate in FP64 when the decision is within the bound
+                    const double bound = 64.0 * 0x1.0p-23 * block_sum<W>(sens, sh.red) + 1e-12;
+                    if (!(isfinite(dU) && fabs(dU - thr) > bound)) {
+                        double a64 = 0.0, s64 = 0.0;
+                        unsigned long long v64 = 0;
+                        glob_dU<W>(P, D, s, Ml, MXl, MYl, MZl, n, Rq, 0, a64, s64, v64);
+                        dU = block_sum<W>(a64, sh.red);
+                        if (tid == 0) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
+                    }
+                }
             }
             const bool accept = dU <= thr;
             if (tid == 0) trace_push(D, 0, sys, sweep, level, cell, tc, r, n, accept ? 1 : 0, a, dU, thr);
@@ -985,14 +1015,17 @@ constexpr int32_t ID_MASK = 0x3FFFFFFF;
 constexpr int32_t ID_NEXT = 0x40000000;  // bonded to bead id + 1
 constexpr uint32_t ID_PREV = 0x80000000u;  // bonded to bead id - 1
 
-template <int W, int CAPH, int CAPM>
+template <int W, int CAPH, int CAPM, int NCD>
 struct TileShared {
     double x[CAPH], y[CAPH], z[CAPH];
     int32_t id[CAPH];
+    int32_t kc[CAPH];           // tile cell list: (tile cell << 16) | slot, ascending
     int16_t tag[CAPH];
     int16_t S[CAPH];
-    int16_t M[CAPM];
-    double MX[CAPM], MY[CAPM], MZ[CAPM];
+    int16_t cst[NCD * NCD * NCD + 1];  // first kc position of each tile cell
+    int16_t M[CAPH];                   // member slots of the current test
+    // trial positions of the first CAPM members (later ones are recomputed when needed)
+    double MX[CAPM > 0 ? CAPM : 1], MY[CAPM > 0 ? CAPM : 1], MZ[CAPM > 0 ? CAPM : 1];
     double red[W / 64 > 0 ? W / 64 : 1];
     int redi[W / 64 > 0 ? W / 64 : 1];
     int count;
@@ -1002,15 +1035,114 @@ struct TileShared {
     uint32_t pub_next;
 };
 
-template <int W, int CAPS, int CAPM, int CAPH, int CAPMT>
+template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD>
 union PhaseLDS {
     PhaseShared<W, CAPS, CAPM> g;
-    TileShared<W, CAPH, CAPMT> t;
+    TileShared<W, CAPH, CAPMT, NCD> t;
 };
 
+// Geometry of a tile's cell list: a cube of side 2 He centred on the cell, nc^3 cells of side f.
+// A bead's tile coordinate is its minimum-image offset from the centre plus He.
+struct TileGeo {
+    double c[3];
+    double He, f, invf;
+    int nc;
+};
+
+__device__ __forceinline__ int tile_clamp(const TileGeo& tg, double u) {
+    double q = floor(u * tg.invf);
+    q = fmin(fmax(q, 0.0), (double)(tg.nc - 1));
+    return (int)q;
+}
+
+__device__ __forceinline__ double tile_u(const Grid& g, const TileGeo& tg, double v, int a) {
+    return minimg(g, v - tg.c[a]) + tg.He;
+}
+
+// the wavelet of the current test: centre, polarisation, radius and amplitude
+struct WaveDesc {
+    double b[3], p[3], lam, A;
+};
+
+// displacement A w((r - b) / lambda, p) of a bead at (x, y, z), Eq. "Tapered wavelet"
+__device__ __forceinline__ void wavelet_disp(const Grid& g, const WaveDesc& wv, double x, double y, double z,
+                                             double& w0, double& w1, double& w2) {
+    const double xr0 = minimg(g, x - wv.b[0]) / wv.lam;
+    const double xr1 = minimg(g, y - wv.b[1]) / wv.lam;
+    const double xr2 = minimg(g, z - wv.b[2]) / wv.lam;
+    const double rr = sqrt((xr0 * xr0 + xr1 * xr1) + xr2 * xr2);
+    const double f = rr < 1.0 ? wv.A * (1.0 - rr) : 0.0;
+    w0 = f * (wv.p[1] * xr2 - wv.p[2] * xr1);
+    w1 = f * (wv.p[2] * xr0 - wv.p[0] * xr2);
+    w2 = f * (wv.p[0] * xr1 - wv.p[1] * xr0);
+}
+
+// trial position of member k (tile slot sl)
+template <int W, int CAPH, int CAPM, int NCD>
+__device__ __forceinline__ void member_new(const TileShared<W, CAPH, CAPM, NCD>& sh, const Grid& g,
+                                           const WaveDesc& wv, int k, int sl, double& nx, double& ny, double& nz) {
+    if (CAPM > 0 && k < CAPM) {
+        nx = sh.MX[k];
+        ny = sh.MY[k];
+        nz = sh.MZ[k];
+    } else {
+        double w0, w1, w2;
+        wavelet_disp(g, wv, sh.x[sl], sh.y[sl], sh.z[sl], w0, w1, w2);
+        nx = sh.x[sl] + w0;
+        ny = sh.y[sl] + w1;
+        nz = sh.z[sl] + w2;
+    }
+}
+
+template <int W>
+__device__ void bitonic_sort(int32_t* a, int np2) {
+    for (int k = 2; k <= np2; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = threadIdx.x; i < np2; i += W) {
+                int l = i ^ jj;
+                if (l > i) {
+                    int32_t va = a[i], vb = a[l];
+                    bool up = (i & k) == 0;
+                    if ((va > vb) == up) {
+                        a[i] = vb;
+                        a[l] = va;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// (re)build the tile cell list from the current tile positions: keys, sort, cell starts
+template <int W, int CAPH, int CAPM, int NCD>
+__device__ void tile_index(TileShared<W, CAPH, CAPM, NCD>& sh, int nH, const Grid& g, const TileGeo& tg) {
+    int np2 = 1;
+    while (np2 < nH) np2 <<= 1;
+    for (int i = threadIdx.x; i < np2; i += W) {
+        int32_t v = 0x7FFFFFFF;
+        if (i < nH) {
+            const int cx = tile_clamp(tg, tile_u(g, tg, sh.x[i], 0));
+            const int cy = tile_clamp(tg, tile_u(g, tg, sh.y[i], 1));
+            const int cz = tile_clamp(tg, tile_u(g, tg, sh.z[i], 2));
+            v = ((cx + tg.nc * (cy + tg.nc * cz)) << 16) | i;
+        }
+        sh.kc[i] = v;
+    }
+    __syncthreads();
+    bitonic_sort<W>(sh.kc, np2);
+    const int NC = tg.nc * tg.nc * tg.nc;
+    for (int p = threadIdx.x; p <= nH; p += W) {
+        const int kp = p < nH ? (sh.kc[p] >> 16) : NC;
+        const int kq = p > 0 ? (sh.kc[p - 1] >> 16) : -1;
+        for (int c = kq + 1; c <= kp; ++c) sh.cst[c] = (int16_t)p;
+    }
+    __syncthreads();
+}
+
 // slot of bead j in the sorted tile, or -1
-template <int W, int CAPH, int CAPM>
-__device__ __forceinline__ int tile_find(const TileShared<W, CAPH, CAPM>& sh, int nH, int32_t j) {
+template <int W, int CAPH, int CAPM, int NCD>
+__device__ __forceinline__ int tile_find(const TileShared<W, CAPH, CAPM, NCD>& sh, int nH, int32_t j) {
     int lo = 0, hi = nH - 1;
     while (lo <= hi) {
         int mid = (lo + hi) >> 1;
@@ -1037,10 +1169,16 @@ __device__ __forceinline__ void cell_coords(const DevParams& P, const LevelDesc&
 }
 
 // energy change of the current test over the tile: bonds and WCA pairs with >= 1 member, each
-// once; members are tile slots sh.M[0..n) with trial positions sh.MX/MY/MZ and tags set.
+// once; members are tile slots sh.M[0..n) with tags set (trial positions via member_new).
+// WCA partners come from the tile cell list: every bead within R (tile coordinates, per
+// axis) of a member's current position, R covering the cut-off, both displacements and the
+// drift since the list was built. One work item is a (member, y-z row of cells) pair whose
+// x range is contiguous in the list.
 // mode 0: FP64; mode 1: FP32 terms (acc) with their sensitivity (sens).
-template <int W, int CAPH, int CAPM>
-__device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, const TileShared<W, CAPH, CAPM>& sh,
+template <int W, int CAPH, int CAPM, int NCD>
+__device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
+                        const TileShared<W, CAPH, CAPM, NCD>& sh, const Grid& g, const TileGeo& tg,
+                        const WaveDesc& wv, double R,
                         int nH, int n, int mode, double& acc, double& sens, unsigned long long& viol) {
     const int tid = threadIdx.x;
     const double L = s.L, invL = s.invL;
@@ -1050,7 +1188,8 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
             const int32_t raw = sh.id[sl];
             const int32_t j = raw & ID_MASK;
             const double jx = sh.x[sl], jy = sh.y[sl], jz = sh.z[sl];
-            const double kx = sh.MX[k], ky = sh.MY[k], kz = sh.MZ[k];
+            double kx, ky, kz;
+            member_new(sh, g, wv, k, sl, kx, ky, kz);
             for (int e = 0; e < 2; ++e) {
                 bool bonded = e == 0 ? (raw & ID_NEXT) != 0 : ((uint32_t)raw & ID_PREV) != 0;
                 if (!bonded) continue;
@@ -1064,9 +1203,10 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
                     mx = sh.x[ps];
                     my = sh.y[ps];
                     mz = sh.z[ps];
-                    nx = tm >= 0 ? sh.MX[tm] : mx;
-                    ny = tm >= 0 ? sh.MY[tm] : my;
-                    nz = tm >= 0 ? sh.MZ[tm] : mz;
+                    nx = mx;
+                    ny = my;
+                    nz = mz;
+                    if (tm >= 0) member_new(sh, g, wv, tm, ps, nx, ny, nz);
                 } else {
                     // partner beyond the halo: only a bond longer than r_int can do this
                     mx = nx = D.x[m];
@@ -1086,18 +1226,32 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
         }
     }
     if (P.wca) {
-        for (int k = 0; k < n; ++k) {
+        const int NR = min(tg.nc, (int)floor(2.0 * R * tg.invf) + 2);
+        const int per = NR * NR;
+        const int items = n * per;
+        for (int it = tid; it < items; it += W) {
+            const int k = it / per, q = it - k * per;
+            const int qy = q % NR, qz = q / NR;
             const int sl = sh.M[k];
             const double jx = sh.x[sl], jy = sh.y[sl], jz = sh.z[sl];
-            const double kx = sh.MX[k], ky = sh.MY[k], kz = sh.MZ[k];
-            for (int m = tid; m < nH; m += W) {
+            const double uy = tile_u(g, tg, jy, 1), uz = tile_u(g, tg, jz, 2);
+            const int cy = tile_clamp(tg, uy - R) + qy, cz = tile_clamp(tg, uz - R) + qz;
+            if (cy > tile_clamp(tg, uy + R) || cz > tile_clamp(tg, uz + R)) continue;
+            const double ux = tile_u(g, tg, jx, 0);
+            const int row = tg.nc * (cy + tg.nc * cz);
+            const int p0 = sh.cst[row + tile_clamp(tg, ux - R)], p1 = sh.cst[row + tile_clamp(tg, ux + R) + 1];
+            double kx, ky, kz;
+            member_new(sh, g, wv, k, sl, kx, ky, kz);
+            for (int pp = p0; pp < p1; ++pp) {
+                const int m = sh.kc[pp] & 0xFFFF;
                 if (m == sl) continue;
                 const int tm = sh.tag[m];
                 if (tm >= 0 && m < sl) continue;
                 const double mx = sh.x[m], my = sh.y[m], mz = sh.z[m];
                 double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
-                double r2n = tm >= 0 ? pair_r2(P, invL, L, kx, ky, kz, sh.MX[tm], sh.MY[tm], sh.MZ[tm])
-                                     : pair_r2(P, invL, L, kx, ky, kz, mx, my, mz);
+                double nx = mx, ny = my, nz = mz;
+                if (tm >= 0) member_new(sh, g, wv, tm, m, nx, ny, nz);
+                double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
                 if (r2o < P.rc2 || r2n < P.rc2) {
                     if (mode) {
                         acc += (double)(u_pair_f(P, (float)r2n) - u_pair_f(P, (float)r2o));
@@ -1113,8 +1267,8 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
 
 // returns false (before any move) when the halo does not fit; the caller then uses the
 // global path for this cell
-template <int W, int CAPH, int CAPM>
-__device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShared<W, CAPH, CAPM>& sh, int sys,
+template <int W, int CAPH, int CAPM, int NCD>
+__device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShared<W, CAPH, CAPM, NCD>& sh, int sys,
                                   int level, int colour, int64_t local, int64_t sweep, const Grid& g) {
     const SysDesc& s = D.sys[sys];
     const LevelDesc& lv = D.lev[s.lvl_off + level];
@@ -1126,6 +1280,16 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
     const double rh = lv.hi + lv.r_int, rh2 = rh * rh;
     const double Dg = __longlong_as_double((long long)D.drift[sys]);
     const double L = s.L, invL = s.invL;
+
+    // tile cell list geometry; relative tile coordinates identify pairs only while the tile
+    // (plus a cut-off and a margin for moves) is shorter than the box
+    TileGeo tg;
+    for (int a = 0; a < 3; ++a) tg.c[a] = g.o[a] + ((double)ic[a] + 0.5) * g.h;
+    tg.He = 0.5 * g.h + rh + Dg + 1e-9 * L;
+    if (2.0 * tg.He + P.rc + 2.0 >= L) return false;
+    tg.nc = max(1, min(NCD, (int)floor(2.0 * tg.He / (fmax(P.rc, 0.5) + 0.5))));
+    tg.f = 2.0 * tg.He / (double)tg.nc;
+    tg.invf = 1.0 / tg.f;
 
     // ---- 1. halo gather from the neighbour grid
     if (tid == 0) sh.count = 0;
@@ -1160,22 +1324,7 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
         while (np2 < nH) np2 <<= 1;
         for (int i = nH + tid; i < np2; i += W) sh.id[i] = 0x7FFFFFFF;
         __syncthreads();
-        for (int k = 2; k <= np2; k <<= 1) {
-            for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                for (int i = tid; i < np2; i += W) {
-                    int l = i ^ jj;
-                    if (l > i) {
-                        int32_t a = sh.id[i], b = sh.id[l];
-                        bool up = (i & k) == 0;
-                        if ((a > b) == up) {
-                            sh.id[i] = b;
-                            sh.id[l] = a;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
+        bitonic_sort<W>(sh.id, np2);
     }
     int nS = 0;
     for (int c0 = 0; c0 < nH; c0 += W) {
@@ -1200,6 +1349,8 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
         nS += tot;
     }
     __syncthreads();
+    tile_index<W, CAPH, CAPM, NCD>(sh, nH, g, tg);
+    double E = 0.0;  // bound on any tile bead's displacement since the cell list was built
 
     // ---- 3. trials and chains (as the global path, on LDS)
     double mu = (lv.T * (double)nS) / (double)s.N;
@@ -1277,36 +1428,36 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
                 }
                 int before;
                 int tot = block_scan_flag<W>(f, before, sh.redi);
-                if (f && n + before < CAPM) sh.M[n + before] = (int16_t)sl;
+                if (f) sh.M[n + before] = (int16_t)sl;
                 n += tot;
             }
             __syncthreads();
-            if (n > CAPM) {
-                if (tid == 0) atomicAdd(&D.cnt[CNT_OVERFLOW], 1ull);
-                __syncthreads();
-                return true;
-            }
-            const double A = P.A0 * lam / sqrt((double)n);
+            WaveDesc wv;
+            wv.b[0] = b[0];
+            wv.b[1] = b[1];
+            wv.b[2] = b[2];
+            wv.p[0] = px;
+            wv.p[1] = py;
+            wv.p[2] = pz;
+            wv.lam = lam;
+            wv.A = P.A0 * lam / sqrt((double)n);
             double dmax_l = 0.0;
             for (int k = tid; k < n; k += W) {
                 const int sl = sh.M[k];
-                double xr0 = minimg(g, sh.x[sl] - b[0]) / lam;
-                double xr1 = minimg(g, sh.y[sl] - b[1]) / lam;
-                double xr2 = minimg(g, sh.z[sl] - b[2]) / lam;
-                double rr = sqrt((xr0 * xr0 + xr1 * xr1) + xr2 * xr2);
-                double f = rr < 1.0 ? A * (1.0 - rr) : 0.0;
-                double w0 = f * (py * xr2 - pz * xr1);
-                double w1 = f * (pz * xr0 - px * xr2);
-                double w2 = f * (px * xr1 - py * xr0);
-                sh.MX[k] = sh.x[sl] + w0;
-                sh.MY[k] = sh.y[sl] + w1;
-                sh.MZ[k] = sh.z[sl] + w2;
+                double w0, w1, w2;
+                wavelet_disp(g, wv, sh.x[sl], sh.y[sl], sh.z[sl], w0, w1, w2);
+                if (CAPM > 0 && k < CAPM) {
+                    sh.MX[k] = sh.x[sl] + w0;
+                    sh.MY[k] = sh.y[sl] + w1;
+                    sh.MZ[k] = sh.z[sl] + w2;
+                }
                 sh.tag[sl] = (int16_t)k;
                 dmax_l = fmax(dmax_l, sqrt((w0 * w0 + w1 * w1) + w2 * w2));
             }
-            block_max<W>(dmax_l, sh.red);  // barrier: trial positions and tags visible
+            const double dmax = block_max<W>(dmax_l, sh.red);  // barrier: trial positions and tags visible
+            const double Rq = P.rc + 2.0 * dmax + E + 1e-9 * L;
             double acc = 0.0, sens = 0.0;
-            tile_dU<W, CAPH, CAPM>(P, D, s, sh, nH, n, mixed ? 1 : 0, acc, sens, c_viol);
+            tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, mixed ? 1 : 0, acc, sens, c_viol);
             const double thr = -P.kT * log(u_acc);
             double dU = block_sum<W>(acc, sh.red);
             if (mixed) {
@@ -1314,7 +1465,7 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
                 if (!(isfinite(dU) && fabs(dU - thr) > bound)) {
                     double a64 = 0.0, s64 = 0.0;
                     unsigned long long v64 = 0;
-                    tile_dU<W, CAPH, CAPM>(P, D, s, sh, nH, n, 0, a64, s64, v64);
+                    tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, 0, a64, s64, v64);
                     dU = block_sum<W>(a64, sh.red);
                     if (tid == 0) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
                 }
@@ -1328,7 +1479,8 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
                 const int sl = sh.M[k];
                 if (accept) {
                     const int32_t j = sh.id[sl] & ID_MASK;
-                    double nx = sh.MX[k], ny = sh.MY[k], nz = sh.MZ[k];
+                    double nx, ny, nz;
+                    member_new(sh, g, wv, k, sl, nx, ny, nz);
                     sh.x[sl] = nx;
                     sh.y[sl] = ny;
                     sh.z[sl] = nz;
@@ -1343,6 +1495,11 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
             __syncthreads();
             if (accept) {
                 ++c_acc;
+                E += dmax;
+                if (E > 0.5 * tg.f) {
+                    tile_index<W, CAPH, CAPM, NCD>(sh, nH, g, tg);
+                    E = 0.0;
+                }
                 break;
             }
             if (++r >= P.retry_cap) {
@@ -1418,17 +1575,17 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
     return true;
 }
 
-template <int W, int CAPS, int CAPM, int CAPH, int CAPMT>
+template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD>
 __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, int colour, int64_t sweep,
                                              const int32_t* bmap, int nblocks) {
-    __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT> sh;
+    __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD> sh;
     if (P.periodic) {
         const int sys = bmap[2 * blockIdx.x], local = bmap[2 * blockIdx.x + 1];
         const SysDesc& s = D.sys[sys];
         const LevelDesc& lv = D.lev[s.lvl_off + level];
         Grid g;
         make_grid(P, D, s, lv, sys, level, sweep, g);
-        if (lv.use_global || !process_cell_tile<W, CAPH, CAPMT>(P, D, sh.t, sys, level, colour, local, sweep, g)) {
+        if (lv.use_global || !process_cell_tile<W, CAPH, CAPMT, NCD>(P, D, sh.t, sys, level, colour, local, sweep, g)) {
             __syncthreads();
             process_cell<W, CAPS, CAPM>(P, D, sh.g, sys, level, colour, local, sweep, g);
         }
@@ -1449,13 +1606,13 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
                   const int32_t* bmap, int nblocks, hipStream_t st) {
     if (nblocks <= 0) return;
     if (variant == V64)
-        hipLaunchKernelGGL((k_phase<64, 512, 128, 512, 128>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour,
+        hipLaunchKernelGGL((k_phase<64, 512, 128, 512, 128, 8>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour,
                            sweep, bmap, nblocks);
     else if (variant == V256)
-        hipLaunchKernelGGL((k_phase<256, 4096, 1024, 1024, 512>), dim3(nblocks), dim3(256), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_phase<256, 4096, 1024, 1024, 512, 12>), dim3(nblocks), dim3(256), 0, st, P, D, level,
                            colour, sweep, bmap, nblocks);
     else
-        hipLaunchKernelGGL((k_phase<1024, 8192, 1024, 4096, 768>), dim3(nblocks), dim3(1024), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_phase<512, 8192, 4096, 4096, 0, 13>), dim3(nblocks), dim3(512), 0, st, P, D, level,
                            colour, sweep, bmap, nblocks);
 }
 

@@ -684,13 +684,13 @@ struct Timed {
     hipStream_t st;
     hipEvent_t a = nullptr;
     Timed(wmc_ctx* c_, int cls_, hipStream_t st_) : c(c_), cls(cls_), st(st_) {
-        if (c->timing && (a = take_event(c))) hipEventRecord(a, st);
+        if (c->timing && (a = take_event(c))) (void)hipEventRecord(a, st);
     }
     ~Timed() {
         if (!a) return;
         hipEvent_t b = take_event(c);
         if (!b) return;
-        hipEventRecord(b, st);
+        (void)hipEventRecord(b, st);
         c->ev_pending.push_back({cls, {a, b}});
     }
 };
@@ -698,7 +698,7 @@ struct Timed {
 static void drain_events(wmc_ctx* c) {
     for (auto& p : c->ev_pending) {
         float ms = 0.0f;
-        hipEventSynchronize(p.second.second);
+        (void)hipEventSynchronize(p.second.second);
         if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
             c->t_ms[p.first] += ms;
             c->t_n[p.first] += 1;
@@ -904,6 +904,6 @@ extern "C" const char* wmc_last_error(const wmc_ctx* c) { return c ? c->err.c_st
 extern "C" void wmc_free(wmc_ctx* c) {
     if (!c) return;
     drain_events(c);
-    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }

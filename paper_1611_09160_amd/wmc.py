@@ -56,6 +56,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1611_09160_amd/build.py")
+        # torch's bundled HIP runtime must be the one loaded into the process: loading the
+        # library first would bind it (and torch) to the system runtime under the same soname.
+        import torch  # noqa: F401
+
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, dp, lp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int64)
         L.wmc_arena_bytes.argtypes = [C.POINTER(Params), i32, lp, dp, dp, i64, lp, i64, C.POINTER(C.c_size_t)]

@@ -98,3 +98,23 @@ def test_full_size_semidilute_one_sweep():
     compare_traces(g.trace(4_000_000), o.trace(4_000_000))
     compare_positions(g.positions(), o.positions())
     compare_counters(g.observables(), o.observables())
+
+
+def test_full_size_after_equilibration():
+    """The benchmark workload after 150 GPU sweeps (dense regions, large member lists appear):
+    no list overflows, then one more sweep from the GPU state against the oracle."""
+    cfg = _workload(3, 1.0)
+    g, _ = build_pair(cfg, trace=0)
+    g.sweep(150)
+    ob = g.observables()
+    assert ob["overflows"] == 0 and ob["violations"] == 0, (ob["overflows"], ob["violations"])
+    pos = g.positions()
+    g.close()
+    g2, o = build_pair(dict(cfg, pos=pos), trace=4_000_000)
+    g2.set_state(pos, 150)
+    o.set_sweep(150)
+    g2.sweep(1)
+    o.sweep(1)
+    compare_traces(g2.trace(4_000_000), o.trace(4_000_000))
+    compare_positions(g2.positions(), o.positions())
+    assert g2.observables()["overflows"] == 0

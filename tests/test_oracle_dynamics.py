@@ -142,8 +142,10 @@ def test_wavelet_linear_map_defect_is_second_order(oracle_mod):
     m5, e5, _ = one_sweep_drift(oracle_mod, dict(base, A0=0.5), 4, 500, np.random.default_rng(8))
     m25, e25, _ = one_sweep_drift(oracle_mod, dict(base, A0=0.25), 4, 500, np.random.default_rng(9))
     assert m5 > 3 * e5
-    ratio = m5 / m25
-    assert 1.5 < ratio < 12.0, (m5, e5, m25, e25)
+    # the drift falls with A0 and is consistent with A0^2 scaling (m25 ~ m5 / 4); the A0 = 0.25
+    # estimate is too noisy for a ratio, so compare differences against their standard errors
+    assert m5 - m25 > 3.0 * np.hypot(e5, e25), (m5, e5, m25, e25)
+    assert abs(m25 - m5 / 4.0) < 4.0 * np.hypot(e25, e5 / 4.0), (m5, e5, m25, e25)
 
 
 def test_k_sampler_distribution(oracle_mod):
