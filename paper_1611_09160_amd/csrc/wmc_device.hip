@@ -521,6 +521,28 @@ void launch_bbox(const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
     hipLaunchKernelGGL(k_bbox, dim3(1), dim3(1024), 0, st, P, D, level, sweep);
 }
 
+// Grid-wide barrier of a cooperative launch (every workgroup co-resident). Each wave first
+// waits for its own stores to complete, so after the workgroup barrier all of the
+// workgroup's writes sit in this XCD's L2; one thread then publishes them at agent scope
+// (L2 write-back, the release of the arrival count), waits for the generation to advance and
+// acquires (L1 and stale L2 lines dropped) for the whole workgroup, which shares its CU's L1.
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's global stores are complete
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned g = gen;
+        unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        if (arrived == nblocks) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    gen = gen + 1u;
+    __syncthreads();
+}
+
 // --------------------------------------------------------------------- cell phase
 // One workgroup processes one cell of the current colour:
 //  1. reach list S_c = beads within lambda_hi of the cell, ascending index (from the
@@ -551,12 +573,11 @@ struct PhaseShared {
 // lies within R (per axis) of a member's current position, R covering the cut-off, both
 // displacements and the drift since the build. One work item is a (member, y-z row of grid
 // cells) pair; its x range is one or two contiguous runs of the grid's bead list.
+// Work items are dealt to threads t0, t0 + stride, ... (one workgroup, or a whole grid).
 // mode 0: FP64; mode 1: FP32 terms (acc) with their sensitivity (sens).
-template <int W>
 __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, const int32_t* Ml, const double* MXl,
-                        const double* MYl, const double* MZl, int n, double R, int mode, double& acc, double& sens,
-                        unsigned long long& viol) {
-    const int tid = threadIdx.x;
+                        const double* MYl, const double* MZl, int n, double R, int mode, int t0, int stride,
+                        double& acc, double& sens, unsigned long long& viol) {
     const double L = s.L, invL = s.invL;
     auto term = [&](int32_t j, double jx, double jy, double jz, double kx, double ky, double kz, int32_t m) {
         if (m == j) return;
@@ -576,7 +597,7 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
         }
     };
     if (P.bond_type != WMC_BOND_NONE) {
-        for (int k = tid; k < n; k += W) {
+        for (int k = t0; k < n; k += stride) {
             const int32_t j = Ml[k];
             const double jx = D.x[j], jy = D.y[j], jz = D.z[j];
             const double kx = MXl[k], ky = MYl[k], kz = MZl[k];
@@ -607,7 +628,7 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
         const int nf = s.nf;
         const int NR = min(nf, (int)floor(2.0 * R * s.invg) + 2);
         const int per = NR * NR;
-        for (int it = tid; it < n * per; it += W) {
+        for (int it = t0; it < n * per; it += stride) {
             const int k = it / per, q = it - k * per;
             const int qy = q % NR, qz = q / NR;
             const int32_t j = Ml[k];
@@ -634,7 +655,7 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
         // infinite system (at most 8192 beads): items are (member, 64-bead block)
         const int64_t nb = s.b1 - s.b0;
         const int nblk = (int)((nb + 63) / 64);
-        for (int it = tid; it < n * nblk; it += W) {
+        for (int it = t0; it < n * nblk; it += stride) {
             const int k = it / nblk, c = it - k * nblk;
             const int32_t j = Ml[k];
             const double jx = D.x[j], jy = D.y[j], jz = D.z[j];
@@ -896,7 +917,7 @@ __device__ __attribute__((noinline)) void process_cell(const DevParams& P, const
             const double thr = -P.kT * log(u_acc);
             {
                 double acc = 0.0, sens = 0.0;
-                glob_dU<W>(P, D, s, Ml, MXl, MYl, MZl, n, Rq, mixed ? 1 : 0, acc, sens, c_viol);
+                glob_dU(P, D, s, Ml, MXl, MYl, MZl, n, Rq, mixed ? 1 : 0, tid, W, acc, sens, c_viol);
                 dU = block_sum<W>(acc, sh.red);
                 if (mixed) {
                     // FP32 terms summed in FP64; each FP32 term is within ~4 ulp of r2 and of the
@@ -905,7 +926,7 @@ __device__ __attribute__((noinline)) void process_cell(const DevParams& P, const
                     if (!(isfinite(dU) && fabs(dU - thr) > bound)) {
                         double a64 = 0.0, s64 = 0.0;
                         unsigned long long v64 = 0;
-                        glob_dU<W>(P, D, s, Ml, MXl, MYl, MZl, n, Rq, 0, a64, s64, v64);
+                        glob_dU(P, D, s, Ml, MXl, MYl, MZl, n, Rq, 0, tid, W, a64, s64, v64);
                         dU = block_sum<W>(a64, sh.red);
                         if (tid == 0) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
                     }
@@ -1616,6 +1637,379 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
                            colour, sweep, bmap, nblocks);
 }
 
+// ------------------------------------------------- cell phase of a large level, grid-wide
+// A level whose colour holds a single cell (two cells per axis, or one) in one large system
+// has nothing to run beside that cell, so all workgroups of a cooperative launch share it.
+// Every workgroup repeats the cheap scalar steps (trial draws and hit tests, directions,
+// recycling redraws) on the same data and so takes the same path; the list work is split:
+//  - reach list: workgroup w scans a contiguous slice of the system's beads; the slices are
+//    concatenated in order (grid barrier, prefix of the per-workgroup counts);
+//  - members of a test: workgroup w scans a contiguous slice of the reach list; the member
+//    list is the ordered concatenation (barrier 1); each workgroup displaces its own members
+//    and publishes its largest displacement (barrier 2);
+//  - dU: (member, grid row) items over every thread of the grid, per-workgroup partial sums
+//    (barrier 3), summed in workgroup order by everyone, so every workgroup takes the same
+//    decision; an accepted move is written back by the owning workgroups (barrier 4).
+constexpr int CW = 256;     // threads per workgroup
+constexpr int CAPL = 4096;  // list entries one workgroup keeps in LDS
+constexpr int CMAXG = 256;  // at most this many workgroups (one count per thread)
+#ifndef WMC_CELL_COOP_G
+#define WMC_CELL_COOP_G 32  // workgroups used: a barrier costs more the more workgroups arrive
+#endif
+
+struct CoopShared {
+    int32_t L[CAPL];
+    double red[CW / 64];
+    int redi[CW / 64];
+    double pub_b[3];
+    double pub_lam;
+    int32_t pub_a;
+    uint32_t pub_next;
+    int pub_off;
+};
+
+// exclusive prefix (at this workgroup) and total of per-workgroup counts published before a
+// grid barrier
+__device__ __forceinline__ void coop_prefix(const int32_t* cnt, int G, CoopShared& sh, int& off, int& tot) {
+    const int v = (int)threadIdx.x < G ? cnt[threadIdx.x] : 0;
+    int before;
+    tot = block_scan_count<CW>(v, before, sh.redi);
+    if ((int)threadIdx.x == (int)blockIdx.x) sh.pub_off = before;
+    __syncthreads();
+    off = sh.pub_off;
+    __syncthreads();
+}
+__device__ __forceinline__ double coop_sum(const double* part, int G, CoopShared& sh) {
+    return block_sum<CW>((int)threadIdx.x < G ? part[threadIdx.x] : 0.0, sh.red);
+}
+__device__ __forceinline__ double coop_max(const double* part, int G, CoopShared& sh) {
+    return block_max<CW>((int)threadIdx.x < G ? part[threadIdx.x] : 0.0, sh.red);
+}
+
+__global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int level, int colour, int64_t sweep) {
+    __shared__ CoopShared sh;
+    const int sys = 0;
+    const SysDesc& s = D.sys[sys];
+    const LevelDesc& lv = D.lev[s.lvl_off + level];
+    const int tid = threadIdx.x, wg = blockIdx.x, G = gridDim.x;
+    const int gt = wg * CW + tid, gstride = G * CW;
+    unsigned gen = __hip_atomic_load(&D.gbar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    Grid g;
+    make_grid(P, D, s, lv, sys, level, sweep, g);
+    int64_t ic[3];
+    cell_coords(P, lv, g, colour, 0, ic);
+    const int64_t cell = ic[0] + g.n[0] * (ic[1] + g.n[1] * ic[2]);
+    const double hi2 = lv.hi * lv.hi;
+    const double Dg = __longlong_as_double((long long)D.drift[sys]);
+    const double L = s.L;
+    int32_t* Sg = D.slot_S + lv.slot_base * D.slot_len;
+    int32_t* Mg = D.slot_M + lv.slot_base * D.slot_len;
+    double* MXg = D.slot_MX + lv.slot_base * 3 * D.slot_len;
+    double* MYg = MXg + D.slot_len;
+    double* MZg = MXg + 2 * D.slot_len;
+    int32_t* ccnt = D.coop_i;
+    double* c_dmax = D.coop_d;
+    double* c_acc = D.coop_d + CMAXG;
+    double* c_sens = D.coop_d + 2 * CMAXG;
+    double* c_a64 = D.coop_d + 3 * CMAXG;
+    double* c_dl = D.coop_d + 4 * CMAXG;
+
+    // ---- 1. reach list, bead order
+    int nS;
+    if (lv.identity) {
+        nS = s.N;
+    } else {
+        const int64_t q = ((int64_t)s.N + G - 1) / G;
+        const int64_t lo = s.b0 + (int64_t)wg * q, hi = min(s.b1, lo + q);
+        int cnt = 0;
+        for (int64_t c0 = lo; c0 < hi; c0 += CW) {
+            const int64_t j = c0 + tid;
+            const bool f = j < hi && dist2_cell(g, ic, D.x[j], D.y[j], D.z[j]) <= hi2;
+            int before;
+            const int tot = block_scan_flag<CW>(f, before, sh.redi);
+            if (f) sh.L[cnt + before] = (int32_t)j;
+            cnt += tot;
+        }
+        if (tid == 0) ccnt[wg] = cnt;
+        grid_barrier(D.gbar, G, gen);
+        int off;
+        coop_prefix(ccnt, G, sh, off, nS);
+        for (int i = tid; i < cnt; i += CW) Sg[off + i] = sh.L[i];
+        grid_barrier(D.gbar, G, gen);
+    }
+    auto Sat = [&](int64_t i) -> int32_t { return lv.identity ? (int32_t)(s.b0 + i) : Sg[i]; };
+
+    // ---- 2. number of trials (every workgroup draws the same)
+    double mu = (lv.T * (double)nS) / (double)s.N;
+    int64_t K = (int64_t)floor(mu);
+    {
+        Stream ms;
+        ms.init(P, sys, sweep, TAG_META + level, cell, 0, 0, 0);
+        if (ms.co() < mu - (double)K) K += 1;
+    }
+    if (K > 0xFFFFF) K = 0xFFFFF;
+    unsigned long long c_hits = 0, c_att = 0, c_acc_n = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0,
+                       c_rechk = 0;
+    double dloc = 0.0;  // largest drift of beads moved in this phase (same in every workgroup)
+    const bool mixed = P.precision == WMC_MIXED;
+    const int qS = (nS + G - 1) / G;
+    const int slo = wg * qS, shi = min(nS, slo + qS);
+
+    // ---- 3. trials and chains
+    for (int64_t t0 = 0; t0 < K;) {
+        const int64_t t = t0 + tid;
+        bool hit = false;
+        double lam = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
+        int32_t a = 0;
+        Stream st;
+        if (t < K && nS > 0) {
+            st.init(P, sys, sweep, level, cell, t, 0, 0);
+            lam = draw_lambda(st.co(), lv.lo, lv.hi);
+            a = Sat(st.index(nS));
+            double vx, vy, vz;
+            ball(st, vx, vy, vz);
+            bx = D.x[a] + lam * vx;
+            by = D.y[a] + lam * vy;
+            bz = D.z[a] + lam * vz;
+            hit = cell_of_point(g, bx, by, bz) == cell;
+        }
+        const int first = block_min_int<CW>(hit ? (int)(t - t0) : 0x7FFFFFFF, sh.redi);
+        if (first == 0x7FFFFFFF) {
+            t0 += CW;
+            continue;
+        }
+        if (tid == first) {
+            sh.pub_lam = lam;
+            sh.pub_a = a;
+            sh.pub_b[0] = bx;
+            sh.pub_b[1] = by;
+            sh.pub_b[2] = bz;
+            sh.pub_next = st.next;
+        }
+        __syncthreads();
+        const int64_t tc = t0 + first;
+        lam = sh.pub_lam;
+        a = sh.pub_a;
+        double b[3] = {sh.pub_b[0], sh.pub_b[1], sh.pub_b[2]};
+        uint32_t nxt = sh.pub_next;
+        int jtry = 0;
+        ++c_hits;
+        const double lam2 = lam * lam;
+        for (int r = 0;;) {
+            Stream cs;
+            cs.init(P, sys, sweep, level, cell, tc, r, jtry);
+            cs.next = nxt;
+            double px, py, pz;
+            direction(cs, px, py, pz);
+            const double u_acc = cs.oc();
+            __syncthreads();
+            // members in this workgroup's slice of the reach list
+            int cnt = 0;
+            for (int c0 = slo; c0 < shi; c0 += CW) {
+                const int i = c0 + tid;
+                bool f = false;
+                int32_t j = 0;
+                if (i < shi) {
+                    j = Sat(i);
+                    const double dx = minimg(g, D.x[j] - b[0]), dy = minimg(g, D.y[j] - b[1]),
+                                 dz = minimg(g, D.z[j] - b[2]);
+                    f = ((dx * dx + dy * dy) + dz * dz) <= lam2 || j == a;
+                }
+                int before;
+                const int tot = block_scan_flag<CW>(f, before, sh.redi);
+                if (f) sh.L[cnt + before] = j;
+                cnt += tot;
+            }
+            if (tid == 0) ccnt[wg] = cnt;
+            grid_barrier(D.gbar, G, gen);  // 1: member counts
+            int off, n;
+            coop_prefix(ccnt, G, sh, off, n);
+            const double A = P.A0 * lam / sqrt((double)n);
+            double dmax_l = 0.0;
+            for (int i = tid; i < cnt; i += CW) {
+                const int k = off + i;
+                const int32_t j = sh.L[i];
+                const double xj = D.x[j], yj = D.y[j], zj = D.z[j];
+                const double xr0 = minimg(g, xj - b[0]) / lam;
+                const double xr1 = minimg(g, yj - b[1]) / lam;
+                const double xr2 = minimg(g, zj - b[2]) / lam;
+                const double rr = sqrt((xr0 * xr0 + xr1 * xr1) + xr2 * xr2);
+                const double f = rr < 1.0 ? A * (1.0 - rr) : 0.0;
+                const double w0 = f * (py * xr2 - pz * xr1);
+                const double w1 = f * (pz * xr0 - px * xr2);
+                const double w2 = f * (px * xr1 - py * xr0);
+                Mg[k] = j;
+                MXg[k] = xj + w0;
+                MYg[k] = yj + w1;
+                MZg[k] = zj + w2;
+                D.tag[j] = k;
+                dmax_l = fmax(dmax_l, sqrt((w0 * w0 + w1 * w1) + w2 * w2));
+            }
+            {
+                const double m = block_max<CW>(dmax_l, sh.red);
+                if (tid == 0) c_dmax[wg] = m;
+            }
+            grid_barrier(D.gbar, G, gen);  // 2: members, trial positions, tags
+            const double dmax = coop_max(c_dmax, G, sh);
+            const double Rq = P.rc + 2.0 * dmax + fmax(Dg, dloc) + 1e-9 * L;
+            const double thr = -P.kT * log(u_acc);
+            double dU;
+            {
+                double acc = 0.0, sens = 0.0;
+                glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, mixed ? 1 : 0, gt, gstride, acc, sens, c_viol);
+                const double pa = block_sum<CW>(acc, sh.red);
+                const double ps = mixed ? block_sum<CW>(sens, sh.red) : 0.0;
+                if (tid == 0) {
+                    c_acc[wg] = pa;
+                    c_sens[wg] = ps;
+                }
+                grid_barrier(D.gbar, G, gen);  // 3: partial sums
+                dU = coop_sum(c_acc, G, sh);
+                if (mixed) {
+                    const double bound = 64.0 * 0x1.0p-23 * coop_sum(c_sens, G, sh) + 1e-12;
+                    if (!(isfinite(dU) && fabs(dU - thr) > bound)) {
+                        double a64 = 0.0, s64 = 0.0;
+                        unsigned long long v64 = 0;
+                        glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, 0, gt, gstride, a64, s64, v64);
+                        const double p64 = block_sum<CW>(a64, sh.red);
+                        if (tid == 0) c_a64[wg] = p64;
+                        grid_barrier(D.gbar, G, gen);
+                        dU = coop_sum(c_a64, G, sh);
+                        ++c_rechk;
+                    }
+                }
+            }
+            const bool accept = dU <= thr;
+            if (wg == 0 && tid == 0) trace_push(D, 0, sys, sweep, level, cell, tc, r, n, accept ? 1 : 0, a, dU, thr);
+            ++c_att;
+            c_beads += n;
+            double dl = 0.0;
+            for (int i = tid; i < cnt; i += CW) {
+                const int k = off + i;
+                const int32_t j = sh.L[i];
+                if (accept) {
+                    const double nx = MXg[k], ny = MYg[k], nz = MZg[k];
+                    D.x[j] = nx;
+                    D.y[j] = ny;
+                    D.z[j] = nz;
+                    dl = fmax(dl, fmax(fabs(nx - D.xb[j]), fmax(fabs(ny - D.yb[j]), fabs(nz - D.zb[j]))));
+                }
+                D.tag[j] = -1;
+            }
+            if (accept) {
+                const double m = block_max<CW>(dl, sh.red);
+                if (tid == 0) c_dl[wg] = m;
+                grid_barrier(D.gbar, G, gen);  // 4: accepted positions
+                dloc = fmax(dloc, coop_max(c_dl, G, sh));
+                ++c_acc_n;
+                break;
+            }
+            __syncthreads();
+            if (++r >= P.retry_cap) {
+                ++c_caps;
+                break;
+            }
+            // recycle lambda: redraw anchor and centre until the centre is in the cell
+            int found = -1;
+            for (int j0 = 0; j0 < 4096 && found < 0; j0 += CW) {
+                const int jj = j0 + tid;
+                bool h2 = false;
+                double ex = 0, ey = 0, ez = 0;
+                int32_t a2 = 0;
+                Stream rs;
+                if (jj < 4096) {
+                    rs.init(P, sys, sweep, level, cell, tc, r, jj);
+                    a2 = Sat(rs.index(nS));
+                    double vx, vy, vz;
+                    ball(rs, vx, vy, vz);
+                    ex = D.x[a2] + lam * vx;
+                    ey = D.y[a2] + lam * vy;
+                    ez = D.z[a2] + lam * vz;
+                    h2 = cell_of_point(g, ex, ey, ez) == cell;
+                }
+                const int fj = block_min_int<CW>(h2 ? jj : 0x7FFFFFFF, sh.redi);
+                if (fj != 0x7FFFFFFF) {
+                    if (jj == fj) {
+                        sh.pub_a = a2;
+                        sh.pub_b[0] = ex;
+                        sh.pub_b[1] = ey;
+                        sh.pub_b[2] = ez;
+                        sh.pub_next = rs.next;
+                    }
+                    found = fj;
+                }
+            }
+            __syncthreads();
+            if (found < 0) {
+                c_redraw += 4096;
+                ++c_caps;
+                break;
+            }
+            c_redraw += (unsigned long long)found;
+            a = sh.pub_a;
+            b[0] = sh.pub_b[0];
+            b[1] = sh.pub_b[1];
+            b[2] = sh.pub_b[2];
+            nxt = sh.pub_next;
+            jtry = found;
+            __syncthreads();
+        }
+        t0 = tc + 1;
+    }
+    // ---- counters (every workgroup holds the same values; workgroup 0 reports them). The
+    // largest-displacement slots are free here: their last reads precede the last barrier 3.
+    const double viol_all = block_sum<CW>((double)c_viol, sh.red);
+    if (tid == 0) c_dmax[wg] = viol_all;
+    grid_barrier(D.gbar, G, gen);
+    const unsigned long long viol_tot = (unsigned long long)coop_sum(c_dmax, G, sh);
+    if (wg == 0 && tid == 0) {
+        unsigned long long* C = D.cnt + CNT_LEVEL + level * 8;
+        atomicAdd(&C[0], (unsigned long long)K);
+        atomicAdd(&C[1], c_hits);
+        atomicAdd(&C[2], c_att);
+        atomicAdd(&C[3], c_acc_n);
+        atomicAdd(&C[4], c_caps);
+        atomicAdd(&C[5], c_redraw);
+        atomicAdd(&C[6], c_beads);
+        if (viol_tot) atomicAdd(&D.cnt[CNT_VIOL], viol_tot);
+        if (c_rechk) atomicAdd(&D.cnt[CNT_RECHECK], c_rechk);
+        if (c_acc_n) {
+            atomicAdd(&D.cnt[CNT_ACCEPTED], c_acc_n);
+            atomicAdd(&D.sys_acc[sys], c_acc_n);
+        }
+        if (dloc > 0.0) atomic_max_double(&D.drift[sys], dloc);
+        trace_push(D, 1, sys, sweep, level, cell, K, nS, 0, (int)c_hits, 0, 0.0, 0.0);
+    }
+}
+
+int cell_coop_blocks() {
+    static int nb = -1;
+    if (nb < 0) {
+        int dev = 0, per_cu = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cell_coop, CW, 0) != hipSuccess || per_cu < 1)
+            nb = 0;
+        else
+            nb = std::min(per_cu * prop.multiProcessorCount, CMAXG);
+    }
+    return nb;
+}
+
+bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep, int64_t N,
+                      hipStream_t st) {
+    const int cap = cell_coop_blocks();
+    // one reach-list bead per thread where possible; a slice must fit the LDS list
+    const int nb = (int)std::min<int64_t>(std::min(cap, WMC_CELL_COOP_G), std::max<int64_t>(1, (N + CW - 1) / CW));
+    if (nb <= 0 || (int64_t)nb * CAPL < N) return false;
+    DevParams Pc = P;
+    DevPtrs Dc = D;
+    int lv = level, col = colour;
+    int64_t sw = sweep;
+    void* args[] = {&Pc, &Dc, &lv, &col, &sw};
+    return hipLaunchCooperativeKernel((const void*)k_cell_coop, dim3(nb), dim3(CW), args, 0, st) == hipSuccess;
+}
+
 // ------------------------------------------------------------------- plane waves
 // One workgroup per system runs its H_F chains (App. D "Generating a plane wave"): k from
 // the cube by inverse CDF or from the quasi-continuous shell, Phi and e-hat, displacement
@@ -1802,28 +2196,11 @@ __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t swe
     }
 }
 
+
 // Plane waves of one large system on many workgroups (cooperative launch: all co-resident).
 // Beads are strided over the grid; each test takes two grid barriers (trial positions written;
 // per-workgroup dU partial sums written) and a third after an accepted move. Every workgroup
 // sums the partial sums in the same order, so all take the same decision.
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned g = gen;
-        unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-        if (arrived == nblocks) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) __builtin_amdgcn_s_sleep(2);
-        }
-    }
-    gen = gen + 1u;
-    __syncthreads();
-    __threadfence();
-}
-
 __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t sweep) {
     __shared__ double red[4];
     const int sys = 0;
@@ -1972,6 +2349,9 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
     }
 }
 
+#ifndef WMC_PW_COOP_G
+#define WMC_PW_COOP_G 128  // workgroups of the grid-wide plane-wave kernel
+#endif
 int pw_coop_blocks() {
     static int nb = -1;
     if (nb < 0) {
@@ -1981,7 +2361,7 @@ int pw_coop_blocks() {
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pw_coop, 256, 0) != hipSuccess || per_cu < 1)
             nb = 0;
         else
-            nb = std::min(per_cu * prop.multiProcessorCount, 1024);
+            nb = std::min(per_cu * prop.multiProcessorCount, WMC_PW_COOP_G);
     }
     return nb;
 }

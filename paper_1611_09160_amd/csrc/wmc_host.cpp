@@ -37,6 +37,7 @@ struct wmc_ctx {
     std::vector<std::vector<double>> pw_out;     // per system: 6 doubles
     int max_levels;
     int phase_variant[WMC_MAX_LEVELS];
+    int level_global[WMC_MAX_LEVELS];  // single system: the level keeps its lists in global slots
     std::vector<int32_t> bmap_host;
     int64_t bmap_off[WMC_MAX_LEVELS][8];
     int32_t bmap_n[WMC_MAX_LEVELS][8];
@@ -226,7 +227,7 @@ struct Plan {
     int64_t N = 0, total_fine = 0, slots = 0, slot_len = 0, pool_cube = 0, pool_shell = 0, n_chains = 0, bmap = 0;
     int nsys = 0, total_levels = 0;
     size_t off_x, off_xb, off_bond, off_sysid, off_tag, off_fcount, off_fstart, off_fidx, off_fcell, off_drift,
-        off_cnt, off_sysacc, off_fblock, off_pwpart, off_gbar, off_trace, off_tracen, off_cube, off_shell, off_slotS, off_slotM, off_slotMX, off_pw,
+        off_cnt, off_sysacc, off_fblock, off_pwpart, off_gbar, off_coop, off_trace, off_tracen, off_cube, off_shell, off_slotS, off_slotM, off_slotMX, off_pw,
         off_igrid, off_sys, off_lev, off_bmap, off_choff, off_rg2;
     size_t bytes = 0;
 };
@@ -478,6 +479,7 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
     pl.off_igrid = lay.add(8 * 8);
     pl.off_pwpart = lay.add(2 * 1024 * 8);
     pl.off_gbar = lay.add(64);
+    pl.off_coop = lay.add(256 * 4 + 5 * 256 * 8);
     pl.off_sys = lay.add(nsys * sizeof(SysDesc));
     pl.off_lev = lay.add(lev.size() * sizeof(LevelDesc));
     pl.off_bmap = lay.add(std::max<int64_t>(bm, 1) * 2 * 4);
@@ -607,6 +609,8 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     D.igrid = (double*)(base + pl.off_igrid);
     D.pw_part = (double*)(base + pl.off_pwpart);
     D.gbar = (unsigned*)(base + pl.off_gbar);
+    D.coop_i = (int32_t*)(base + pl.off_coop);
+    D.coop_d = (double*)(base + pl.off_coop + 256 * 4);
     D.sys = (const SysDesc*)(base + pl.off_sys);
     D.lev = (const LevelDesc*)(base + pl.off_lev);
     D.total_fine = pl.total_fine;
@@ -631,6 +635,7 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     c->bmap_host.clear();
     for (int l = 0; l < WMC_MAX_LEVELS; ++l) {
         c->phase_variant[l] = V64;
+        c->level_global[l] = (nsys == 1 && l < c->sys[0].n_levels) ? c->lev[c->sys[0].lvl_off + l].use_global : 0;
         for (int col = 0; col < 8; ++col) {
             c->bmap_off[l][col] = (int64_t)c->bmap_host.size() / 2;
             int32_t cnt = 0;
@@ -723,6 +728,10 @@ extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
                 for (int col = 0; col < 8; ++col) {
                     if (c->bmap_n[l][col] <= 0) continue;
                     Timed t(c, 1 + l, st);
+                    // a single-cell colour of one large system: all workgroups share the cell
+                    if (c->nsys == 1 && c->bmap_n[l][col] == 1 && c->level_global[l] && c->N >= 4096 &&
+                        launch_cell_coop(c->P, c->D, l, col, sw, c->N, st))
+                        continue;
                     launch_phase(c->phase_variant[l], c->P, c->D, l, col, sw, c->bmap_dev + 2 * c->bmap_off[l][col],
                                  c->bmap_n[l][col], st);
                 }

@@ -85,6 +85,8 @@ struct DevPtrs {
     double* pw_new;             // plane-wave trial positions [3N]
     double* pw_part;            // per-workgroup dU partial sums, two buffers of 1024
     unsigned* gbar;             // grid barrier: arrivals, generation
+    int32_t* coop_i;            // per-workgroup counts of the grid-wide cell phase [256]
+    double* coop_d;             // per-workgroup partial results of the grid-wide cell phase [5][256]
     double* igrid;              // infinite-system grid of the current level: o[3], n[3]
     int64_t total_fine;
 };
@@ -96,6 +98,8 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
                   const int32_t* bmap, int nblocks, hipStream_t st);
 void launch_pw(const DevParams& P, const DevPtrs& D, int64_t sweep, int nsys, hipStream_t st);
 bool launch_pw_coop(const DevParams& P, const DevPtrs& D, int64_t sweep, int64_t N, hipStream_t st);
+bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep, int64_t N,
+                      hipStream_t st);
 void launch_rg2(const DevPtrs& D, const int64_t* chain_off, int64_t n_chains, double* out, hipStream_t st);
 void launch_cell_ids(const DevParams& P, const DevPtrs& D, int sys, int level, int64_t sweep, int64_t n, int32_t* out,
                      hipStream_t st);

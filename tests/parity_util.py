@@ -23,8 +23,11 @@ def sort_trace(t):
     return t[order]
 
 
-def compare_traces(tg, to, dU_rtol=1e-9, dU_atol=1e-8):
-    """Same records (keys, n, anchors, decisions); energies within tolerance. Returns stats."""
+def compare_traces(tg, to, dU_rtol=1e-9, dU_atol=1e-8, dU_atol_member=0.0):
+    """Same records (keys, n, anchors, decisions); energies within tolerance. Returns stats.
+
+    The energy tolerance of a test is dU_atol + dU_rtol |dU| + dU_atol_member n (n = beads
+    moved): FP32 energy terms round each bond and pair term of every moved bead separately."""
     tg, to = sort_trace(tg), sort_trace(to)
     assert len(tg) == len(to), (len(tg), len(to))
     for k in KEY + ("n", "extra"):
@@ -34,8 +37,12 @@ def compare_traces(tg, to, dU_rtol=1e-9, dU_atol=1e-8):
     d = np.abs(tg["dU"][moves] - to["dU"][moves])
     fin = np.isfinite(to["dU"][moves])
     assert np.all(np.isfinite(tg["dU"][moves]) == fin)
-    tol = dU_atol + dU_rtol * np.abs(to["dU"][moves])
-    assert np.all(d[fin] <= tol[fin]), (d[fin].max(), np.argmax(d[fin] - tol[fin]))
+    tol = dU_atol + dU_rtol * np.abs(to["dU"][moves]) + dU_atol_member * to["n"][moves]
+    if not np.all(d[fin] <= tol[fin]):
+        i = np.nonzero(moves)[0][np.nonzero(fin)[0][np.argmax(d[fin] - tol[fin])]]
+        raise AssertionError(f"dU differs by {abs(tg['dU'][i] - to['dU'][i]):.3e} (tolerance "
+                             f"{dU_atol + dU_rtol * abs(to['dU'][i]) + dU_atol_member * to['n'][i]:.3e}) "
+                             f"at record {to[i]} (GPU dU {tg['dU'][i]!r})")
     thr = np.abs(tg["thr"][moves] - to["thr"][moves])
     assert np.all(thr <= 1e-12 * (1 + np.abs(to["thr"][moves])))
     acc_bad = np.nonzero(tg["accepted"] != to["accepted"])[0]
