@@ -543,6 +543,17 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, un
     __syncthreads();
 }
 
+// barrier over the nblocks workgroups of one cooperative group (a plain workgroup barrier when
+// the group is a single workgroup)
+__device__ __forceinline__ void group_barrier(unsigned* bar, unsigned nblocks, unsigned& gen) {
+    if (nblocks > 1) {
+        grid_barrier(bar, nblocks, gen);
+    } else {
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+        __syncthreads();
+    }
+}
+
 // --------------------------------------------------------------------- cell phase
 // One workgroup processes one cell of the current colour:
 //  1. reach list S_c = beads within lambda_hi of the cell, ascending index (from the
@@ -1638,9 +1649,10 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
 }
 
 // ------------------------------------------------- cell phase of a large level, grid-wide
-// A level whose colour holds a single cell (two cells per axis, or one) in one large system
-// has nothing to run beside that cell, so all workgroups of a cooperative launch share it.
-// Every workgroup repeats the cheap scalar steps (trial draws and hit tests, directions,
+// A level with one or two cells per axis has few cells per colour (one per system), so a
+// cooperative launch gives each such cell a group of workgroups (CoopGroup, sized by the
+// system's bead count; the groups of one launch are the cells of one colour). Within a group,
+// every workgroup repeats the cheap scalar steps (trial draws and hit tests, directions,
 // recycling redraws) on the same data and so takes the same path; the list work is split:
 //  - reach list: workgroup w scans a contiguous slice of the system's beads; the slices are
 //    concatenated in order (grid barrier, prefix of the per-workgroup counts);
@@ -1651,11 +1663,8 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
 //    (barrier 3), summed in workgroup order by everyone, so every workgroup takes the same
 //    decision; an accepted move is written back by the owning workgroups (barrier 4).
 constexpr int CW = 256;     // threads per workgroup
-constexpr int CAPL = 4096;  // list entries one workgroup keeps in LDS
-constexpr int CMAXG = 256;  // at most this many workgroups (one count per thread)
-#ifndef WMC_CELL_COOP_G
-#define WMC_CELL_COOP_G 32  // workgroups used: a barrier costs more the more workgroups arrive
-#endif
+constexpr int CAPL = COOP_LIST_CAP;  // list entries one workgroup keeps in LDS
+constexpr int CMAXG = 256;  // at most this many workgroups per group (one count per thread)
 
 struct CoopShared {
     int32_t L[CAPL];
@@ -1668,13 +1677,13 @@ struct CoopShared {
     int pub_off;
 };
 
-// exclusive prefix (at this workgroup) and total of per-workgroup counts published before a
-// grid barrier
-__device__ __forceinline__ void coop_prefix(const int32_t* cnt, int G, CoopShared& sh, int& off, int& tot) {
+// exclusive prefix (at the workgroup of rank wg in its group) and total of the group's
+// per-workgroup counts published before a group barrier
+__device__ __forceinline__ void coop_prefix(const int32_t* cnt, int G, int wg, CoopShared& sh, int& off, int& tot) {
     const int v = (int)threadIdx.x < G ? cnt[threadIdx.x] : 0;
     int before;
     tot = block_scan_count<CW>(v, before, sh.redi);
-    if ((int)threadIdx.x == (int)blockIdx.x) sh.pub_off = before;
+    if ((int)threadIdx.x == wg) sh.pub_off = before;
     __syncthreads();
     off = sh.pub_off;
     __syncthreads();
@@ -1686,33 +1695,38 @@ __device__ __forceinline__ double coop_max(const double* part, int G, CoopShared
     return block_max<CW>((int)threadIdx.x < G ? part[threadIdx.x] : 0.0, sh.red);
 }
 
-__global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int level, int colour, int64_t sweep) {
+__global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int level, int colour, int64_t sweep,
+                                                  const CoopGroup* groups, const int32_t* wg_group) {
     __shared__ CoopShared sh;
-    const int sys = 0;
+    const int gi = wg_group[blockIdx.x];
+    const CoopGroup grp = groups[gi];
+    const int sys = grp.sys;
     const SysDesc& s = D.sys[sys];
     const LevelDesc& lv = D.lev[s.lvl_off + level];
-    const int tid = threadIdx.x, wg = blockIdx.x, G = gridDim.x;
+    const int tid = threadIdx.x, wg = (int)blockIdx.x - grp.first, G = grp.size;
     const int gt = wg * CW + tid, gstride = G * CW;
-    unsigned gen = __hip_atomic_load(&D.gbar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned* bar = D.gbar + 2 * (1 + gi);
+    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     Grid g;
     make_grid(P, D, s, lv, sys, level, sweep, g);
     int64_t ic[3];
-    cell_coords(P, lv, g, colour, 0, ic);
+    cell_coords(P, lv, g, colour, grp.local, ic);
     const int64_t cell = ic[0] + g.n[0] * (ic[1] + g.n[1] * ic[2]);
     const double hi2 = lv.hi * lv.hi;
     const double Dg = __longlong_as_double((long long)D.drift[sys]);
     const double L = s.L;
-    int32_t* Sg = D.slot_S + lv.slot_base * D.slot_len;
-    int32_t* Mg = D.slot_M + lv.slot_base * D.slot_len;
-    double* MXg = D.slot_MX + lv.slot_base * 3 * D.slot_len;
+    int32_t* Sg = D.slot_S + (lv.slot_base + grp.local) * D.slot_len;
+    int32_t* Mg = D.slot_M + (lv.slot_base + grp.local) * D.slot_len;
+    double* MXg = D.slot_MX + (lv.slot_base + grp.local) * 3 * D.slot_len;
     double* MYg = MXg + D.slot_len;
     double* MZg = MXg + 2 * D.slot_len;
-    int32_t* ccnt = D.coop_i;
-    double* c_dmax = D.coop_d;
-    double* c_acc = D.coop_d + CMAXG;
-    double* c_sens = D.coop_d + 2 * CMAXG;
-    double* c_a64 = D.coop_d + 3 * CMAXG;
-    double* c_dl = D.coop_d + 4 * CMAXG;
+    // this group's per-workgroup slots
+    int32_t* ccnt = D.coop_i + grp.first;
+    double* c_dmax = D.coop_d + grp.first;
+    double* c_acc = D.coop_d + COOP_SLOTS + grp.first;
+    double* c_sens = D.coop_d + 2 * COOP_SLOTS + grp.first;
+    double* c_a64 = D.coop_d + 3 * COOP_SLOTS + grp.first;
+    double* c_dl = D.coop_d + 4 * COOP_SLOTS + grp.first;
 
     // ---- 1. reach list, bead order
     int nS;
@@ -1731,11 +1745,11 @@ __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int le
             cnt += tot;
         }
         if (tid == 0) ccnt[wg] = cnt;
-        grid_barrier(D.gbar, G, gen);
+        group_barrier(bar, G, gen);
         int off;
-        coop_prefix(ccnt, G, sh, off, nS);
+        coop_prefix(ccnt, G, wg, sh, off, nS);
         for (int i = tid; i < cnt; i += CW) Sg[off + i] = sh.L[i];
-        grid_barrier(D.gbar, G, gen);
+        group_barrier(bar, G, gen);
     }
     auto Sat = [&](int64_t i) -> int32_t { return lv.identity ? (int32_t)(s.b0 + i) : Sg[i]; };
 
@@ -1821,9 +1835,9 @@ __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int le
                 cnt += tot;
             }
             if (tid == 0) ccnt[wg] = cnt;
-            grid_barrier(D.gbar, G, gen);  // 1: member counts
+            group_barrier(bar, G, gen);  // 1: member counts
             int off, n;
-            coop_prefix(ccnt, G, sh, off, n);
+            coop_prefix(ccnt, G, wg, sh, off, n);
             const double A = P.A0 * lam / sqrt((double)n);
             double dmax_l = 0.0;
             for (int i = tid; i < cnt; i += CW) {
@@ -1849,7 +1863,7 @@ __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int le
                 const double m = block_max<CW>(dmax_l, sh.red);
                 if (tid == 0) c_dmax[wg] = m;
             }
-            grid_barrier(D.gbar, G, gen);  // 2: members, trial positions, tags
+            group_barrier(bar, G, gen);  // 2: members, trial positions, tags
             const double dmax = coop_max(c_dmax, G, sh);
             const double Rq = P.rc + 2.0 * dmax + fmax(Dg, dloc) + 1e-9 * L;
             const double thr = -P.kT * log(u_acc);
@@ -1863,7 +1877,7 @@ __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int le
                     c_acc[wg] = pa;
                     c_sens[wg] = ps;
                 }
-                grid_barrier(D.gbar, G, gen);  // 3: partial sums
+                group_barrier(bar, G, gen);  // 3: partial sums
                 dU = coop_sum(c_acc, G, sh);
                 if (mixed) {
                     const double bound = 64.0 * 0x1.0p-23 * coop_sum(c_sens, G, sh) + 1e-12;
@@ -1873,7 +1887,7 @@ __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int le
                         glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, 0, gt, gstride, a64, s64, v64);
                         const double p64 = block_sum<CW>(a64, sh.red);
                         if (tid == 0) c_a64[wg] = p64;
-                        grid_barrier(D.gbar, G, gen);
+                        group_barrier(bar, G, gen);
                         dU = coop_sum(c_a64, G, sh);
                         ++c_rechk;
                     }
@@ -1899,7 +1913,7 @@ __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int le
             if (accept) {
                 const double m = block_max<CW>(dl, sh.red);
                 if (tid == 0) c_dl[wg] = m;
-                grid_barrier(D.gbar, G, gen);  // 4: accepted positions
+                group_barrier(bar, G, gen);  // 4: accepted positions
                 dloc = fmax(dloc, coop_max(c_dl, G, sh));
                 ++c_acc_n;
                 break;
@@ -1960,7 +1974,7 @@ __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int le
     // largest-displacement slots are free here: their last reads precede the last barrier 3.
     const double viol_all = block_sum<CW>((double)c_viol, sh.red);
     if (tid == 0) c_dmax[wg] = viol_all;
-    grid_barrier(D.gbar, G, gen);
+    group_barrier(bar, G, gen);
     const unsigned long long viol_tot = (unsigned long long)coop_sum(c_dmax, G, sh);
     if (wg == 0 && tid == 0) {
         unsigned long long* C = D.cnt + CNT_LEVEL + level * 8;
@@ -1991,23 +2005,22 @@ int cell_coop_blocks() {
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cell_coop, CW, 0) != hipSuccess || per_cu < 1)
             nb = 0;
         else
-            nb = std::min(per_cu * prop.multiProcessorCount, CMAXG);
+            nb = std::min(per_cu * prop.multiProcessorCount, COOP_SLOTS);
     }
     return nb;
 }
 
-bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep, int64_t N,
-                      hipStream_t st) {
-    const int cap = cell_coop_blocks();
-    // one reach-list bead per thread where possible; a slice must fit the LDS list
-    const int nb = (int)std::min<int64_t>(std::min(cap, WMC_CELL_COOP_G), std::max<int64_t>(1, (N + CW - 1) / CW));
-    if (nb <= 0 || (int64_t)nb * CAPL < N) return false;
+bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
+                      const CoopGroup* groups, const int32_t* wg_group, int nwg, hipStream_t st) {
+    if (nwg <= 0 || nwg > cell_coop_blocks()) return false;
     DevParams Pc = P;
     DevPtrs Dc = D;
     int lv = level, col = colour;
     int64_t sw = sweep;
-    void* args[] = {&Pc, &Dc, &lv, &col, &sw};
-    return hipLaunchCooperativeKernel((const void*)k_cell_coop, dim3(nb), dim3(CW), args, 0, st) == hipSuccess;
+    const CoopGroup* gp = groups;
+    const int32_t* wp = wg_group;
+    void* args[] = {&Pc, &Dc, &lv, &col, &sw, &gp, &wp};
+    return hipLaunchCooperativeKernel((const void*)k_cell_coop, dim3(nwg), dim3(CW), args, 0, st) == hipSuccess;
 }
 
 // ------------------------------------------------------------------- plane waves
@@ -2197,20 +2210,26 @@ __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t swe
 }
 
 
-// Plane waves of one large system on many workgroups (cooperative launch: all co-resident).
-// Beads are strided over the grid; each test takes two grid barriers (trial positions written;
-// per-workgroup dU partial sums written) and a third after an accepted move. Every workgroup
-// sums the partial sums in the same order, so all take the same decision.
-__global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t sweep) {
+// Plane waves on groups of workgroups (cooperative launch: all co-resident), one group per
+// system, sized by its bead count. A group's beads are strided over its workgroups; each test
+// takes two group barriers (trial positions written; per-workgroup dU partial sums written) and
+// a third after an accepted move. Every workgroup sums the partial sums in the same order, so
+// all take the same decision.
+__global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t sweep, const CoopGroup* groups,
+                                                 const int32_t* wg_group) {
     __shared__ double red[4];
-    const int sys = 0;
+    const int gi = wg_group[blockIdx.x];
+    const CoopGroup grp = groups[gi];
+    const int sys = grp.sys;
     const SysDesc& s = D.sys[sys];
     const int tid = threadIdx.x;
-    const unsigned G = gridDim.x;
+    const unsigned G = grp.size;
+    const int rank = (int)blockIdx.x - grp.first;
     const int64_t stride = (int64_t)G * 256;
-    const int64_t g0 = s.b0 + (int64_t)blockIdx.x * 256 + tid;
+    const int64_t g0 = s.b0 + (int64_t)rank * 256 + tid;
     const double L = s.L, invL = s.invL;
-    unsigned gen = __hip_atomic_load(&D.gbar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned* bar = D.gbar + 2 * (1 + gi);
+    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     Stream cs;
     cs.init(P, sys, sweep, TAG_PWCOUNT, 0, 0, 0, 0);
     double mu = (double)s.N * s.PF;
@@ -2236,7 +2255,7 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
             if (l[0] == 0 && l[1] == 0 && l[2] == 0) {
                 ++c_k0;
                 ++c_acc;
-                if (blockIdx.x == 0 && tid == 0)
+                if (rank == 0 && tid == 0)
                     trace_push(D, 2, sys, sweep, -1, h, 0, r, 0, 1, (int)((512u << 20) | (512u << 10) | 512u), 0.0,
                                thr);
                 break;
@@ -2265,7 +2284,7 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
                 NY[j] = D.y[j] + f * e[1];
                 NZ[j] = D.z[j] + f * e[2];
             }
-            grid_barrier(D.gbar, G, gen);
+            group_barrier(bar, G, gen);
             double acc = 0.0;
             const double R = P.rc + 2.0 * AF + Dg + 1e-9 * L;
             for (int64_t j = g0; j < s.b1; j += stride) {
@@ -2297,16 +2316,16 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
                 }
             }
             double part = block_sum<256>(acc, red);
-            double* partials = D.pw_part + (parity ? G : 0);
-            if (tid == 0) partials[blockIdx.x] = part;
-            grid_barrier(D.gbar, G, gen);
+            double* partials = D.coop_d + (parity ? COOP_SLOTS : 0) + grp.first;
+            if (tid == 0) partials[rank] = part;
+            group_barrier(bar, G, gen);
             double dU = 0.0;
             for (unsigned b = 0; b < G; ++b) dU += partials[b];
             parity ^= 1;
             const bool accept = dU <= thr;
             ++c_att;
             c_beads += s.N;
-            if (blockIdx.x == 0 && tid == 0) {
+            if (rank == 0 && tid == 0) {
                 int extra = (int)((((uint32_t)(l[0] + 512) & 0x3FFu) << 20) | (((uint32_t)(l[1] + 512) & 0x3FFu) << 10) |
                                   ((uint32_t)(l[2] + 512) & 0x3FFu));
                 trace_push(D, 2, sys, sweep, -1, h, 0, r, s.N, accept ? 1 : 0, extra, dU, thr);
@@ -2319,7 +2338,7 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
                 }
                 Dg += AF;
                 ++c_acc;
-                grid_barrier(D.gbar, G, gen);
+                group_barrier(bar, G, gen);
                 break;
             }
             if (++r >= P.retry_cap) {
@@ -2333,7 +2352,7 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
             for (int q = 0; q < 3; ++q) l[q] = st.co() < 0.5 ? -nl[q] : nl[q];
         }
     }
-    if (blockIdx.x == 0 && tid == 0) {
+    if (rank == 0 && tid == 0) {
         unsigned long long* C = D.cnt + CNT_PW;
         atomicAdd(&C[0], (unsigned long long)HF);
         atomicAdd(&C[1], c_att);
@@ -2349,9 +2368,6 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
     }
 }
 
-#ifndef WMC_PW_COOP_G
-#define WMC_PW_COOP_G 128  // workgroups of the grid-wide plane-wave kernel
-#endif
 int pw_coop_blocks() {
     static int nb = -1;
     if (nb < 0) {
@@ -2361,20 +2377,21 @@ int pw_coop_blocks() {
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pw_coop, 256, 0) != hipSuccess || per_cu < 1)
             nb = 0;
         else
-            nb = std::min(per_cu * prop.multiProcessorCount, WMC_PW_COOP_G);
+            nb = std::min(per_cu * prop.multiProcessorCount, COOP_SLOTS);
     }
     return nb;
 }
 
-bool launch_pw_coop(const DevParams& P, const DevPtrs& D, int64_t sweep, int64_t N, hipStream_t st) {
-    int cap = pw_coop_blocks();
-    if (cap <= 0) return false;
-    int nb = (int)std::min<int64_t>(cap, (N + 255) / 256);
+bool launch_pw_coop(const DevParams& P, const DevPtrs& D, int64_t sweep, const CoopGroup* groups,
+                    const int32_t* wg_group, int nwg, hipStream_t st) {
+    if (nwg <= 0 || nwg > pw_coop_blocks()) return false;
     DevParams Pc = P;
     DevPtrs Dc = D;
     int64_t sw = sweep;
-    void* args[] = {&Pc, &Dc, &sw};
-    return hipLaunchCooperativeKernel((const void*)k_pw_coop, dim3(nb), dim3(256), args, 0, st) == hipSuccess;
+    const CoopGroup* gp = groups;
+    const int32_t* wp = wg_group;
+    void* args[] = {&Pc, &Dc, &sw, &gp, &wp};
+    return hipLaunchCooperativeKernel((const void*)k_pw_coop, dim3(nwg), dim3(256), args, 0, st) == hipSuccess;
 }
 
 void launch_pw(const DevParams& P, const DevPtrs& D, int64_t sweep, int nsys, hipStream_t st) {

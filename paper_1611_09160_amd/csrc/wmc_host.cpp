@@ -37,11 +37,19 @@ struct wmc_ctx {
     std::vector<std::vector<double>> pw_out;     // per system: 6 doubles
     int max_levels;
     int phase_variant[WMC_MAX_LEVELS];
-    int level_global[WMC_MAX_LEVELS];  // single system: the level keeps its lists in global slots
     std::vector<int32_t> bmap_host;
-    int64_t bmap_off[WMC_MAX_LEVELS][8];
+    int64_t bmap_off[WMC_MAX_LEVELS][8];  // every cell of the colour
     int32_t bmap_n[WMC_MAX_LEVELS][8];
+    int64_t tile_off[WMC_MAX_LEVELS][8];  // the cells left to k_phase when the groups run
+    int32_t tile_n[WMC_MAX_LEVELS][8];
     int32_t* bmap_dev;
+    // cooperative groups (int32 table: CoopGroup records, then the workgroup -> group map)
+    std::vector<int32_t> coop_host;
+    int32_t* coop_dev;
+    int64_t cgrp_off[WMC_MAX_LEVELS][8], cwg_off[WMC_MAX_LEVELS][8];
+    int32_t cwg_n[WMC_MAX_LEVELS][8];     // workgroups of the cell-group launch (0: none)
+    int64_t pgrp_off = 0, pwg_off = 0;
+    int32_t pwg_n = 0;                    // workgroups of the plane-wave group launch (0: none)
     int64_t* chain_off_dev;
     double* rg2_dev;
     int64_t sweep;
@@ -224,10 +232,10 @@ struct Layout {
 
 // everything the arena holds, computed identically by wmc_arena_bytes and wmc_init
 struct Plan {
-    int64_t N = 0, total_fine = 0, slots = 0, slot_len = 0, pool_cube = 0, pool_shell = 0, n_chains = 0, bmap = 0;
+    int64_t N = 0, total_fine = 0, slots = 0, slot_len = 0, pool_cube = 0, pool_shell = 0, n_chains = 0, bmap = 0, coop_ints = 0;
     int nsys = 0, total_levels = 0;
     size_t off_x, off_xb, off_bond, off_sysid, off_tag, off_fcount, off_fstart, off_fidx, off_fcell, off_drift,
-        off_cnt, off_sysacc, off_fblock, off_pwpart, off_gbar, off_coop, off_trace, off_tracen, off_cube, off_shell, off_slotS, off_slotM, off_slotMX, off_pw,
+        off_cnt, off_sysacc, off_fblock, off_gbar, off_coop, off_cooptab, off_trace, off_tracen, off_cube, off_shell, off_slotS, off_slotM, off_slotMX, off_pw,
         off_igrid, off_sys, off_lev, off_bmap, off_choff, off_rg2;
     size_t bytes = 0;
 };
@@ -442,16 +450,23 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
     pl.pool_cube = cube_pool;
     pl.pool_shell = shell_pool;
     pl.total_levels = (int)lev.size();
-    // block maps: one entry (system, local cell) per workgroup of each (level, colour) launch
-    int64_t bm = 0;
+    // block maps: one entry (system, local cell) per workgroup of each (level, colour) launch;
+    // phases holding global-list cells may run them as cooperative groups
+    int64_t bm = 0, gphases = 0;
     for (int l = 0; l < WMC_MAX_LEVELS; ++l)
-        for (int col = 0; col < 8; ++col)
+        for (int col = 0; col < 8; ++col) {
+            bool glob = false;
             for (int s = 0; s < nsys; ++s)
                 if (p->periodic && l < sys[s].n_levels) {
                     const LevelDesc& L = lev[sys[s].lvl_off + l];
-                    bm += L.n >= 2 ? (int64_t)(L.n / 2) * (L.n / 2) * (L.n / 2) : (col == 0 ? 1 : 0);
+                    int64_t ncol = L.n >= 2 ? (int64_t)(L.n / 2) * (L.n / 2) * (L.n / 2) : (col == 0 ? 1 : 0);
+                    bm += ncol;
+                    if (ncol > 0 && L.use_global) glob = true;
                 }
+            gphases += glob ? 1 : 0;
+        }
     pl.bmap = bm;
+    pl.coop_ints = 4 * (bm + nsys) + (int64_t)COOP_SLOTS * (gphases + 1);
     // arena layout
     Layout lay;
     const int64_t N = pl.N;
@@ -477,12 +492,12 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
     pl.off_slotMX = lay.add(slots * slot_len * 3 * 8);
     pl.off_pw = lay.add((p->periodic && p->plane_waves) ? 3 * N * 8 : 8);
     pl.off_igrid = lay.add(8 * 8);
-    pl.off_pwpart = lay.add(2 * 1024 * 8);
-    pl.off_gbar = lay.add(64);
-    pl.off_coop = lay.add(256 * 4 + 5 * 256 * 8);
+    pl.off_gbar = lay.add(2 * (1 + COOP_SLOTS) * 4);
+    pl.off_coop = lay.add(COOP_SLOTS * 4 + 5 * COOP_SLOTS * 8);
+    pl.off_cooptab = lay.add(pl.coop_ints * 4);
     pl.off_sys = lay.add(nsys * sizeof(SysDesc));
     pl.off_lev = lay.add(lev.size() * sizeof(LevelDesc));
-    pl.off_bmap = lay.add(std::max<int64_t>(bm, 1) * 2 * 4);
+    pl.off_bmap = lay.add(std::max<int64_t>(bm, 1) * 2 * 2 * 4);
     pl.off_choff = lay.add((n_chains + 1) * 8);
     pl.off_rg2 = lay.add(std::max<int64_t>(n_chains, 1) * 8);
     pl.bytes = lay.total + 256;
@@ -502,6 +517,98 @@ extern "C" int wmc_arena_bytes(const wmc_params* p, int32_t n_systems, const int
     if (rc) return rc;
     *out_bytes = pl.bytes;
     return 0;
+}
+
+// Group sizes of the cooperative launches, from each system's bead count: a cell group gets one
+// workgroup per CELL_GROUP_BEADS beads (at most CELL_GROUP_MAX, and enough that a workgroup's
+// slice of the reach list fits its LDS list), a plane-wave group one per PW_GROUP_BEADS (at most
+// PW_GROUP_MAX). Sizes shrink proportionally when the sum exceeds what can be co-resident; a
+// launch is planned only if it fits and some group has more than one workgroup.
+static bool size_groups(std::vector<int>& G, const std::vector<int64_t>& Ns, int per, int gmax, int cap,
+                        int64_t slice_cap) {
+    int64_t T = 0;
+    int top = 0;
+    for (size_t i = 0; i < Ns.size(); ++i) {
+        G[i] = (int)std::min<int64_t>(gmax, std::max<int64_t>(1, (Ns[i] + per - 1) / per));
+        T += G[i];
+    }
+    if (T > cap) {
+        int64_t T2 = 0;
+        for (size_t i = 0; i < Ns.size(); ++i) {
+            G[i] = (int)std::max<int64_t>(1, (int64_t)G[i] * cap / T);
+            T2 += G[i];
+        }
+        T = T2;
+    }
+    for (size_t i = 0; i < Ns.size(); ++i) {
+        if (slice_cap > 0 && (Ns[i] + G[i] - 1) / G[i] > slice_cap) return false;
+        top = std::max(top, G[i]);
+    }
+    return cap > 0 && T <= cap && top > 1;
+}
+
+static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
+    c->coop_host.clear();
+    auto& H = c->coop_host;
+    std::vector<int32_t> tiles;
+    const int ccap = c->P.periodic ? cell_coop_blocks() : 0;
+    for (int l = 0; l < WMC_MAX_LEVELS; ++l)
+        for (int col = 0; col < 8; ++col) {
+            c->cwg_n[l][col] = 0;
+            c->tile_n[l][col] = 0;
+            std::vector<std::pair<int32_t, int32_t>> glob;
+            tiles.clear();
+            for (int32_t e = 0; e < c->bmap_n[l][col]; ++e) {
+                const int32_t s = c->bmap_host[2 * (c->bmap_off[l][col] + e)];
+                const int32_t k = c->bmap_host[2 * (c->bmap_off[l][col] + e) + 1];
+                if (c->lev[c->sys[s].lvl_off + l].use_global) {
+                    glob.push_back({s, k});
+                } else {
+                    tiles.push_back(s);
+                    tiles.push_back(k);
+                }
+            }
+            c->tile_off[l][col] = (int64_t)c->bmap_host.size() / 2;
+            c->tile_n[l][col] = (int32_t)(tiles.size() / 2);
+            c->bmap_host.insert(c->bmap_host.end(), tiles.begin(), tiles.end());
+            if (glob.empty()) continue;
+            std::vector<int64_t> Ns(glob.size());
+            for (size_t i = 0; i < glob.size(); ++i) Ns[i] = c->sys[glob[i].first].N;
+            std::vector<int> G(glob.size());
+            if (!size_groups(G, Ns, CELL_GROUP_BEADS, CELL_GROUP_MAX, ccap, COOP_LIST_CAP)) continue;
+            int first = 0;
+            c->cgrp_off[l][col] = (int64_t)H.size();
+            for (size_t i = 0; i < glob.size(); ++i) {
+                H.insert(H.end(), {glob[i].first, glob[i].second, first, G[i]});
+                first += G[i];
+            }
+            c->cwg_off[l][col] = (int64_t)H.size();
+            for (size_t i = 0; i < glob.size(); ++i) H.insert(H.end(), (size_t)G[i], (int32_t)i);
+            c->cwg_n[l][col] = first;
+        }
+    c->pwg_n = 0;
+    if (c->P.periodic && c->P.plane_waves) {
+        std::vector<int64_t> Ns(c->nsys);
+        for (int s = 0; s < c->nsys; ++s) Ns[s] = c->sys[s].N;
+        std::vector<int> G(c->nsys);
+        if (size_groups(G, Ns, PW_GROUP_BEADS, PW_GROUP_MAX, pw_coop_blocks(), 0)) {
+            int first = 0;
+            c->pgrp_off = (int64_t)H.size();
+            for (int s = 0; s < c->nsys; ++s) {
+                H.insert(H.end(), {s, 0, first, G[s]});
+                first += G[s];
+            }
+            c->pwg_off = (int64_t)H.size();
+            for (int s = 0; s < c->nsys; ++s) H.insert(H.end(), (size_t)G[s], (int32_t)s);
+            c->pwg_n = first;
+        }
+    }
+    if ((int64_t)H.size() > capacity_ints) {  // cannot happen: the layout bounds the table
+        H.clear();
+        for (int l = 0; l < WMC_MAX_LEVELS; ++l)
+            for (int col = 0; col < 8; ++col) c->cwg_n[l][col] = 0;
+        c->pwg_n = 0;
+    }
 }
 
 extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const int64_t* so, const double* sL,
@@ -607,10 +714,10 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     D.slot_len = pl.slot_len;
     D.pw_new = (double*)(base + pl.off_pw);
     D.igrid = (double*)(base + pl.off_igrid);
-    D.pw_part = (double*)(base + pl.off_pwpart);
     D.gbar = (unsigned*)(base + pl.off_gbar);
     D.coop_i = (int32_t*)(base + pl.off_coop);
-    D.coop_d = (double*)(base + pl.off_coop + 256 * 4);
+    D.coop_d = (double*)(base + pl.off_coop + COOP_SLOTS * 4);
+    c->coop_dev = (int32_t*)(base + pl.off_cooptab);
     D.sys = (const SysDesc*)(base + pl.off_sys);
     D.lev = (const LevelDesc*)(base + pl.off_lev);
     D.total_fine = pl.total_fine;
@@ -635,7 +742,6 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     c->bmap_host.clear();
     for (int l = 0; l < WMC_MAX_LEVELS; ++l) {
         c->phase_variant[l] = V64;
-        c->level_global[l] = (nsys == 1 && l < c->sys[0].n_levels) ? c->lev[c->sys[0].lvl_off + l].use_global : 0;
         for (int col = 0; col < 8; ++col) {
             c->bmap_off[l][col] = (int64_t)c->bmap_host.size() / 2;
             int32_t cnt = 0;
@@ -654,6 +760,7 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
         }
         if (!p->periodic && l < c->max_levels) c->phase_variant[l] = c->lev[l].variant;
     }
+    build_groups(c, pl.coop_ints);
     HIPCHK(c, hipMemsetAsync(base, 0, pl.bytes - 256, st));
     HIPCHK(c, hipMemcpyAsync(D.x, soa.data(), 3 * N * 8, hipMemcpyHostToDevice, st));
     HIPCHK(c, hipMemcpyAsync(D.bond_next, bond.data(), N, hipMemcpyHostToDevice, st));
@@ -666,6 +773,8 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     HIPCHK(c, hipMemcpyAsync((void*)D.lev, c->lev.data(), c->lev.size() * sizeof(LevelDesc), hipMemcpyHostToDevice, st));
     if (!c->bmap_host.empty())
         HIPCHK(c, hipMemcpyAsync(c->bmap_dev, c->bmap_host.data(), c->bmap_host.size() * 4, hipMemcpyHostToDevice, st));
+    if (!c->coop_host.empty())
+        HIPCHK(c, hipMemcpyAsync(c->coop_dev, c->coop_host.data(), c->coop_host.size() * 4, hipMemcpyHostToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->chain_off_dev, co, (n_chains + 1) * 8, hipMemcpyHostToDevice, st));
     HIPCHK(c, hipStreamSynchronize(st));
     return 0;
@@ -728,10 +837,15 @@ extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
                 for (int col = 0; col < 8; ++col) {
                     if (c->bmap_n[l][col] <= 0) continue;
                     Timed t(c, 1 + l, st);
-                    // a single-cell colour of one large system: all workgroups share the cell
-                    if (c->nsys == 1 && c->bmap_n[l][col] == 1 && c->level_global[l] && c->N >= 4096 &&
-                        launch_cell_coop(c->P, c->D, l, col, sw, c->N, st))
+                    // global-list cells as cooperative groups, the other cells one workgroup each
+                    if (c->cwg_n[l][col] > 0 &&
+                        launch_cell_coop(c->P, c->D, l, col, sw, (const CoopGroup*)(c->coop_dev + c->cgrp_off[l][col]),
+                                         c->coop_dev + c->cwg_off[l][col], c->cwg_n[l][col], st)) {
+                        if (c->tile_n[l][col] > 0)
+                            launch_phase(c->phase_variant[l], c->P, c->D, l, col, sw,
+                                         c->bmap_dev + 2 * c->tile_off[l][col], c->tile_n[l][col], st);
                         continue;
+                    }
                     launch_phase(c->phase_variant[l], c->P, c->D, l, col, sw, c->bmap_dev + 2 * c->bmap_off[l][col],
                                  c->bmap_n[l][col], st);
                 }
@@ -749,8 +863,10 @@ extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
                 launch_fine_build(c->P, c->D, c->N, st);
             }
             Timed t(c, 17, st);
-            // one large system: all workgroups cooperate; otherwise one workgroup per system
-            if (!(c->nsys == 1 && c->N >= 8192 && launch_pw_coop(c->P, c->D, sw, c->N, st)))
+            // groups of workgroups per system when they fit one cooperative launch, otherwise one
+            // workgroup per system
+            if (!(c->pwg_n > 0 && launch_pw_coop(c->P, c->D, sw, (const CoopGroup*)(c->coop_dev + c->pgrp_off),
+                                                 c->coop_dev + c->pwg_off, c->pwg_n, st)))
                 launch_pw(c->P, c->D, sw, c->nsys, st);
         }
         c->sweep++;

@@ -24,6 +24,20 @@ constexpr int CNT_REBUILD = 139;
 constexpr int CNT_ACCEPTED = 140;
 constexpr int CNT_TOTAL = 160;
 
+// Cooperative launches: groups of co-resident workgroups, each group on one (system, cell) of a
+// colour phase or on one system's plane waves. A group owns workgroups [first, first + size)
+// of the launch and the same range of per-workgroup result slots; its barrier counters are
+// gbar[2 (1 + group index) ..].
+struct CoopGroup {
+    int32_t sys, local, first, size;
+};
+constexpr int COOP_SLOTS = 1024;      // workgroups of one cooperative launch at most
+constexpr int CELL_GROUP_MAX = 32;    // workgroups per cell group (barrier cost grows with it)
+constexpr int CELL_GROUP_BEADS = 1024;
+constexpr int PW_GROUP_MAX = 128;     // workgroups per plane-wave group
+constexpr int PW_GROUP_BEADS = 256;
+constexpr int COOP_LIST_CAP = 4096;  // list entries one workgroup of a cell group holds (LDS)
+
 // kernel variants of the cell phase: threads per workgroup and LDS list capacities
 enum Variant { V64 = 0, V256 = 1, V1024 = 2 };
 
@@ -83,10 +97,9 @@ struct DevPtrs {
     double* slot_MX;            // global member positions (3 * slot_len per slot)
     int64_t slot_len;
     double* pw_new;             // plane-wave trial positions [3N]
-    double* pw_part;            // per-workgroup dU partial sums, two buffers of 1024
     unsigned* gbar;             // grid barrier: arrivals, generation
-    int32_t* coop_i;            // per-workgroup counts of the grid-wide cell phase [256]
-    double* coop_d;             // per-workgroup partial results of the grid-wide cell phase [5][256]
+    int32_t* coop_i;            // per-workgroup counts of the cooperative kernels [COOP_SLOTS]
+    double* coop_d;             // per-workgroup partial results [5][COOP_SLOTS]
     double* igrid;              // infinite-system grid of the current level: o[3], n[3]
     int64_t total_fine;
 };
@@ -97,9 +110,12 @@ void launch_bbox(const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
 void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
                   const int32_t* bmap, int nblocks, hipStream_t st);
 void launch_pw(const DevParams& P, const DevPtrs& D, int64_t sweep, int nsys, hipStream_t st);
-bool launch_pw_coop(const DevParams& P, const DevPtrs& D, int64_t sweep, int64_t N, hipStream_t st);
-bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep, int64_t N,
-                      hipStream_t st);
+bool launch_pw_coop(const DevParams& P, const DevPtrs& D, int64_t sweep, const CoopGroup* groups,
+                    const int32_t* wg_group, int nwg, hipStream_t st);
+bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
+                      const CoopGroup* groups, const int32_t* wg_group, int nwg, hipStream_t st);
+int cell_coop_blocks();
+int pw_coop_blocks();
 void launch_rg2(const DevPtrs& D, const int64_t* chain_off, int64_t n_chains, double* out, hipStream_t st);
 void launch_cell_ids(const DevParams& P, const DevPtrs& D, int sys, int level, int64_t sweep, int64_t n, int32_t* out,
                      hipStream_t st);

@@ -58,20 +58,32 @@ def make_solution(n_chains: int, n_beads, box_L: float, seed: int, bond: float =
     i = 0
     offsets = [0]
     for n in lens:
-        for b in range(n):
-            for attempt in range(10000):
-                if b == 0:
-                    p = rng.uniform(0.0, L, 3)
+        # a walk that traps its own end is withdrawn and regrown from a new start
+        for restart in range(100):
+            start = i
+            ok = True
+            for b in range(n):
+                for attempt in range(10000):
+                    if b == 0:
+                        p = rng.uniform(0.0, L, 3)
+                    else:
+                        u = rng.normal(size=3)
+                        p = pos[i - 1] + bond * u / np.linalg.norm(u)
+                    if free(p):
+                        break
                 else:
-                    u = rng.normal(size=3)
-                    p = pos[i - 1] + bond * u / np.linalg.norm(u)
-                if free(p):
+                    ok = False
                     break
-            else:
-                raise RuntimeError("random walk stuck: box too dense")
-            pos[i] = p
-            grid.setdefault(_cell_key(p, h, ncell), []).append(i)
-            i += 1
+                pos[i] = p
+                grid.setdefault(_cell_key(p, h, ncell), []).append(i)
+                i += 1
+            if ok:
+                break
+            for j in range(start, i):
+                grid[_cell_key(pos[j], h, ncell)].remove(j)
+            i = start
+        else:
+            raise RuntimeError("random walk stuck: box too dense")
         offsets.append(i)
     return {"pos": pos, "chain_offset": np.array(offsets, dtype=np.int64), "box_L": L}
 
@@ -147,3 +159,16 @@ def config(index: int, scale: float = 1.0, seed: int | None = None) -> dict:
                     params=params, pos=s["pos"], chain_offset=s["chain_offset"],
                     sys_offset=np.array([0, nch * nb]))
     raise ValueError(index)
+
+
+def replicas(index: int, count: int, scale: float = 1.0) -> dict:
+    """``count`` independent copies of workload ``index`` (each from its own starting state) as
+    one batch of systems; copy 0 is ``config(index, scale)`` itself."""
+    cs = [config(index, scale, seed=BASE_SEED + index + 1000 * r) for r in range(count)]
+    so, co = [0], [0]
+    for c in cs:
+        co += list(np.asarray(c["chain_offset"][1:]) + so[-1])
+        so.append(so[-1] + int(c["sys_offset"][-1]))
+    return dict(name=f"{count} copies of: {cs[0]['name']}", params=cs[0]["params"],
+                pos=np.concatenate([c["pos"] for c in cs]), chain_offset=np.array(co, dtype=np.int64),
+                sys_offset=np.array(so, dtype=np.int64))

@@ -80,6 +80,24 @@ def test_sweep_parity(index, scale, sweeps, precision):
     np.testing.assert_allclose(g.chain_rg2(), o.chain_rg2(), rtol=1e-10)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_copies_parity(precision):
+    """Three 8192-bead semi-dilute systems in one batch: every colour phase of the top levels and
+    the plane waves run as several cooperative groups in one launch."""
+    from paper_1611_09160_amd import workloads as W
+
+    cfg = W.replicas(3, 3, 0.25)
+    g, o = build_pair(cfg, precision=precision, trace=2_000_000)
+    g.sweep(1)
+    o.sweep(1)
+    tol = dict(dU_rtol=1e-5, dU_atol=1e-4, dU_atol_member=1e-5) if precision == "mixed" else {}
+    stats = compare_traces(g.trace(2_000_000), o.trace(2_000_000), **tol)
+    assert stats["moves"] > 0
+    compare_positions(g.positions(), o.positions())
+    compare_counters(g.observables(), o.observables())
+    np.testing.assert_allclose(g.tau(), o.tau(), rtol=1e-12)
+
+
 def test_mixed_rechecks_near_threshold():
     cfg = _workload(3, 0.0625)
     g, _ = build_pair(cfg, precision="mixed", trace=0)
