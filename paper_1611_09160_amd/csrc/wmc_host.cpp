@@ -551,7 +551,7 @@ static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
     c->coop_host.clear();
     auto& H = c->coop_host;
     std::vector<int32_t> tiles;
-    const int ccap = c->P.periodic ? cell_coop_blocks() : 0;
+    const int ccap = c->P.periodic ? std::min(cell_coop_blocks(), CELL_LAUNCH_MAX) : 0;
     for (int l = 0; l < WMC_MAX_LEVELS; ++l)
         for (int col = 0; col < 8; ++col) {
             c->cwg_n[l][col] = 0;
@@ -591,7 +591,7 @@ static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
         std::vector<int64_t> Ns(c->nsys);
         for (int s = 0; s < c->nsys; ++s) Ns[s] = c->sys[s].N;
         std::vector<int> G(c->nsys);
-        if (size_groups(G, Ns, PW_GROUP_BEADS, PW_GROUP_MAX, pw_coop_blocks(), 0)) {
+        if (size_groups(G, Ns, PW_GROUP_BEADS, PW_GROUP_MAX, std::min(pw_coop_blocks(), PW_LAUNCH_MAX), 0)) {
             int first = 0;
             c->pgrp_off = (int64_t)H.size();
             for (int s = 0; s < c->nsys; ++s) {

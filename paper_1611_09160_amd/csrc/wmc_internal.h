@@ -31,11 +31,27 @@ constexpr int CNT_TOTAL = 160;
 struct CoopGroup {
     int32_t sys, local, first, size;
 };
+// Group and launch sizes: a barrier costs more the more workgroups of a group arrive, and every
+// arriving workgroup writes back its L2, so a launch is also capped in total.
+#ifndef WMC_CELL_GROUP_MAX
+#define WMC_CELL_GROUP_MAX 16
+#endif
+#ifndef WMC_CELL_LAUNCH_MAX
+#define WMC_CELL_LAUNCH_MAX 256
+#endif
+#ifndef WMC_PW_GROUP_MAX
+#define WMC_PW_GROUP_MAX 128
+#endif
+#ifndef WMC_PW_LAUNCH_MAX
+#define WMC_PW_LAUNCH_MAX 512
+#endif
 constexpr int COOP_SLOTS = 1024;      // workgroups of one cooperative launch at most
-constexpr int CELL_GROUP_MAX = 32;    // workgroups per cell group (barrier cost grows with it)
-constexpr int CELL_GROUP_BEADS = 1024;
-constexpr int PW_GROUP_MAX = 128;     // workgroups per plane-wave group
-constexpr int PW_GROUP_BEADS = 256;
+constexpr int CELL_GROUP_MAX = WMC_CELL_GROUP_MAX;    // workgroups per cell group
+constexpr int CELL_LAUNCH_MAX = WMC_CELL_LAUNCH_MAX;  // workgroups per cell-group launch
+constexpr int CELL_GROUP_BEADS = 1024;                // beads per workgroup of a cell group
+constexpr int PW_GROUP_MAX = WMC_PW_GROUP_MAX;        // workgroups per plane-wave group
+constexpr int PW_LAUNCH_MAX = WMC_PW_LAUNCH_MAX;      // workgroups per plane-wave launch
+constexpr int PW_GROUP_BEADS = 256;                   // beads per workgroup of a plane-wave group
 constexpr int COOP_LIST_CAP = 4096;  // list entries one workgroup of a cell group holds (LDS)
 
 // kernel variants of the cell phase: threads per workgroup and LDS list capacities

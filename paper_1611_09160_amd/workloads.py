@@ -172,3 +172,24 @@ def replicas(index: int, count: int, scale: float = 1.0) -> dict:
     return dict(name=f"{count} copies of: {cs[0]['name']}", params=cs[0]["params"],
                 pos=np.concatenate([c["pos"] for c in cs]), chain_offset=np.array(co, dtype=np.int64),
                 sys_offset=np.array(so, dtype=np.int64))
+
+
+def batch_semidilute(n_systems: int, n_chains: int, n_beads: int = 128, seed: int | None = None) -> dict:
+    """``n_systems`` independent semi-dilute solutions of ``n_chains`` x ``n_beads`` FENE + WCA
+    chains, each in its own periodic box at the bead density of the 32,768-bead solution in
+    L = 84 (that solution cut into smaller systems of the same chains and concentration),
+    lambda 1 .. L/4, plane waves."""
+    base = BASE_SEED + 30 if seed is None else seed
+    pos, so, co, Ls = [], [0], [0], []
+    for i in range(n_systems):
+        L = round(84.0 * (n_chains * n_beads / 32768.0) ** (1.0 / 3.0), 3)
+        s = make_solution(n_chains, n_beads, L, base + 7919 * i)
+        pos.append(s["pos"])
+        co += list(s["chain_offset"][1:] + so[-1])
+        so.append(so[-1] + n_chains * n_beads)
+        Ls.append(L)
+    params = dict(KG, periodic=1, plane_waves=1, box_L=Ls[0], lambda_max=Ls[0] / 4, seed=base)
+    return dict(name=f"{n_systems} semi-dilute systems of {n_chains}x{n_beads} beads, FENE+WCA, L={Ls[0]:g}, "
+                     f"c/c*~1, lambda 1..L/4, plane waves",
+                params=params, pos=np.concatenate(pos), chain_offset=np.array(co, dtype=np.int64),
+                sys_offset=np.array(so, dtype=np.int64))
