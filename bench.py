@@ -25,23 +25,23 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(cls: str, N: int, n_fine: int, pw_attempts_per_launch: float) -> float:
-    """Bytes one launch of a kernel class must move at minimum.
+def algorithmic_bytes_per_sweep(cls: str, N: int, n_fine: int, pw_attempts_per_sweep: float) -> float:
+    """Bytes one sweep's launches of a kernel class must move at minimum.
 
-    level phases: each of the 8 colour phases of a level reads and writes the positions of
-      its share of the beads once and re-reads the neighbour-grid entries (4 B index + 4 B
-      cell start): N (24 + 24 + 8) / 8 per launch.
-    grid: read positions, write the reference copy and the cell of every bead, count, scan,
-      scatter and sort: N (24 + 24 + 4 + 4 + 8 + 8) + 12 n_fine.
+    level passes: every bead's position is read and written once per level, plus its
+      neighbour-grid entry (4 B index + 4 B cell start): N (24 + 24 + 8).
+    grid: per build read positions, write the reference copy and the cell of every bead, count,
+      scan, scatter and sort: N (24 + 24 + 4 + 4 + 8 + 8) + 12 n_fine (6 builds per sweep here,
+      one per level and one before the plane waves; the caller passes the build count).
     plane waves: per test read positions, write and re-read trial positions, read the
       neighbour grid and write accepted positions: N (24 + 24 + 24 + 8 + 24).
     """
     if cls.startswith("level"):
-        return N * (24 + 24 + 8) / 8.0
+        return N * (24 + 24 + 8)
     if cls == "grid":
         return N * (24 + 24 + 4 + 4 + 8 + 8) + 12.0 * n_fine
     if cls == "plane_waves":
-        return N * (24 + 24 + 24 + 8 + 24) * pw_attempts_per_launch
+        return N * (24 + 24 + 24 + 8 + 24) * pw_attempts_per_sweep
     return 0.0
 
 
@@ -125,14 +125,18 @@ def main():
     start = g64.positions()
     sweep0 = args.equilibrate + args.warmup + args.steps
     gm, rmix = run_gpu(cfg, "mixed", 0, args.warmup, args.steps, start=start)
-    # roofline of the dominant kernel class of the FP64 run
+    # roofline of the dominant kernel class of the FP64 run (a level's LDS-tile cells run as one
+    # launch per sweep; its global-list cells, if any, as one launch per colour)
     kt = r64["kernel_ms"]
     n_fine = 55 ** 3
-    pw_per_launch = r64["pw_attempts"] / max(1, kt.get("plane_waves", (0, 1))[1])
+    steps = r64["steps"]
     dom = max(kt, key=lambda k: kt[k][0])
     ms, launches = kt[dom]
+    per_sweep = algorithmic_bytes_per_sweep(dom, N, n_fine, r64["pw_attempts"] / steps)
+    if dom == "grid":
+        per_sweep *= launches / steps
+    alg = per_sweep * steps / launches
     avg_s = ms / 1000.0 / launches
-    alg = algorithmic_bytes(dom, N, n_fine, pw_per_launch)
     achieved = alg / avg_s / 1e9
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 3), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=achieved / HBM_PEAK_GBS, traffic=None, avg_launch_us=round(avg_s * 1e6, 2),

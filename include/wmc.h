@@ -105,6 +105,8 @@ typedef struct {
     int64_t rechecks;                     /* WMC_MIXED: decisions re-evaluated in FP64 */
     int64_t overflows;                    /* cell lists that exceeded capacity (must be 0) */
     int64_t grid_rebuilds;                /* neighbour-grid rebuilds */
+    int64_t wait_timeouts;                /* dependency waits between cells that hit their bound
+                                             (must be 0; the pass then ran out of order) */
 } wmc_obs;
 
 /* One trace record per Metropolis test (kind 0 wavelet, 2 plane wave) and per cell phase

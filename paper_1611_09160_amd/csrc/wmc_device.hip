@@ -536,7 +536,10 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, un
             __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) __builtin_amdgcn_s_sleep(2);
+            // spin on relaxed loads (an acquiring load would invalidate the L2 on every poll), then
+            // acquire once
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
     }
     gen = gen + 1u;
@@ -1646,6 +1649,87 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
     else
         hipLaunchKernelGGL((k_phase<512, 8192, 4096, 4096, 0, 13>), dim3(nblocks), dim3(512), 0, st, P, D, level,
                            colour, sweep, bmap, nblocks);
+}
+
+// ------------------------------------------- level pass in dependency order (LDS tiles)
+// The colour phases of a level ask only that adjacent cells run in colour order: same-colour
+// cells are independent and cells further apart than one cell never interact. So one launch
+// runs every LDS-tile cell of the level: cells are handed out in colour order through an
+// atomic counter, and a cell first waits until each adjacent cell of a lower colour has
+// published this pass's epoch. A workgroup waits only on cells handed out before its own,
+// whose workgroups are already running, so the pass cannot deadlock; the wait is still bounded
+// (counted in CNT_FLOWWAIT when the bound is hit). Same result as eight colour phases.
+constexpr unsigned FLOW_SPIN_LIMIT = 1u << 24;
+
+template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD>
+__global__ __launch_bounds__(W) void k_level_flow(DevParams P, DevPtrs D, int level, int64_t sweep,
+                                                  const int32_t* items, FlowArgs fa) {
+    __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD> sh;
+    __shared__ int s_idx;
+    __shared__ int s_timeout;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        s_idx = (int)(atomicAdd(&D.flow_ctr[level], 1ull) - fa.qbase);
+        s_timeout = 0;
+    }
+    __syncthreads();
+    const int idx = s_idx;
+    if (idx < 0 || idx >= fa.nitems) return;
+    int colour = 0;
+    while (colour < 7 && idx >= fa.colour_end[colour]) ++colour;
+    const int sys = items[2 * idx], local = items[2 * idx + 1];
+    const SysDesc& s = D.sys[sys];
+    const LevelDesc& lv = D.lev[s.lvl_off + level];
+    Grid g;
+    make_grid(P, D, s, lv, sys, level, sweep, g);
+    int64_t ic[3];
+    cell_coords(P, lv, g, colour, local, ic);
+    const int n = lv.n;
+    // adjacent cells of lower colours (n >= 4: the 26 neighbours are distinct)
+    if (tid < 27 && tid != 13) {
+        const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = tid / 9 - 1;
+        const int jx = (int)((ic[0] + dx + n) % n), jy = (int)((ic[1] + dy + n) % n), jz = (int)((ic[2] + dz + n) % n);
+        const int cn = (jx & 1) | ((jy & 1) << 1) | ((jz & 1) << 2);
+        if (cn < colour) {
+            const int32_t* f = D.cell_done + lv.flag_base + jx + (int64_t)n * (jy + (int64_t)n * jz);
+            unsigned spins = 0;
+            while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != fa.epoch) {
+                if (++spins >= FLOW_SPIN_LIMIT) {
+                    s_timeout = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && s_timeout) atomicAdd(&D.cnt[CNT_FLOWWAIT], 1ull);
+    if (!process_cell_tile<W, CAPH, CAPMT, NCD>(P, D, sh.t, sys, level, colour, local, sweep, g)) {
+        __syncthreads();
+        process_cell<W, CAPS, CAPM>(P, D, sh.g, sys, level, colour, local, sweep, g);
+    }
+    // publish: every wave's stores complete, then one release of the epoch
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (tid == 0) {
+        int32_t* f = D.cell_done + lv.flag_base + ic[0] + (int64_t)n * (ic[1] + (int64_t)n * ic[2]);
+        __hip_atomic_store(f, fa.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
+                       const int32_t* items, const FlowArgs& fa, hipStream_t st) {
+    if (fa.nitems <= 0) return;
+    if (variant == V64)
+        hipLaunchKernelGGL((k_level_flow<64, 512, 128, 512, 128, 8>), dim3(fa.nitems), dim3(64), 0, st, P, D, level,
+                           sweep, items, fa);
+    else if (variant == V256)
+        hipLaunchKernelGGL((k_level_flow<256, 4096, 1024, 1024, 512, 12>), dim3(fa.nitems), dim3(256), 0, st, P, D,
+                           level, sweep, items, fa);
+    else
+        hipLaunchKernelGGL((k_level_flow<512, 8192, 4096, 4096, 0, 13>), dim3(fa.nitems), dim3(512), 0, st, P, D,
+                           level, sweep, items, fa);
 }
 
 // ------------------------------------------------- cell phase of a large level, grid-wide

@@ -40,8 +40,12 @@ struct wmc_ctx {
     std::vector<int32_t> bmap_host;
     int64_t bmap_off[WMC_MAX_LEVELS][8];  // every cell of the colour
     int32_t bmap_n[WMC_MAX_LEVELS][8];
-    int64_t tile_off[WMC_MAX_LEVELS][8];  // the cells left to k_phase when the groups run
+    int64_t tile_off[WMC_MAX_LEVELS][8];  // LDS-tile cells (run by the dependency-ordered pass)
     int32_t tile_n[WMC_MAX_LEVELS][8];
+    int64_t glob_off[WMC_MAX_LEVELS][8];  // global-list cells (cooperative groups or k_phase)
+    int32_t glob_n[WMC_MAX_LEVELS][8];
+    unsigned long long flow_handed[WMC_MAX_LEVELS] = {0};  // cells handed out per level so far
+    int32_t flow_epoch = 0;
     int32_t* bmap_dev;
     // cooperative groups (int32 table: CoopGroup records, then the workgroup -> group map)
     std::vector<int32_t> coop_host;
@@ -232,10 +236,10 @@ struct Layout {
 
 // everything the arena holds, computed identically by wmc_arena_bytes and wmc_init
 struct Plan {
-    int64_t N = 0, total_fine = 0, slots = 0, slot_len = 0, pool_cube = 0, pool_shell = 0, n_chains = 0, bmap = 0, coop_ints = 0;
+    int64_t N = 0, total_fine = 0, slots = 0, slot_len = 0, pool_cube = 0, pool_shell = 0, n_chains = 0, bmap = 0, coop_ints = 0, flags = 0;
     int nsys = 0, total_levels = 0;
     size_t off_x, off_xb, off_bond, off_sysid, off_tag, off_fcount, off_fstart, off_fidx, off_fcell, off_drift,
-        off_cnt, off_sysacc, off_fblock, off_gbar, off_coop, off_cooptab, off_trace, off_tracen, off_cube, off_shell, off_slotS, off_slotM, off_slotMX, off_pw,
+        off_cnt, off_sysacc, off_fblock, off_gbar, off_coop, off_cooptab, off_flags, off_flowctr, off_trace, off_tracen, off_cube, off_shell, off_slotS, off_slotM, off_slotMX, off_pw,
         off_igrid, off_sys, off_lev, off_bmap, off_choff, off_rg2;
     size_t bytes = 0;
 };
@@ -300,7 +304,7 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
     std::vector<SysDesc> sys(nsys);
     std::vector<LevelDesc> lev;
     std::map<double, int> pw_by_ratio;
-    int64_t fine = 0, slots = 0, cube_pool = 0, shell_pool = 0, slot_len = 0;
+    int64_t fine = 0, slots = 0, cube_pool = 0, shell_pool = 0, slot_len = 0, flags = 0;
     const double lam_a = 2.0 / kPi * M4() / M3();
     for (int s = 0; s < nsys; ++s) {
         SysDesc& d = sys[s];
@@ -431,6 +435,8 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
                 slots += cells_per_colour;
                 slot_len = std::max(slot_len, (int64_t)d.N);
             }
+            L.flag_base = flags;
+            if (p->periodic) flags += (int64_t)std::max(L.n, 1) * std::max(L.n, 1) * std::max(L.n, 1);
             lev.push_back(L);
             lout.insert(lout.end(), {L.lo, L.hi, L.p, L.T, L.h, (double)L.n});
             ++nl;
@@ -447,6 +453,7 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
     pl.total_fine = fine;
     pl.slots = slots;
     pl.slot_len = slot_len;
+    pl.flags = flags;
     pl.pool_cube = cube_pool;
     pl.pool_shell = shell_pool;
     pl.total_levels = (int)lev.size();
@@ -495,9 +502,11 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
     pl.off_gbar = lay.add(2 * (1 + COOP_SLOTS) * 4);
     pl.off_coop = lay.add(COOP_SLOTS * 4 + 5 * COOP_SLOTS * 8);
     pl.off_cooptab = lay.add(pl.coop_ints * 4);
+    pl.off_flags = lay.add(std::max<int64_t>(pl.flags, 1) * 4);
+    pl.off_flowctr = lay.add(WMC_MAX_LEVELS * 8);
     pl.off_sys = lay.add(nsys * sizeof(SysDesc));
     pl.off_lev = lay.add(lev.size() * sizeof(LevelDesc));
-    pl.off_bmap = lay.add(std::max<int64_t>(bm, 1) * 2 * 2 * 4);
+    pl.off_bmap = lay.add(std::max<int64_t>(bm, 1) * 3 * 2 * 4);
     pl.off_choff = lay.add((n_chains + 1) * 8);
     pl.off_rg2 = lay.add(std::max<int64_t>(n_chains, 1) * 8);
     pl.bytes = lay.total + 256;
@@ -571,6 +580,9 @@ static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
             c->tile_off[l][col] = (int64_t)c->bmap_host.size() / 2;
             c->tile_n[l][col] = (int32_t)(tiles.size() / 2);
             c->bmap_host.insert(c->bmap_host.end(), tiles.begin(), tiles.end());
+            c->glob_off[l][col] = (int64_t)c->bmap_host.size() / 2;
+            c->glob_n[l][col] = (int32_t)glob.size();
+            for (auto& e : glob) c->bmap_host.insert(c->bmap_host.end(), {e.first, e.second});
             if (glob.empty()) continue;
             std::vector<int64_t> Ns(glob.size());
             for (size_t i = 0; i < glob.size(); ++i) Ns[i] = c->sys[glob[i].first].N;
@@ -718,6 +730,8 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     D.coop_i = (int32_t*)(base + pl.off_coop);
     D.coop_d = (double*)(base + pl.off_coop + COOP_SLOTS * 4);
     c->coop_dev = (int32_t*)(base + pl.off_cooptab);
+    D.cell_done = (int32_t*)(base + pl.off_flags);
+    D.flow_ctr = (unsigned long long*)(base + pl.off_flowctr);
     D.sys = (const SysDesc*)(base + pl.off_sys);
     D.lev = (const LevelDesc*)(base + pl.off_lev);
     D.total_fine = pl.total_fine;
@@ -834,20 +848,32 @@ extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
                     Timed t(c, 0, st);
                     launch_fine_build(c->P, c->D, c->N, st);
                 }
+                // LDS-tile cells of every colour in one dependency-ordered pass (their tile lists
+                // are consecutive in the block map, colour by colour)
+                FlowArgs fa;
+                fa.nitems = 0;
                 for (int col = 0; col < 8; ++col) {
-                    if (c->bmap_n[l][col] <= 0) continue;
+                    fa.nitems += c->tile_n[l][col];
+                    fa.colour_end[col] = fa.nitems;
+                }
+                if (fa.nitems > 0) {
                     Timed t(c, 1 + l, st);
-                    // global-list cells as cooperative groups, the other cells one workgroup each
+                    fa.epoch = ++c->flow_epoch;
+                    fa.qbase = c->flow_handed[l];
+                    c->flow_handed[l] += (unsigned long long)fa.nitems;
+                    launch_level_flow(c->phase_variant[l], c->P, c->D, l, sw, c->bmap_dev + 2 * c->tile_off[l][0], fa,
+                                      st);
+                }
+                // global-list cells colour by colour: cooperative groups, else one workgroup each
+                for (int col = 0; col < 8; ++col) {
+                    if (c->glob_n[l][col] <= 0) continue;
+                    Timed t(c, 1 + l, st);
                     if (c->cwg_n[l][col] > 0 &&
                         launch_cell_coop(c->P, c->D, l, col, sw, (const CoopGroup*)(c->coop_dev + c->cgrp_off[l][col]),
-                                         c->coop_dev + c->cwg_off[l][col], c->cwg_n[l][col], st)) {
-                        if (c->tile_n[l][col] > 0)
-                            launch_phase(c->phase_variant[l], c->P, c->D, l, col, sw,
-                                         c->bmap_dev + 2 * c->tile_off[l][col], c->tile_n[l][col], st);
+                                         c->coop_dev + c->cwg_off[l][col], c->cwg_n[l][col], st))
                         continue;
-                    }
-                    launch_phase(c->phase_variant[l], c->P, c->D, l, col, sw, c->bmap_dev + 2 * c->bmap_off[l][col],
-                                 c->bmap_n[l][col], st);
+                    launch_phase(c->phase_variant[l], c->P, c->D, l, col, sw, c->bmap_dev + 2 * c->glob_off[l][col],
+                                 c->glob_n[l][col], st);
                 }
             } else {
                 launch_bbox(c->P, c->D, l, sw, st);
@@ -958,6 +984,7 @@ extern "C" int wmc_observables(wmc_ctx* c, wmc_obs* o) {
     o->rechecks = cnt[CNT_RECHECK];
     o->grid_rebuilds = cnt[CNT_REBUILD];
     o->accepted_total = cnt[CNT_ACCEPTED];
+    o->wait_timeouts = cnt[CNT_FLOWWAIT];
     return 0;
 }
 

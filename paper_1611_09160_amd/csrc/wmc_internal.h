@@ -22,6 +22,7 @@ constexpr int CNT_OVERFLOW = 137;
 constexpr int CNT_RECHECK = 138;
 constexpr int CNT_REBUILD = 139;
 constexpr int CNT_ACCEPTED = 140;
+constexpr int CNT_FLOWWAIT = 141;   // dependency waits that hit their spin limit (must be 0)
 constexpr int CNT_TOTAL = 160;
 
 // Cooperative launches: groups of co-resident workgroups, each group on one (system, cell) of a
@@ -80,6 +81,7 @@ struct LevelDesc {
     int32_t identity;      // the cell holds every bead (n == 1)
     int32_t use_global;    // reach and member lists in global slots
     int64_t slot_base;     // first global slot of this (system, level)
+    int64_t flag_base;     // first done-flag of this (system, level)'s cells
 };
 
 struct DevParams {
@@ -114,6 +116,8 @@ struct DevPtrs {
     int64_t slot_len;
     double* pw_new;             // plane-wave trial positions [3N]
     unsigned* gbar;             // grid barrier: arrivals, generation
+    int32_t* cell_done;         // per (system, level, cell): epoch of its last completed pass
+    unsigned long long* flow_ctr;  // per level: cells handed out by the dependency-ordered kernel
     int32_t* coop_i;            // per-workgroup counts of the cooperative kernels [COOP_SLOTS]
     double* coop_d;             // per-workgroup partial results [5][COOP_SLOTS]
     double* igrid;              // infinite-system grid of the current level: o[3], n[3]
@@ -125,6 +129,15 @@ void launch_fine_build(const DevParams& P, const DevPtrs& D, int64_t N, hipStrea
 void launch_bbox(const DevParams& P, const DevPtrs& D, int level, int64_t sweep, hipStream_t st);
 void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
                   const int32_t* bmap, int nblocks, hipStream_t st);
+// One level pass of LDS-tile cells in dependency order (all colours in one launch).
+struct FlowArgs {
+    int32_t colour_end[8];   // items [colour_end[c-1], colour_end[c]) have colour c
+    int32_t nitems;
+    int32_t epoch;           // value a completed cell publishes; never reused within a context
+    unsigned long long qbase;  // flow_ctr[level] before this launch
+};
+void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
+                       const int32_t* items, const FlowArgs& fa, hipStream_t st);
 void launch_pw(const DevParams& P, const DevPtrs& D, int64_t sweep, int nsys, hipStream_t st);
 bool launch_pw_coop(const DevParams& P, const DevPtrs& D, int64_t sweep, const CoopGroup* groups,
                     const int32_t* wg_group, int nwg, hipStream_t st);

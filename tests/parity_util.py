@@ -64,3 +64,4 @@ def compare_counters(og, oo):
               "accepted_total"):
         assert og[k] == oo[k], (k, og[k], oo[k])
     assert og["overflows"] == 0
+    assert og.get("wait_timeouts", 0) == 0
