@@ -10,6 +10,11 @@ A step is one sweep. Prints one JSON line:
   tau_per_wall_s  physical time (units of tau) advanced per wall-clock second
   roofline      the dominant kernel class, timed with HIP events on the library's stream
   cpu_baseline  the FP64 oracle on the host, on a bounded sample of sweeps of the same state
+  mixed         the same system in mixed precision (FP32 energy terms, FP64 recheck near the
+                threshold), from the FP64 run's final state
+  batched       mixed precision on many systems at once: 8 independent copies of the solution,
+                and the 32,768 beads as 8 smaller solutions of the same chains and concentration;
+                ratio_vs_fp64 compares with the single-system FP64 value
 """
 from __future__ import annotations
 
@@ -80,6 +85,19 @@ def run_gpu(cfg, precision: str, equilibrate: int, warmup: int, steps: int, star
     return g, res
 
 
+def run_batched(cfg, precision: str, equilibrate: int, warmup: int, steps: int) -> dict:
+    """Many independent systems advanced together (one launch per level and colour serves all)."""
+    g, r = run_gpu(cfg, precision, equilibrate, warmup, steps)
+    nsys = len(cfg["sys_offset"]) - 1
+    out = dict(value=round(r["bead_updates_per_s"], 1), unit="bead-updates/s", ms_per_step=round(r["ms_per_step"], 3),
+               systems=nsys, beads=int(cfg["sys_offset"][-1]), precision=precision,
+               tau_per_wall_s_per_system=round(r["tau_per_wall_s"] / nsys, 4),
+               tau_per_wall_s_total=round(r["tau_per_wall_s"], 4), overflows=r["overflows"],
+               kernel_ms={k: [round(v[0], 3), v[1]] for k, v in r["kernel_ms"].items()})
+    g.close()
+    return out
+
+
 def run_oracle(cfg, start, sweep0: int, budget_s: float):
     from oracle import oracle as O
 
@@ -108,6 +126,8 @@ def main():
     ap.add_argument("--equilibrate", type=int, default=200)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-equilibrate", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built.",
@@ -142,6 +162,18 @@ def main():
                 frac=achieved / HBM_PEAK_GBS, traffic=None, avg_launch_us=round(avg_s * 1e6, 2),
                 launches=launches, algorithmic_bytes_per_launch=int(alg),
                 share_of_step=round(ms / (r64["seconds"] * 1000.0), 3))
+    batched = None
+    if not args.no_batched:
+        g64.close()
+        gm.close()
+        copies = run_batched(W.replicas(3, 8), "mixed", args.batch_equilibrate, args.warmup, args.steps)
+        split = run_batched(W.batch_semidilute(8, 32), "mixed", args.batch_equilibrate, args.warmup, args.steps)
+        ref = r64["bead_updates_per_s"]
+        copies["ratio_vs_fp64"] = round(copies["value"] / ref, 3)
+        split["ratio_vs_fp64"] = round(split["value"] / ref, 3)
+        copies["workload"] = "8 independent copies of the 32,768-bead solution (each its own start)"
+        split["workload"] = "the 32,768 beads as 8 solutions of 32 x 128 beads, L = 42, same concentration"
+        batched = dict(copies=copies, split_32k=split)
     cpu = None
     if not args.no_cpu:
         cpu = run_oracle(cfg, start, sweep0, args.cpu_budget)
@@ -158,6 +190,7 @@ def main():
         mixed=dict(value=round(rmix["bead_updates_per_s"], 1), ms_per_step=round(rmix["ms_per_step"], 3),
                    tau_per_wall_s=round(rmix["tau_per_wall_s"], 4), rechecks=rmix["rechecks"],
                    ratio_vs_fp64=round(rmix["bead_updates_per_s"] / r64["bead_updates_per_s"], 3)),
+        batched=batched,
         kernel_ms_fp64={k: [round(v[0], 3), v[1]] for k, v in kt.items()},
         checks=dict(overflows=r64["overflows"] + rmix["overflows"], violations=r64["violations"]),
     )
