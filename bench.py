@@ -29,6 +29,22 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by a plain copy of
+# known size (profiles/traffic_sweep_semidilute32k.md); valid only for the device source they
+# were measured on, otherwise the bench reports null
+TRAFFIC_SOURCE_SHA16 = "14df9b7d962a84c7"
+TRAFFIC_BYTES_PER_LAUNCH = {"level0": 192.10e6, "level1": 105.33e6, "level2": 44.35e6, "level3": 13.22e6,
+                            "level4": 13.22e6, "plane_waves": 28.93e6, "grid": 9.60e6}
+
+
+def measured_traffic(cls: str):
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1611_09160_amd", "csrc", "wmc_device.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return TRAFFIC_BYTES_PER_LAUNCH.get(cls) if sha == TRAFFIC_SOURCE_SHA16 else None
+
 
 def algorithmic_bytes_per_sweep(cls: str, N: int, n_fine: int, pw_attempts_per_sweep: float) -> float:
     """Bytes one sweep's launches of a kernel class must move at minimum.
@@ -128,7 +144,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-equilibrate", type=int, default=100)
+    ap.add_argument("--copy-check", type=int, default=0, metavar="MB",
+                    help="only copy a buffer of MB megabytes 4 times (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_check:
+        import torch
+
+        a = torch.ones(args.copy_check * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_check_bytes=a.numel() * 8, copies=4)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built.",
               file=sys.stderr)
@@ -158,8 +186,10 @@ def main():
     alg = per_sweep * steps / launches
     avg_s = ms / 1000.0 / launches
     achieved = alg / avg_s / 1e9
+    traffic = measured_traffic(dom)
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 3), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=achieved / HBM_PEAK_GBS, traffic=None, avg_launch_us=round(avg_s * 1e6, 2),
+                frac=achieved / HBM_PEAK_GBS, traffic=traffic, traffic_unit="bytes per launch",
+                avg_launch_us=round(avg_s * 1e6, 2),
                 launches=launches, algorithmic_bytes_per_launch=int(alg),
                 share_of_step=round(ms / (r64["seconds"] * 1000.0), 3))
     batched = None
