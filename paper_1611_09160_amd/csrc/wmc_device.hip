@@ -1402,40 +1402,46 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
     unsigned long long c_hits = 0, c_att = 0, c_acc = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0;
     double d_local = 0.0;
     const bool mixed = P.precision == WMC_MIXED;
-    for (int64_t t0 = 0; t0 < K;) {
-        int64_t t = t0 + tid;
-        bool hit = false;
-        double lam = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
-        int as = 0;
-        Stream st;
-        if (t < K && nS > 0) {
+    // trials are drawn W at a time (one per lane); the draws (lambda, anchor, ball vector, stream
+    // position) do not depend on positions, so a lane keeps its trial across the chains of earlier
+    // hits and only its hit test, which reads the anchor's current position, is repeated
+    for (int64_t t0 = 0; t0 < K; t0 += W) {
+        const int64_t t = t0 + tid;
+        const bool drawn = t < K && nS > 0;
+        double lam_t = 0.0, vx_t = 0.0, vy_t = 0.0, vz_t = 0.0;
+        int as_t = 0;
+        uint32_t next_t = 0;
+        if (drawn) {
+            Stream st;
             st.init(P, sys, sweep, level, cell, t, 0, 0);
-            lam = draw_lambda(st.co(), lv.lo, lv.hi);
-            as = sh.S[st.index(nS)];
-            double vx, vy, vz;
-            ball(st, vx, vy, vz);
-            bx = sh.x[as] + lam * vx;
-            by = sh.y[as] + lam * vy;
-            bz = sh.z[as] + lam * vz;
+            lam_t = draw_lambda(st.co(), lv.lo, lv.hi);
+            as_t = sh.S[st.index(nS)];
+            ball(st, vx_t, vy_t, vz_t);
+            next_t = st.next;
+        }
+      for (int from = 0;;) {
+        bool hit = false;
+        double bx = 0.0, by = 0.0, bz = 0.0;
+        if (drawn && tid >= from) {
+            bx = sh.x[as_t] + lam_t * vx_t;
+            by = sh.y[as_t] + lam_t * vy_t;
+            bz = sh.z[as_t] + lam_t * vz_t;
             hit = cell_of_point(g, bx, by, bz) == cell;
         }
-        int first = block_min_int<W>(hit ? (int)(t - t0) : 0x7FFFFFFF, sh.redi);
-        if (first == 0x7FFFFFFF) {
-            t0 += W;
-            continue;
-        }
+        int first = block_min_int<W>(hit ? tid : 0x7FFFFFFF, sh.redi);
+        if (first == 0x7FFFFFFF) break;
         if (tid == first) {
-            sh.pub_lam = lam;
-            sh.pub_a = as;
+            sh.pub_lam = lam_t;
+            sh.pub_a = as_t;
             sh.pub_b[0] = bx;
             sh.pub_b[1] = by;
             sh.pub_b[2] = bz;
-            sh.pub_next = st.next;
+            sh.pub_next = next_t;
         }
         __syncthreads();
         const int64_t tc = t0 + first;
-        lam = sh.pub_lam;
-        as = sh.pub_a;
+        double lam = sh.pub_lam;
+        int as = sh.pub_a;
         double b[3] = {sh.pub_b[0], sh.pub_b[1], sh.pub_b[2]};
         uint32_t nxt = sh.pub_next;
         int jtry = 0;
@@ -1541,14 +1547,16 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
                 ++c_caps;
                 break;
             }
+            // redraws in chunks: 16 tries first (the ball's rejection loop runs as long as its
+            // slowest lane, so a narrow first chunk is cheaper), then W at a time
             int found = -1;
-            for (int j0 = 0; j0 < 4096 && found < 0; j0 += W) {
+            for (int j0 = 0, len = W < 16 ? W : 16; j0 < 4096 && found < 0; j0 += len, len = W) {
                 int jj = j0 + tid;
                 bool h2 = false;
                 double ex = 0, ey = 0, ez = 0;
                 int a2 = 0;
                 Stream rs;
-                if (jj < 4096) {
+                if (tid < len && jj < 4096) {
                     rs.init(P, sys, sweep, level, cell, tc, r, jj);
                     a2 = sh.S[rs.index(nS)];
                     double vx, vy, vz;
@@ -1585,7 +1593,8 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
             jtry = found;
             __syncthreads();
         }
-        t0 = tc + 1;
+        from = first + 1;
+      }
     }
     d_local = block_max<W>(d_local, sh.red);
     unsigned long long viol_all = (unsigned long long)block_sum<W>((double)c_viol, sh.red);
