@@ -143,33 +143,41 @@ __device__ __forceinline__ double u_pair(const DevParams& P, double r2) {
     return 4.0 * P.eps * (s6 * s6 - s6 + 0.25);
 }
 
-// FP32 energy terms with an error bound, for WMC_MIXED (see k_phase)
-__device__ __forceinline__ float u_bond_f(const DevParams& P, float r2) {
-    float R02 = (float)P.R02;
+// FP32 term and its sensitivity together (mixed precision). The cut-off and the FENE limit are
+// applied to the FP64 r2, exactly as in the FP64 terms; the term is then evaluated in FP32. The
+// sensitivity only scales the recheck margin (64 ulp of it, about ten times the rounding it
+// covers), so FP32 suffices; a bond pushed to R0 by rounding gives an infinite term, which
+// forces the recheck.
+__device__ __forceinline__ float u_bond_fs(const DevParams& P, double r2, float& sens) {
     if (P.bond_type == WMC_BOND_FENE) {
-        if (r2 >= R02) return INFINITY;
-        return -0.5f * (float)P.k_bond * R02 * logf(1.0f - r2 / R02);
+        const float x = 1.0f - (float)r2 / (float)P.R02;
+        if (r2 >= P.R02 || x <= 0.0f) {
+            sens = INFINITY;
+            return INFINITY;
+        }
+        sens = 0.5f * (float)P.k_bond * (float)r2 / x;
+        return -0.5f * (float)P.k_bond * (float)P.R02 * logf(x);
     }
-    if (P.bond_type == WMC_BOND_HARMONIC) return 0.5f * (float)P.k_bond * r2;
+    if (P.bond_type == WMC_BOND_HARMONIC) {
+        sens = 0.5f * (float)P.k_bond * (float)r2;
+        return sens;
+    }
+    sens = 0.0f;
     return 0.0f;
 }
-__device__ __forceinline__ float u_pair_f(const DevParams& P, float r2) {
-    if (r2 >= (float)P.rc2) return 0.0f;
-    if (r2 <= 0.0f) return INFINITY;
-    float s2 = (float)P.sigma2 / r2;
-    float s6 = s2 * s2 * s2;
-    return 4.0f * (float)P.eps * (s6 * s6 - s6 + 0.25f);
-}
-// |dU/d(r2)| * r2, the sensitivity of a term to a relative error of r2
-__device__ __forceinline__ double sens_bond(const DevParams& P, double r2) {
-    if (P.bond_type == WMC_BOND_FENE) return r2 >= P.R02 ? INFINITY : 0.5 * P.k_bond * r2 / (1.0 - r2 / P.R02);
-    if (P.bond_type == WMC_BOND_HARMONIC) return 0.5 * P.k_bond * r2;
-    return 0.0;
-}
-__device__ __forceinline__ double sens_pair(const DevParams& P, double r2) {
-    if (r2 >= P.rc2) return 0.0;
-    double s2 = P.sigma2 / r2, s6 = s2 * s2 * s2;
-    return 4.0 * P.eps * (6.0 * s6 * s6 + 3.0 * s6);
+__device__ __forceinline__ float u_pair_fs(const DevParams& P, double r2, float& sens) {
+    if (r2 >= P.rc2) {
+        sens = 0.0f;
+        return 0.0f;
+    }
+    const float r2f = (float)r2;
+    if (r2f <= 0.0f) {
+        sens = INFINITY;
+        return INFINITY;
+    }
+    const float s2 = (float)P.sigma2 / r2f, s6 = s2 * s2 * s2, e4 = 4.0f * (float)P.eps;
+    sens = e4 * (6.0f * s6 * s6 + 3.0f * s6);
+    return e4 * (s6 * s6 - s6 + 0.25f);
 }
 
 // ------------------------------------------------------------------------------ geometry
@@ -603,8 +611,9 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
         const double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
         if (r2o < P.rc2 || r2n < P.rc2) {
             if (mode) {
-                acc += (double)(u_pair_f(P, (float)r2n) - u_pair_f(P, (float)r2o));
-                sens += sens_pair(P, r2n) + sens_pair(P, r2o);
+                float sn, so;
+                acc += (double)(u_pair_fs(P, r2n, sn) - u_pair_fs(P, r2o, so));
+                sens += (double)sn + (double)so;
             } else {
                 acc += u_pair(P, r2n) - u_pair(P, r2o);
             }
@@ -629,8 +638,9 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
                 const double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
                 if (r2o > P.r_int * P.r_int) ++viol;
                 if (mode) {
-                    acc += (double)(u_bond_f(P, (float)r2n) - u_bond_f(P, (float)r2o));
-                    sens += sens_bond(P, r2n) + sens_bond(P, r2o);
+                    float sn, so;
+                    acc += (double)(u_bond_fs(P, r2n, sn) - u_bond_fs(P, r2o, so));
+                    sens += (double)sn + (double)so;
                 } else {
                     acc += u_bond(P, r2n) - u_bond(P, r2o);
                 }
@@ -1252,8 +1262,9 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                 double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
                 if (r2o > P.r_int * P.r_int) ++viol;
                 if (mode) {
-                    acc += (double)(u_bond_f(P, (float)r2n) - u_bond_f(P, (float)r2o));
-                    sens += sens_bond(P, r2n) + sens_bond(P, r2o);
+                    float sn, so;
+                    acc += (double)(u_bond_fs(P, r2n, sn) - u_bond_fs(P, r2o, so));
+                    sens += (double)sn + (double)so;
                 } else {
                     acc += u_bond(P, r2n) - u_bond(P, r2o);
                 }
@@ -1289,8 +1300,9 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                 double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
                 if (r2o < P.rc2 || r2n < P.rc2) {
                     if (mode) {
-                        acc += (double)(u_pair_f(P, (float)r2n) - u_pair_f(P, (float)r2o));
-                        sens += sens_pair(P, r2n) + sens_pair(P, r2o);
+                        float sn, so;
+                        acc += (double)(u_pair_fs(P, r2n, sn) - u_pair_fs(P, r2o, so));
+                        sens += (double)sn + (double)so;
                     } else {
                         acc += u_pair(P, r2n) - u_pair(P, r2o);
                     }
