@@ -135,6 +135,16 @@ __device__ __forceinline__ double u_bond(const DevParams& P, double r2) {
     if (P.bond_type == WMC_BOND_HARMONIC) return 0.5 * P.k_bond * r2;
     return 0.0;
 }
+// U_bond(r2n) - U_bond(r2o) of one bond; for FENE one logarithm of the ratio of the two
+// (R0^2 - r^2) factors instead of two logarithms (equal up to rounding)
+__device__ __forceinline__ double u_bond_delta(const DevParams& P, double r2n, double r2o) {
+    if (P.bond_type == WMC_BOND_FENE) {
+        if (r2n >= P.R02 || r2o >= P.R02) return u_bond(P, r2n) - u_bond(P, r2o);
+        return -0.5 * P.k_bond * P.R02 * log((P.R02 - r2n) / (P.R02 - r2o));
+    }
+    if (P.bond_type == WMC_BOND_HARMONIC) return 0.5 * P.k_bond * (r2n - r2o);
+    return 0.0;
+}
 __device__ __forceinline__ double u_pair(const DevParams& P, double r2) {
     if (r2 >= P.rc2) return 0.0;
     if (r2 <= 0.0) return INFINITY;
@@ -642,7 +652,7 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
                     acc += (double)(u_bond_fs(P, r2n, sn) - u_bond_fs(P, r2o, so));
                     sens += (double)sn + (double)so;
                 } else {
-                    acc += u_bond(P, r2n) - u_bond(P, r2o);
+                    acc += u_bond_delta(P, r2n, r2o);
                 }
             }
         }
@@ -1065,7 +1075,10 @@ struct TileShared {
     double x[CAPH], y[CAPH], z[CAPH];
     int32_t id[CAPH];
     int32_t kc[CAPH];           // tile cell list: (tile cell << 16) | slot, ascending
-    int16_t tag[CAPH];
+    // member index of a moved slot (-1: not moved); with no trial positions kept (CAPM == 0)
+    // only whether it moved is needed, one bit per slot
+    int16_t tag[CAPM > 0 ? CAPH : 1];
+    uint32_t tagb[CAPM > 0 ? 1 : (CAPH + 31) / 32];
     int16_t S[CAPH];
     int16_t cst[NCD * NCD * NCD + 1];  // first kc position of each tile cell
     int16_t M[CAPH];                   // member slots of the current test
@@ -1085,6 +1098,26 @@ union PhaseLDS {
     PhaseShared<W, CAPS, CAPM> g;
     TileShared<W, CAPH, CAPMT, NCD> t;
 };
+
+template <int W, int CAPH, int CAPM, int NCD>
+__device__ __forceinline__ int tile_tag(const TileShared<W, CAPH, CAPM, NCD>& sh, int sl) {
+    if (CAPM > 0) return sh.tag[sl];
+    return ((sh.tagb[sl >> 5] >> (sl & 31)) & 1u) ? 0 : -1;
+}
+template <int W, int CAPH, int CAPM, int NCD>
+__device__ __forceinline__ void tile_tag_set(TileShared<W, CAPH, CAPM, NCD>& sh, int sl, int k) {
+    if (CAPM > 0)
+        sh.tag[sl] = (int16_t)k;
+    else
+        atomicOr(&sh.tagb[sl >> 5], 1u << (sl & 31));
+}
+template <int W, int CAPH, int CAPM, int NCD>
+__device__ __forceinline__ void tile_tag_clear(TileShared<W, CAPH, CAPM, NCD>& sh, int sl) {
+    if (CAPM > 0)
+        sh.tag[sl] = -1;
+    else
+        atomicAnd(&sh.tagb[sl >> 5], ~(1u << (sl & 31)));
+}
 
 // Geometry of a tile's cell list: a cube of side 2 He centred on the cell, nc^3 cells of side f.
 // A bead's tile coordinate is its minimum-image offset from the centre plus He.
@@ -1243,7 +1276,7 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                 if (ps < 0 || ps >= nH || (sh.id[ps] & ID_MASK) != m) ps = tile_find(sh, nH, m);
                 double mx, my, mz, nx, ny, nz;
                 if (ps >= 0) {
-                    const int tm = sh.tag[ps];
+                    const int tm = tile_tag(sh, ps);
                     if (tm >= 0 && ps < sl) continue;
                     mx = sh.x[ps];
                     my = sh.y[ps];
@@ -1266,7 +1299,7 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                     acc += (double)(u_bond_fs(P, r2n, sn) - u_bond_fs(P, r2o, so));
                     sens += (double)sn + (double)so;
                 } else {
-                    acc += u_bond(P, r2n) - u_bond(P, r2o);
+                    acc += u_bond_delta(P, r2n, r2o);
                 }
             }
         }
@@ -1291,7 +1324,7 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
             for (int pp = p0; pp < p1; ++pp) {
                 const int m = sh.kc[pp] & 0xFFFF;
                 if (m == sl) continue;
-                const int tm = sh.tag[m];
+                const int tm = tile_tag(sh, m);
                 if (tm >= 0 && m < sl) continue;
                 const double mx = sh.x[m], my = sh.y[m], mz = sh.z[m];
                 double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
@@ -1373,6 +1406,8 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
         __syncthreads();
         bitonic_sort<W>(sh.id, np2);
     }
+    if (CAPM == 0)
+        for (int w = tid; w < (nH + 31) / 32; w += W) sh.tagb[w] = 0u;
     int nS = 0;
     for (int c0 = 0; c0 < nH; c0 += W) {
         int i = c0 + tid;
@@ -1383,7 +1418,7 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
             sh.x[i] = x;
             sh.y[i] = y;
             sh.z[i] = z;
-            sh.tag[i] = -1;
+            if (CAPM > 0) sh.tag[i] = -1;
             int32_t fl = j;
             if (j + 1 < s.b1 && D.bond_next[j]) fl |= ID_NEXT;
             if (j > s.b0 && D.bond_next[j - 1]) fl = (int32_t)((uint32_t)fl | ID_PREV);
@@ -1504,7 +1539,7 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
                     sh.MY[k] = sh.y[sl] + w1;
                     sh.MZ[k] = sh.z[sl] + w2;
                 }
-                sh.tag[sl] = (int16_t)k;
+                tile_tag_set(sh, sl, k);
                 dmax_l = fmax(dmax_l, sqrt((w0 * w0 + w1 * w1) + w2 * w2));
             }
             const double dmax = block_max<W>(dmax_l, sh.red);  // barrier: trial positions and tags visible
@@ -1543,7 +1578,7 @@ __device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShar
                     double dd = fmax(fabs(nx - D.xb[j]), fmax(fabs(ny - D.yb[j]), fabs(nz - D.zb[j])));
                     d_local = fmax(d_local, dd);
                 }
-                sh.tag[sl] = -1;
+                tile_tag_clear(sh, sl);
             }
             __syncthreads();
             if (accept) {
@@ -1662,13 +1697,13 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
                   const int32_t* bmap, int nblocks, hipStream_t st) {
     if (nblocks <= 0) return;
     if (variant == V64)
-        hipLaunchKernelGGL((k_phase<64, 512, 128, 512, 128, 8>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour,
+        hipLaunchKernelGGL((k_phase<64, 1024, 256, 512, 128, 8>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour,
                            sweep, bmap, nblocks);
     else if (variant == V256)
         hipLaunchKernelGGL((k_phase<256, 4096, 1024, 1024, 512, 12>), dim3(nblocks), dim3(256), 0, st, P, D, level,
                            colour, sweep, bmap, nblocks);
     else
-        hipLaunchKernelGGL((k_phase<512, 8192, 4096, 4096, 0, 13>), dim3(nblocks), dim3(512), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_phase<512, 8192, 4096, 4096, 0, 18>), dim3(nblocks), dim3(512), 0, st, P, D, level,
                            colour, sweep, bmap, nblocks);
 }
 
@@ -1743,13 +1778,13 @@ void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int le
                        const int32_t* items, const FlowArgs& fa, hipStream_t st) {
     if (fa.nitems <= 0) return;
     if (variant == V64)
-        hipLaunchKernelGGL((k_level_flow<64, 512, 128, 512, 128, 8>), dim3(fa.nitems), dim3(64), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_level_flow<64, 1024, 256, 512, 128, 8>), dim3(fa.nitems), dim3(64), 0, st, P, D, level,
                            sweep, items, fa);
     else if (variant == V256)
         hipLaunchKernelGGL((k_level_flow<256, 4096, 1024, 1024, 512, 12>), dim3(fa.nitems), dim3(256), 0, st, P, D,
                            level, sweep, items, fa);
     else
-        hipLaunchKernelGGL((k_level_flow<512, 8192, 4096, 4096, 0, 13>), dim3(fa.nitems), dim3(512), 0, st, P, D,
+        hipLaunchKernelGGL((k_level_flow<512, 8192, 4096, 4096, 0, 18>), dim3(fa.nitems), dim3(512), 0, st, P, D,
                            level, sweep, items, fa);
 }
 
@@ -2243,7 +2278,7 @@ __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t swe
                 if (P.bond_type != WMC_BOND_NONE && j + 1 < s.b1 && D.bond_next[j]) {
                     double r2o = pair_r2(P, invL, L, jx, jy, jz, D.x[j + 1], D.y[j + 1], D.z[j + 1]);
                     double r2n = pair_r2(P, invL, L, NX[j], NY[j], NZ[j], NX[j + 1], NY[j + 1], NZ[j + 1]);
-                    acc += u_bond(P, r2n) - u_bond(P, r2o);
+                    acc += u_bond_delta(P, r2n, r2o);
                 }
                 if (P.wca) {
                     double cx = wrap01(jx, L, invL), cy = wrap01(jy, L, invL), cz = wrap01(jz, L, invL);
@@ -2397,7 +2432,7 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
                 if (P.bond_type != WMC_BOND_NONE && j + 1 < s.b1 && D.bond_next[j]) {
                     double r2o = pair_r2(P, invL, L, jx, jy, jz, D.x[j + 1], D.y[j + 1], D.z[j + 1]);
                     double r2n = pair_r2(P, invL, L, NX[j], NY[j], NZ[j], NX[j + 1], NY[j + 1], NZ[j + 1]);
-                    acc += u_bond(P, r2n) - u_bond(P, r2o);
+                    acc += u_bond_delta(P, r2n, r2o);
                 }
                 if (P.wca) {
                     double cx = wrap01(jx, L, invL), cy = wrap01(jy, L, invL), cz = wrap01(jz, L, invL);

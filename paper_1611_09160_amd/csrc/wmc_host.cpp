@@ -750,6 +750,61 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
         std::copy(pool[k].cdf.begin(), pool[k].cdf.end(), cube.begin() + k * pool[k].cdf.size());
         std::copy(pool[k].shell.begin(), pool[k].shell.end(), shell.begin() + k * 4097);
     }
+    // capacities from the actual clustering: a dilute chain puts most of its beads into one
+    // cell's reach, far above the uniform-density estimate the plan used. A tile that does not
+    // fit LDS falls back to the global path, whose reach and member lists live in LDS too and
+    // must not overflow. Per periodic LDS-tile level the beads are binned at a quarter of the
+    // cell side; the largest periodic box window as wide as a cell's reach (cell + 2 lambda_hi)
+    // and as wide as a wavelet (2 lambda_hi) bound those lists for any shifted cell and any
+    // centre, and the variant is raised until both fit with a 12.5% margin.
+    if (p->periodic) {
+        const int caps[3] = {1024, 4096, 8192}, capm[3] = {256, 1024, 4096};  // global-path lists per variant
+        for (int s = 0; s < nsys; ++s) {
+            const SysDesc& d = c->sys[s];
+            for (int l = 0; l < d.n_levels; ++l) {
+                LevelDesc& L = c->lev[d.lvl_off + l];
+                if (L.use_global || L.n < 4) continue;
+                const int m = 4 * L.n;
+                const double inv_bin = 4.0 * L.invh;
+                std::vector<int32_t> cnt((size_t)m * m * m, 0);
+                for (int64_t i = d.b0; i < d.b1; ++i) {
+                    int q[3];
+                    for (int ax = 0; ax < 3; ++ax) {
+                        double v = pos[3 * i + ax];
+                        v -= d.L * floor(v * d.invL);
+                        q[ax] = std::min(m - 1, std::max(0, (int)(v * inv_bin)));
+                    }
+                    ++cnt[q[0] + (size_t)m * (q[1] + (size_t)m * q[2])];
+                }
+                // largest count over periodic windows of w bins per axis (separable sliding sums)
+                auto window_max = [&](int w) {
+                    w = std::max(1, std::min(m, w));
+                    std::vector<int32_t> a = cnt, b((size_t)m * m * m);
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const size_t stride = ax == 0 ? 1 : (ax == 1 ? (size_t)m : (size_t)m * m);
+                        for (int u = 0; u < m; ++u)
+                            for (int v = 0; v < m; ++v) {
+                                const size_t base = ax == 0 ? (size_t)m * (u + (size_t)m * v)
+                                                  : (ax == 1 ? (size_t)u + (size_t)m * m * v : (size_t)u + (size_t)m * v);
+                                int64_t run = 0;
+                                for (int k = 0; k < w; ++k) run += a[base + stride * (size_t)(k % m)];
+                                for (int k = 0; k < m; ++k) {
+                                    b[base + stride * (size_t)k] = (int32_t)run;
+                                    run += a[base + stride * (size_t)((k + w) % m)] - a[base + stride * (size_t)k];
+                                }
+                            }
+                        std::swap(a, b);
+                    }
+                    int64_t worst = 0;
+                    for (int32_t v : a) worst = std::max<int64_t>(worst, v);
+                    return worst + worst / 8;
+                };
+                const int64_t need_s = window_max((int)ceil((L.h + 2.0 * L.hi) * inv_bin) + 1);
+                const int64_t need_m = window_max((int)ceil(2.0 * L.hi * inv_bin) + 1);
+                while (L.variant < V1024 && (need_s > caps[L.variant] || need_m > capm[L.variant])) L.variant += 1;
+            }
+        }
+    }
     // block maps
     c->max_levels = 0;
     for (auto& s : c->sys) c->max_levels = std::max(c->max_levels, (int)s.n_levels);

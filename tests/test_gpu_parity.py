@@ -136,3 +136,31 @@ def test_full_size_after_equilibration():
     compare_traces(g2.trace(4_000_000), o.trace(4_000_000))
     compare_positions(g2.positions(), o.positions())
     assert g2.observables()["overflows"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_resume_is_bit_exact(precision):
+    """A run is determined by (positions, sweep counter, seed): 6 sweeps in one go equal 3 sweeps,
+    a fresh context started from those positions at sweep 3, and 3 more sweeps."""
+    cfg = _workload(3, 0.0625)
+    a, _ = build_pair(cfg, precision=precision, trace=0)
+    a.sweep(6)
+    full = a.positions()
+    b, _ = build_pair(cfg, precision=precision, trace=0)
+    b.sweep(3)
+    mid = b.positions()
+    c, _ = build_pair(dict(cfg, pos=mid), precision=precision, trace=0)
+    c.set_state(mid, 3)
+    c.sweep(3)
+    np.testing.assert_array_equal(c.positions(), full)
+
+
+def test_full_size_dilute_chain_one_sweep():
+    """The dilute workload (one 1024-bead chain, L = 128) for one sweep against the oracle."""
+    cfg = _workload(2, 1.0)
+    g, o = build_pair(cfg, trace=1_000_000)
+    g.sweep(1)
+    o.sweep(1)
+    compare_traces(g.trace(1_000_000), o.trace(1_000_000))
+    compare_positions(g.positions(), o.positions())
+    compare_counters(g.observables(), o.observables())
