@@ -1777,7 +1777,13 @@ __global__ __launch_bounds__(W) void k_level_flow(DevParams P, DevPtrs D, int le
 void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
                        const int32_t* items, const FlowArgs& fa, hipStream_t st) {
     if (fa.nitems <= 0) return;
-    if (variant == V64)
+    // the smallest tile: a few thousand cells (one large system) finish sooner with four waves
+    // per cell, since the pass is its longest chain of cells; many more cells (a batch) fill the
+    // GPU better with one wave per cell
+    if (variant == V64 && fa.nitems <= 4096)
+        hipLaunchKernelGGL((k_level_flow<256, 1024, 256, 512, 128, 8>), dim3(fa.nitems), dim3(256), 0, st, P, D,
+                           level, sweep, items, fa);
+    else if (variant == V64)
         hipLaunchKernelGGL((k_level_flow<64, 1024, 256, 512, 128, 8>), dim3(fa.nitems), dim3(64), 0, st, P, D, level,
                            sweep, items, fa);
     else if (variant == V256)
