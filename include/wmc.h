@@ -107,6 +107,8 @@ typedef struct {
     int64_t grid_rebuilds;                /* neighbour-grid rebuilds */
     int64_t wait_timeouts;                /* dependency waits between cells that hit their bound
                                              (must be 0; the pass then ran out of order) */
+    int64_t fallback_cells;               /* cells of LDS-tile levels whose halo did not fit the
+                                             tile, run on the global-list path instead */
 } wmc_obs;
 
 /* One trace record per Metropolis test (kind 0 wavelet, 2 plane wave) and per cell phase

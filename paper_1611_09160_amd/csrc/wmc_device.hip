@@ -234,7 +234,7 @@ __device__ __forceinline__ double dist2_cell(const Grid& g, const int64_t ic[3],
     return (acc[0] + acc[1]) + acc[2];
 }
 
-__device__ void make_grid(const DevParams& P, const DevPtrs& D, const SysDesc& s, const LevelDesc& lv, int sys,
+__device__ __forceinline__ void make_grid(const DevParams& P, const DevPtrs& D, const SysDesc& s, const LevelDesc& lv, int sys,
                           int level, int64_t sweep, Grid& g) {
     g.h = lv.h;
     g.invh = 1.0 / lv.h;
@@ -701,7 +701,7 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
 }
 
 template <int W, int CAPS, int CAPM>
-__device__ __attribute__((noinline)) void process_cell(const DevParams& P, const DevPtrs& D,
+__device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& D,
                                                        PhaseShared<W, CAPS, CAPM>& sh, int sys,
                              int level, int colour, int64_t local, int64_t sweep, const Grid& g) {
     const SysDesc& s = D.sys[sys];
@@ -1348,7 +1348,7 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
 // returns false (before any move) when the halo does not fit; the caller then uses the
 // global path for this cell
 template <int W, int CAPH, int CAPM, int NCD>
-__device__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShared<W, CAPH, CAPM, NCD>& sh, int sys,
+__device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShared<W, CAPH, CAPM, NCD>& sh, int sys,
                                   int level, int colour, int64_t local, int64_t sweep, const Grid& g) {
     const SysDesc& s = D.sys[sys];
     const LevelDesc& lv = D.lev[s.lvl_off + level];
@@ -1718,8 +1718,8 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
 constexpr unsigned FLOW_SPIN_LIMIT = 1u << 24;
 
 template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD>
-__global__ __launch_bounds__(W) void k_level_flow(DevParams P, DevPtrs D, int level, int64_t sweep,
-                                                  const int32_t* items, FlowArgs fa) {
+__global__ __launch_bounds__(W, 2) void k_level_flow(DevParams P, DevPtrs D, int level, int64_t sweep,
+                                                     const int32_t* items, FlowArgs fa) {
     __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD> sh;
     __shared__ int s_idx;
     __shared__ int s_timeout;
@@ -1762,7 +1762,10 @@ __global__ __launch_bounds__(W) void k_level_flow(DevParams P, DevPtrs D, int le
     __syncthreads();
     if (tid == 0 && s_timeout) atomicAdd(&D.cnt[CNT_FLOWWAIT], 1ull);
     if (!process_cell_tile<W, CAPH, CAPMT, NCD>(P, D, sh.t, sys, level, colour, local, sweep, g)) {
+        // the halo does not fit the tile: the global-list path, inline (a call would cost a stack
+        // frame and the registers saved around it, for every cell)
         __syncthreads();
+        if (tid == 0) atomicAdd(&D.cnt[CNT_FALLBACK], 1ull);
         process_cell<W, CAPS, CAPM>(P, D, sh.g, sys, level, colour, local, sweep, g);
     }
     // publish: every wave's stores complete, then one release of the epoch
@@ -1841,25 +1844,22 @@ __device__ __forceinline__ double coop_max(const double* part, int G, CoopShared
     return block_max<CW>((int)threadIdx.x < G ? part[threadIdx.x] : 0.0, sh.red);
 }
 
-__global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int level, int colour, int64_t sweep,
-                                                  const CoopGroup* groups, const int32_t* wg_group) {
-    __shared__ CoopShared sh;
-    const int gi = wg_group[blockIdx.x];
-    const CoopGroup grp = groups[gi];
+// one cell of colour `colour` for the group `grp` (index gi); gen is the group's barrier
+// generation and Dg its system's drift bound, both carried from colour to colour
+__device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
+                          const CoopGroup grp, int gi, CoopShared& sh, unsigned& gen, double& Dg) {
     const int sys = grp.sys;
     const SysDesc& s = D.sys[sys];
     const LevelDesc& lv = D.lev[s.lvl_off + level];
     const int tid = threadIdx.x, wg = (int)blockIdx.x - grp.first, G = grp.size;
     const int gt = wg * CW + tid, gstride = G * CW;
     unsigned* bar = D.gbar + 2 * (1 + gi);
-    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     Grid g;
     make_grid(P, D, s, lv, sys, level, sweep, g);
     int64_t ic[3];
     cell_coords(P, lv, g, colour, grp.local, ic);
     const int64_t cell = ic[0] + g.n[0] * (ic[1] + g.n[1] * ic[2]);
     const double hi2 = lv.hi * lv.hi;
-    const double Dg = __longlong_as_double((long long)D.drift[sys]);
     const double L = s.L;
     int32_t* Sg = D.slot_S + (lv.slot_base + grp.local) * D.slot_len;
     int32_t* Mg = D.slot_M + (lv.slot_base + grp.local) * D.slot_len;
@@ -2140,6 +2140,21 @@ __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int le
         if (dloc > 0.0) atomic_max_double(&D.drift[sys], dloc);
         trace_push(D, 1, sys, sweep, level, cell, K, nS, 0, (int)c_hits, 0, 0.0, 0.0);
     }
+    // the next colour's bound: what the drift slot holds once this cell has published
+    Dg = fmax(Dg, dloc);
+}
+
+__global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int level, CoopColours cc, int64_t sweep,
+                                                  const CoopGroup* groups, const int32_t* wg_group) {
+    __shared__ CoopShared sh;
+    const int gi = wg_group[blockIdx.x];
+    const int sys = groups[gi].sys;
+    unsigned gen = __hip_atomic_load(&D.gbar[2 * (1 + gi) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double Dg = __longlong_as_double((long long)D.drift[sys]);
+    for (int i = 0; i < cc.n; ++i) {
+        const CoopGroup* gt = (const CoopGroup*)((const int32_t*)groups + cc.goff[i]);
+        coop_cell(P, D, level, cc.col[i], sweep, gt[gi], gi, sh, gen, Dg);
+    }
 }
 
 int cell_coop_blocks() {
@@ -2156,16 +2171,17 @@ int cell_coop_blocks() {
     return nb;
 }
 
-bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
+bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, const CoopColours& cc, int64_t sweep,
                       const CoopGroup* groups, const int32_t* wg_group, int nwg, hipStream_t st) {
-    if (nwg <= 0 || nwg > cell_coop_blocks()) return false;
+    if (nwg <= 0 || nwg > cell_coop_blocks() || cc.n < 1 || cc.n > 8) return false;
     DevParams Pc = P;
     DevPtrs Dc = D;
-    int lv = level, col = colour;
+    int lv = level;
+    CoopColours ccc = cc;
     int64_t sw = sweep;
     const CoopGroup* gp = groups;
     const int32_t* wp = wg_group;
-    void* args[] = {&Pc, &Dc, &lv, &col, &sw, &gp, &wp};
+    void* args[] = {&Pc, &Dc, &lv, &ccc, &sw, &gp, &wp};
     return hipLaunchCooperativeKernel((const void*)k_cell_coop, dim3(nwg), dim3(CW), args, 0, st) == hipSuccess;
 }
 

@@ -52,6 +52,7 @@ struct wmc_ctx {
     int32_t* coop_dev;
     int64_t cgrp_off[WMC_MAX_LEVELS][8], cwg_off[WMC_MAX_LEVELS][8];
     int32_t cwg_n[WMC_MAX_LEVELS][8];     // workgroups of the cell-group launch (0: none)
+    bool cmerge[WMC_MAX_LEVELS];          // every colour of the level in one cell-group launch
     int64_t pgrp_off = 0, pwg_off = 0;
     int32_t pwg_n = 0;                    // workgroups of the plane-wave group launch (0: none)
     int64_t* chain_off_dev;
@@ -598,6 +599,30 @@ static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
             for (size_t i = 0; i < glob.size(); ++i) H.insert(H.end(), (size_t)G[i], (int32_t)i);
             c->cwg_n[l][col] = first;
         }
+    // a level's colours share one launch when each colour with global-list cells has a group
+    // launch over the same groups (system, first workgroup, size) as the first such colour
+    for (int l = 0; l < WMC_MAX_LEVELS; ++l) {
+        c->cmerge[l] = false;
+        int c0 = -1, ncol = 0;
+        bool ok = true;
+        for (int col = 0; col < 8 && ok; ++col) {
+            if (c->glob_n[l][col] <= 0) continue;
+            ++ncol;
+            if (c->cwg_n[l][col] <= 0) {
+                ok = false;
+            } else if (c0 < 0) {
+                c0 = col;
+            } else {
+                ok = c->glob_n[l][col] == c->glob_n[l][c0] && c->cwg_n[l][col] == c->cwg_n[l][c0];
+                for (int32_t i = 0; ok && i < c->glob_n[l][col]; ++i) {
+                    const int32_t* a = &H[c->cgrp_off[l][c0] + 4 * i];
+                    const int32_t* b = &H[c->cgrp_off[l][col] + 4 * i];
+                    ok = a[0] == b[0] && a[2] == b[2] && a[3] == b[3];
+                }
+            }
+        }
+        c->cmerge[l] = ok && ncol > 1;
+    }
     c->pwg_n = 0;
     if (c->P.periodic && c->P.plane_waves) {
         std::vector<int64_t> Ns(c->nsys);
@@ -617,8 +642,10 @@ static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
     }
     if ((int64_t)H.size() > capacity_ints) {  // cannot happen: the layout bounds the table
         H.clear();
-        for (int l = 0; l < WMC_MAX_LEVELS; ++l)
+        for (int l = 0; l < WMC_MAX_LEVELS; ++l) {
             for (int col = 0; col < 8; ++col) c->cwg_n[l][col] = 0;
+            c->cmerge[l] = false;
+        }
         c->pwg_n = 0;
     }
 }
@@ -919,12 +946,33 @@ extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
                     launch_level_flow(c->phase_variant[l], c->P, c->D, l, sw, c->bmap_dev + 2 * c->tile_off[l][0], fa,
                                       st);
                 }
-                // global-list cells colour by colour: cooperative groups, else one workgroup each
-                for (int col = 0; col < 8; ++col) {
+                // global-list cells colour by colour: cooperative groups, else one workgroup each;
+                // every colour in one group launch when their groups agree
+                bool merged = false;
+                if (c->cmerge[l]) {
+                    CoopColours cc;
+                    cc.n = 0;
+                    int c0 = -1;
+                    for (int col = 0; col < 8; ++col) {
+                        if (c->glob_n[l][col] <= 0) continue;
+                        if (c0 < 0) c0 = col;
+                        cc.col[cc.n] = col;
+                        cc.goff[cc.n] = (int32_t)(c->cgrp_off[l][col] - c->cgrp_off[l][c0]);
+                        ++cc.n;
+                    }
+                    Timed t(c, 1 + l, st);
+                    merged = launch_cell_coop(c->P, c->D, l, cc, sw, (const CoopGroup*)(c->coop_dev + c->cgrp_off[l][c0]),
+                                              c->coop_dev + c->cwg_off[l][c0], c->cwg_n[l][c0], st);
+                }
+                for (int col = 0; col < 8 && !merged; ++col) {
                     if (c->glob_n[l][col] <= 0) continue;
                     Timed t(c, 1 + l, st);
+                    CoopColours cc;
+                    cc.n = 1;
+                    cc.col[0] = col;
+                    cc.goff[0] = 0;
                     if (c->cwg_n[l][col] > 0 &&
-                        launch_cell_coop(c->P, c->D, l, col, sw, (const CoopGroup*)(c->coop_dev + c->cgrp_off[l][col]),
+                        launch_cell_coop(c->P, c->D, l, cc, sw, (const CoopGroup*)(c->coop_dev + c->cgrp_off[l][col]),
                                          c->coop_dev + c->cwg_off[l][col], c->cwg_n[l][col], st))
                         continue;
                     launch_phase(c->phase_variant[l], c->P, c->D, l, col, sw, c->bmap_dev + 2 * c->glob_off[l][col],
@@ -1040,6 +1088,7 @@ extern "C" int wmc_observables(wmc_ctx* c, wmc_obs* o) {
     o->grid_rebuilds = cnt[CNT_REBUILD];
     o->accepted_total = cnt[CNT_ACCEPTED];
     o->wait_timeouts = cnt[CNT_FLOWWAIT];
+    o->fallback_cells = cnt[CNT_FALLBACK];
     return 0;
 }
 

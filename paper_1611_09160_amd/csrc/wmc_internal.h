@@ -23,6 +23,7 @@ constexpr int CNT_RECHECK = 138;
 constexpr int CNT_REBUILD = 139;
 constexpr int CNT_ACCEPTED = 140;
 constexpr int CNT_FLOWWAIT = 141;   // dependency waits that hit their spin limit (must be 0)
+constexpr int CNT_FALLBACK = 142;   // LDS-tile cells whose halo did not fit: run on the global-list path
 constexpr int CNT_TOTAL = 160;
 
 // Cooperative launches: groups of co-resident workgroups, each group on one (system, cell) of a
@@ -31,6 +32,15 @@ constexpr int CNT_TOTAL = 160;
 // gbar[2 (1 + group index) ..].
 struct CoopGroup {
     int32_t sys, local, first, size;
+};
+// The colour phases one cell-group launch runs in order: colour col[i] with its group table
+// goff[i] int32 entries past the first colour's. Several colours share a launch only when their tables hold the same groups
+// (system, first workgroup, size), so each group runs its system's colours back to back and
+// never waits for another system.
+struct CoopColours {
+    int32_t n;
+    int32_t col[8];
+    int32_t goff[8];
 };
 // Group and launch sizes: a barrier costs more the more workgroups of a group arrive, and every
 // arriving workgroup writes back its L2, so a launch is also capped in total.
@@ -141,7 +151,7 @@ void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int le
 void launch_pw(const DevParams& P, const DevPtrs& D, int64_t sweep, int nsys, hipStream_t st);
 bool launch_pw_coop(const DevParams& P, const DevPtrs& D, int64_t sweep, const CoopGroup* groups,
                     const int32_t* wg_group, int nwg, hipStream_t st);
-bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
+bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, const CoopColours& cc, int64_t sweep,
                       const CoopGroup* groups, const int32_t* wg_group, int nwg, hipStream_t st);
 int cell_coop_blocks();
 int pw_coop_blocks();

@@ -38,7 +38,8 @@ class Obs(C.Structure):
         for name in ("trials", "hits", "attempts", "accepts", "caps", "redraws", "bead_updates")
     ] + [(name, C.c_int64) for name in (
         "pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates",
-        "violations", "accepted_total", "rechecks", "overflows", "grid_rebuilds", "wait_timeouts")]
+        "violations", "accepted_total", "rechecks", "overflows", "grid_rebuilds", "wait_timeouts",
+        "fallback_cells")]
 
 
 class TraceRec(C.Structure):
@@ -205,7 +206,7 @@ class WMC:
         for name in ("trials", "hits", "attempts", "accepts", "caps", "redraws", "bead_updates"):
             d[name] = np.array(getattr(o, name)[:], dtype=np.int64)
         for name in ("pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates", "violations",
-                     "accepted_total", "rechecks", "overflows", "grid_rebuilds", "wait_timeouts"):
+                     "accepted_total", "rechecks", "overflows", "grid_rebuilds", "wait_timeouts", "fallback_cells"):
             d[name] = getattr(o, name)
         return d
 
