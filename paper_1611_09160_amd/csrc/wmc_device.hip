@@ -1847,11 +1847,11 @@ __device__ __forceinline__ double coop_max(const double* part, int G, CoopShared
 // one cell of colour `colour` for the group `grp` (index gi); gen is the group's barrier
 // generation and Dg its system's drift bound, both carried from colour to colour
 __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
-                          const CoopGroup grp, int gi, CoopShared& sh, unsigned& gen, double& Dg) {
+                          const CoopGroup grp, int gi, int rank, CoopShared& sh, unsigned& gen, double& Dg) {
     const int sys = grp.sys;
     const SysDesc& s = D.sys[sys];
     const LevelDesc& lv = D.lev[s.lvl_off + level];
-    const int tid = threadIdx.x, wg = (int)blockIdx.x - grp.first, G = grp.size;
+    const int tid = threadIdx.x, wg = rank, G = grp.size;
     const int gt = wg * CW + tid, gstride = G * CW;
     unsigned* bar = D.gbar + 2 * (1 + gi);
     Grid g;
@@ -2147,13 +2147,15 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
 __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int level, CoopColours cc, int64_t sweep,
                                                   const CoopGroup* groups, const int32_t* wg_group) {
     __shared__ CoopShared sh;
-    const int gi = wg_group[blockIdx.x];
+    const int e = wg_group[blockIdx.x];
+    if (e < 0) return;  // a launch slot no group uses
+    const int gi = e & 0xFFFF, rank = e >> 16;
     const int sys = groups[gi].sys;
     unsigned gen = __hip_atomic_load(&D.gbar[2 * (1 + gi) + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     double Dg = __longlong_as_double((long long)D.drift[sys]);
     for (int i = 0; i < cc.n; ++i) {
         const CoopGroup* gt = (const CoopGroup*)((const int32_t*)groups + cc.goff[i]);
-        coop_cell(P, D, level, cc.col[i], sweep, gt[gi], gi, sh, gen, Dg);
+        coop_cell(P, D, level, cc.col[i], sweep, gt[gi], gi, rank, sh, gen, Dg);
     }
 }
 
@@ -2380,13 +2382,15 @@ __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t swe
 __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t sweep, const CoopGroup* groups,
                                                  const int32_t* wg_group) {
     __shared__ double red[4];
-    const int gi = wg_group[blockIdx.x];
+    const int e = wg_group[blockIdx.x];
+    if (e < 0) return;  // a launch slot no group uses
+    const int gi = e & 0xFFFF;
     const CoopGroup grp = groups[gi];
     const int sys = grp.sys;
     const SysDesc& s = D.sys[sys];
     const int tid = threadIdx.x;
     const unsigned G = grp.size;
-    const int rank = (int)blockIdx.x - grp.first;
+    const int rank = e >> 16;
     const int64_t stride = (int64_t)G * 256;
     const int64_t g0 = s.b0 + (int64_t)rank * 256 + tid;
     const double L = s.L, invL = s.invL;

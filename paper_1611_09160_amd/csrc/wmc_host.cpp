@@ -557,6 +557,41 @@ static bool size_groups(std::vector<int>& G, const std::vector<int64_t>& Ns, int
     return cap > 0 && T <= cap && top > 1;
 }
 
+// Launch slots of a group launch. The dispatcher deals a cooperative launch's workgroups to the
+// 8 XCDs in turn, so workgroups whose launch indices agree mod 8 share an XCD and its L2. Each
+// group takes the indices of one residue class (largest groups first, least-loaded class), so
+// its barriers write back and invalidate one L2 and no other group's lines. Entry w of the map
+// is (group | rank << 16), or -1 for a slot no group uses. When the padded launch would exceed
+// cap, groups take consecutive slots instead. Returns the launch size.
+static int map_groups(const std::vector<int>& G, int cap, std::vector<int32_t>& map) {
+    const int ng = (int)G.size();
+    std::vector<int> order(ng), cls(ng);
+    for (int g = 0; g < ng; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return G[a] > G[b]; });
+    int load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int g : order) {
+        int r = 0;
+        for (int q = 1; q < 8; ++q)
+            if (load[q] < load[r]) r = q;
+        cls[g] = r;
+        load[r] += G[g];
+    }
+    int top = 0;
+    for (int q = 0; q < 8; ++q) top = std::max(top, load[q]);
+    map.clear();
+    if (8 * top <= cap) {
+        map.assign((size_t)8 * top, -1);
+        int next[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int g = 0; g < ng; ++g)
+            for (int k = 0; k < G[g]; ++k) map[(size_t)cls[g] + 8 * (size_t)next[cls[g]]++] = g | (k << 16);
+        while (!map.empty() && map.back() < 0) map.pop_back();
+    } else {
+        for (int g = 0; g < ng; ++g)
+            for (int k = 0; k < G[g]; ++k) map.push_back(g | (k << 16));
+    }
+    return (int)map.size();
+}
+
 static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
     c->coop_host.clear();
     auto& H = c->coop_host;
@@ -595,9 +630,11 @@ static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
                 H.insert(H.end(), {glob[i].first, glob[i].second, first, G[i]});
                 first += G[i];
             }
+            std::vector<int32_t> wmap;
+            const int nwg = map_groups(G, ccap, wmap);
             c->cwg_off[l][col] = (int64_t)H.size();
-            for (size_t i = 0; i < glob.size(); ++i) H.insert(H.end(), (size_t)G[i], (int32_t)i);
-            c->cwg_n[l][col] = first;
+            H.insert(H.end(), wmap.begin(), wmap.end());
+            c->cwg_n[l][col] = nwg;
         }
     // a level's colours share one launch when each colour with global-list cells has a group
     // launch over the same groups (system, first workgroup, size) as the first such colour
@@ -635,9 +672,11 @@ static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
                 H.insert(H.end(), {s, 0, first, G[s]});
                 first += G[s];
             }
+            std::vector<int32_t> wmap;
+            const int nwg = map_groups(G, std::min(pw_coop_blocks(), PW_LAUNCH_MAX), wmap);
             c->pwg_off = (int64_t)H.size();
-            for (int s = 0; s < c->nsys; ++s) H.insert(H.end(), (size_t)G[s], (int32_t)s);
-            c->pwg_n = first;
+            H.insert(H.end(), wmap.begin(), wmap.end());
+            c->pwg_n = nwg;
         }
     }
     if ((int64_t)H.size() > capacity_ints) {  // cannot happen: the layout bounds the table
