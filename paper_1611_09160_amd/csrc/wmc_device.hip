@@ -1074,13 +1074,15 @@ template <int W, int CAPH, int CAPM, int NCD>
 struct TileShared {
     double x[CAPH], y[CAPH], z[CAPH];
     int32_t id[CAPH];
-    int32_t kc[CAPH];           // tile cell list: (tile cell << 16) | slot, ascending
+    int16_t kc[CAPH];           // tile cell list: slots by tile cell, ascending within a cell
     // member index of a moved slot (-1: not moved); with no trial positions kept (CAPM == 0)
     // only whether it moved is needed, one bit per slot
     int16_t tag[CAPM > 0 ? CAPH : 1];
     uint32_t tagb[CAPM > 0 ? 1 : (CAPH + 31) / 32];
     int16_t S[CAPH];
-    int16_t cst[NCD * NCD * NCD + 1];  // first kc position of each tile cell
+    // first kc position of each tile cell (entry NC: the total); an even count of 4-byte aligned
+    // entries, so that the index build can update them as packed pairs
+    alignas(4) int16_t cst[(NCD * NCD * NCD + 2) & ~1];
     int16_t M[CAPH];                   // member slots of the current test
     // trial positions of the first CAPM members (later ones are recomputed when needed)
     double MX[CAPM > 0 ? CAPM : 1], MY[CAPM > 0 ? CAPM : 1], MZ[CAPM > 0 ? CAPM : 1];
@@ -1192,28 +1194,64 @@ __device__ void bitonic_sort(int32_t* a, int np2) {
     }
 }
 
-// (re)build the tile cell list from the current tile positions: keys, sort, cell starts
+// tile cell of slot i
+template <int W, int CAPH, int CAPM, int NCD>
+__device__ __forceinline__ int tile_key(const TileShared<W, CAPH, CAPM, NCD>& sh, int i, const Grid& g,
+                                        const TileGeo& tg) {
+    const int cx = tile_clamp(tg, tile_u(g, tg, sh.x[i], 0));
+    const int cy = tile_clamp(tg, tile_u(g, tg, sh.y[i], 1));
+    const int cz = tile_clamp(tg, tile_u(g, tg, sh.z[i], 2));
+    return cx + tg.nc * (cy + tg.nc * cz);
+}
+
+// (re)build the tile cell list from the current tile positions, by counting sort: per-cell
+// counts (two 16-bit counters per LDS word), their inclusive prefix (each cell's end), a
+// scatter that takes positions down from each end (leaving each cell's start), and an
+// insertion sort of every cell's few entries by slot. The result is the list sorted by
+// (cell, slot), whatever order the atomics took.
 template <int W, int CAPH, int CAPM, int NCD>
 __device__ void tile_index(TileShared<W, CAPH, CAPM, NCD>& sh, int nH, const Grid& g, const TileGeo& tg) {
-    int np2 = 1;
-    while (np2 < nH) np2 <<= 1;
-    for (int i = threadIdx.x; i < np2; i += W) {
-        int32_t v = 0x7FFFFFFF;
-        if (i < nH) {
-            const int cx = tile_clamp(tg, tile_u(g, tg, sh.x[i], 0));
-            const int cy = tile_clamp(tg, tile_u(g, tg, sh.y[i], 1));
-            const int cz = tile_clamp(tg, tile_u(g, tg, sh.z[i], 2));
-            v = ((cx + tg.nc * (cy + tg.nc * cz)) << 16) | i;
-        }
-        sh.kc[i] = v;
+    const int tid = threadIdx.x;
+    const int NC = tg.nc * tg.nc * tg.nc;
+    uint32_t* cw = reinterpret_cast<uint32_t*>(sh.cst);
+    for (int w = tid; w < (NC + 2) / 2; w += W) cw[w] = 0u;
+    __syncthreads();
+    for (int i = tid; i < nH; i += W) {
+        const int c = tile_key(sh, i, g, tg);
+        atomicAdd(&cw[c >> 1], 1u << ((c & 1) << 4));
     }
     __syncthreads();
-    bitonic_sort<W>(sh.kc, np2);
-    const int NC = tg.nc * tg.nc * tg.nc;
-    for (int p = threadIdx.x; p <= nH; p += W) {
-        const int kp = p < nH ? (sh.kc[p] >> 16) : NC;
-        const int kq = p > 0 ? (sh.kc[p - 1] >> 16) : -1;
-        for (int c = kq + 1; c <= kp; ++c) sh.cst[c] = (int16_t)p;
+    // inclusive prefix over entries 0..NC, a contiguous chunk per thread
+    const int per = (NC + 1 + W - 1) / W;
+    const int c0 = min(NC + 1, tid * per), c1 = min(NC + 1, c0 + per);
+    int run = 0;
+    for (int c = c0; c < c1; ++c) run += sh.cst[c];
+    int before;
+    block_scan_count<W>(run, before, sh.redi);
+    for (int c = c0; c < c1; ++c) {
+        before += sh.cst[c];
+        sh.cst[c] = (int16_t)before;
+    }
+    __syncthreads();
+    for (int i = tid; i < nH; i += W) {
+        const int c = tile_key(sh, i, g, tg);
+        const int sh16 = (c & 1) << 4;
+        const uint32_t old = atomicSub(&cw[c >> 1], 1u << sh16);
+        const int pos = (int)((old >> sh16) & 0xFFFFu) - 1;
+        sh.kc[pos] = (int16_t)i;
+    }
+    __syncthreads();
+    for (int c = tid; c < NC; c += W) {
+        const int b = sh.cst[c], e = sh.cst[c + 1];
+        for (int p = b + 1; p < e; ++p) {
+            const int16_t v = sh.kc[p];
+            int q = p - 1;
+            while (q >= b && sh.kc[q] > v) {
+                sh.kc[q + 1] = sh.kc[q];
+                --q;
+            }
+            sh.kc[q + 1] = v;
+        }
     }
     __syncthreads();
 }
@@ -1322,7 +1360,7 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
             double kx, ky, kz;
             member_new(sh, g, wv, k, sl, kx, ky, kz);
             for (int pp = p0; pp < p1; ++pp) {
-                const int m = sh.kc[pp] & 0xFFFF;
+                const int m = sh.kc[pp];
                 if (m == sl) continue;
                 const int tm = tile_tag(sh, m);
                 if (tm >= 0 && m < sl) continue;
@@ -1703,7 +1741,7 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
         hipLaunchKernelGGL((k_phase<256, 4096, 1024, 1024, 512, 12>), dim3(nblocks), dim3(256), 0, st, P, D, level,
                            colour, sweep, bmap, nblocks);
     else
-        hipLaunchKernelGGL((k_phase<512, 8192, 4096, 4096, 0, 18>), dim3(nblocks), dim3(512), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_phase<512, 8192, 4096, 4096, 128, 18>), dim3(nblocks), dim3(512), 0, st, P, D, level,
                            colour, sweep, bmap, nblocks);
 }
 
@@ -1793,7 +1831,7 @@ void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int le
         hipLaunchKernelGGL((k_level_flow<256, 4096, 1024, 1024, 512, 12>), dim3(fa.nitems), dim3(256), 0, st, P, D,
                            level, sweep, items, fa);
     else
-        hipLaunchKernelGGL((k_level_flow<512, 8192, 4096, 4096, 0, 18>), dim3(fa.nitems), dim3(512), 0, st, P, D,
+        hipLaunchKernelGGL((k_level_flow<512, 8192, 4096, 4096, 128, 18>), dim3(fa.nitems), dim3(512), 0, st, P, D,
                            level, sweep, items, fa);
 }
 
