@@ -1174,23 +1174,90 @@ __device__ __forceinline__ void member_new(const TileShared<W, CAPH, CAPM, NCD>&
     }
 }
 
+// exchanges at distance J inside one thread's 8 consecutive entries v[0..8) (first index i0),
+// for the merge of blocks of size k
+template <int J>
+__device__ __forceinline__ void bitonic_regs(int32_t (&v)[8], int i0, int k) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int f = e ^ J;
+        if (f > e) {
+            const bool up = ((i0 + e) & k) == 0;
+            const int32_t lo = v[e], hi = v[f];
+            if ((lo > hi) == up) {
+                v[e] = hi;
+                v[f] = lo;
+            }
+        }
+    }
+}
+
+// Bitonic sort of a[0..np2) in LDS (np2 a power of two). Each thread holds 8 consecutive entries
+// in registers for every exchange at distance < 8; exchanges at distance >= 8 go through LDS,
+// one pair per iteration.
 template <int W>
 __device__ void bitonic_sort(int32_t* a, int np2) {
-    for (int k = 2; k <= np2; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int i = threadIdx.x; i < np2; i += W) {
-                int l = i ^ jj;
-                if (l > i) {
-                    int32_t va = a[i], vb = a[l];
-                    bool up = (i & k) == 0;
-                    if ((va > vb) == up) {
-                        a[i] = vb;
-                        a[l] = va;
+    const int tid = threadIdx.x;
+    if (np2 < 8 || np2 > 8 * W) {
+        for (int k = 2; k <= np2; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int i = tid; i < np2; i += W) {
+                    int l = i ^ jj;
+                    if (l > i) {
+                        int32_t va = a[i], vb = a[l];
+                        bool up = (i & k) == 0;
+                        if ((va > vb) == up) {
+                            a[i] = vb;
+                            a[l] = va;
+                        }
                     }
+                }
+                __syncthreads();
+            }
+        }
+        return;
+    }
+    const int nchunk = np2 >> 3;
+    int32_t v[8];
+    // blocks of 2, 4 and 8: within each thread's chunk
+    if (tid < nchunk) {
+        const int i0 = tid << 3;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = a[i0 + e];
+        bitonic_regs<1>(v, i0, 2);
+        bitonic_regs<2>(v, i0, 4);
+        bitonic_regs<1>(v, i0, 4);
+        bitonic_regs<4>(v, i0, 8);
+        bitonic_regs<2>(v, i0, 8);
+        bitonic_regs<1>(v, i0, 8);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[i0 + e] = v[e];
+    }
+    __syncthreads();
+    for (int k = 16; k <= np2; k <<= 1) {
+        for (int jj = k >> 1; jj >= 8; jj >>= 1) {
+            for (int q = tid; q < (np2 >> 1); q += W) {
+                const int i = ((q / jj) * (jj << 1)) + (q % jj), l = i + jj;
+                const int32_t va = a[i], vb = a[l];
+                const bool up = (i & k) == 0;
+                if ((va > vb) == up) {
+                    a[i] = vb;
+                    a[l] = va;
                 }
             }
             __syncthreads();
         }
+        if (tid < nchunk) {
+            const int i0 = tid << 3;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = a[i0 + e];
+            bitonic_regs<4>(v, i0, k);
+            bitonic_regs<2>(v, i0, k);
+            bitonic_regs<1>(v, i0, k);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a[i0 + e] = v[e];
+        }
+        __syncthreads();
     }
 }
 
