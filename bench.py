@@ -8,7 +8,9 @@ A step is one sweep. Prints one JSON line:
   value         bead-updates/s of the timed sweeps (beads displaced per Metropolis test,
                 wavelet and plane wave, accepted or not, summed; inputs resident in HBM)
   tau_per_wall_s  physical time (units of tau) advanced per wall-clock second
-  roofline      the dominant kernel class, timed with HIP events on the library's stream
+  accepted_bead_updates_per_s  beads displaced by accepted moves per second
+  roofline      the dominant kernel class, timed with HIP events on the library's stream, beside
+                the bandwidth of a plain 1 GiB device copy measured in the same run
   cpu_baseline  the FP64 oracle on the host, on a bounded sample of sweeps of the same state
   mixed         the same system in mixed precision (FP32 energy terms, FP64 recheck near the
                 threshold), from the FP64 run's final state
@@ -90,8 +92,10 @@ def run_gpu(cfg, precision: str, equilibrate: int, warmup: int, steps: int, star
     o1 = g.observables()
     tau1 = g.tau().sum()
     beads = int(o1["bead_updates"].sum() - o0["bead_updates"].sum() + o1["pw_bead_updates"] - o0["pw_bead_updates"])
+    acc_beads = int(o1["accepted_bead_updates"] - o0["accepted_bead_updates"])
     res = dict(
         seconds=dt, steps=steps, bead_updates=beads, bead_updates_per_s=beads / dt, ms_per_step=1000.0 * dt / steps,
+        accepted_bead_updates_per_s=acc_beads / dt,
         tau_per_wall_s=(tau1 - tau0) / dt, sweeps_per_s=steps / dt,
         acceptance=[round(float(a) / max(1, b), 4) for a, b in
                     zip(o1["accepts"] - o0["accepts"], o1["attempts"] - o0["attempts"]) if b > 0],
@@ -106,7 +110,7 @@ def run_batched(cfg, precision: str, equilibrate: int, warmup: int, steps: int) 
     g, r = run_gpu(cfg, precision, equilibrate, warmup, steps)
     nsys = len(cfg["sys_offset"]) - 1
     out = dict(value=round(r["bead_updates_per_s"], 1), unit="bead-updates/s", ms_per_step=round(r["ms_per_step"], 3),
-               systems=nsys, beads=int(cfg["sys_offset"][-1]), precision=precision,
+               accepted_bead_updates_per_s=round(r["accepted_bead_updates_per_s"], 1), systems=nsys, beads=int(cfg["sys_offset"][-1]), precision=precision,
                tau_per_wall_s_per_system=round(r["tau_per_wall_s"] / nsys, 4),
                tau_per_wall_s_total=round(r["tau_per_wall_s"], 4), overflows=r["overflows"],
                kernel_ms={k: [round(v[0], 3), v[1]] for k, v in r["kernel_ms"].items()})
@@ -132,6 +136,23 @@ def run_oracle(cfg, start, sweep0: int, budget_s: float):
     return dict(value=beads / dt, unit="bead-updates/s", cores=1, kind="oracle",
                 sample=f"{n} sweeps of the equilibrated workload state, single-threaded FP64 C (gcc -O2)",
                 seconds=round(dt, 2), tau_per_wall_s=float(o.tau().sum()) / dt)
+
+
+def copy_bandwidth_gbs(mib: int = 1024, reps: int = 10) -> float:
+    """HBM bandwidth of a plain device-to-device copy (bytes read + written per second), the
+    measured counterpart of the vendor peak"""
+    import torch
+
+    a = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * a.numel() * 8 * reps / (e0.elapsed_time(e1) / 1000.0) / 1e9
 
 
 def main():
@@ -189,6 +210,7 @@ def main():
     traffic = measured_traffic(dom)
     roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 3), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=achieved / HBM_PEAK_GBS, traffic=traffic, traffic_unit="bytes per launch",
+                measured_copy_gbs=round(copy_bandwidth_gbs(), 1),
                 avg_launch_us=round(avg_s * 1e6, 2),
                 launches=launches, algorithmic_bytes_per_launch=int(alg),
                 share_of_step=round(ms / (r64["seconds"] * 1000.0), 3))
@@ -216,9 +238,11 @@ def main():
                              "L=84 (c/c*~1), lambda 1..21 octave levels + plane waves, A0=0.5, plain FP64 GPU path",
                     n_beads=N, box_L=84.0, equilibration_sweeps=args.equilibrate),
         tau_per_wall_s=round(r64["tau_per_wall_s"], 4), sweeps_per_s=round(r64["sweeps_per_s"], 2),
+        accepted_bead_updates_per_s=round(r64["accepted_bead_updates_per_s"], 1),
         acceptance_per_level=r64["acceptance"], roofline=roof, cpu_baseline=cpu,
         mixed=dict(value=round(rmix["bead_updates_per_s"], 1), ms_per_step=round(rmix["ms_per_step"], 3),
                    tau_per_wall_s=round(rmix["tau_per_wall_s"], 4), rechecks=rmix["rechecks"],
+                   accepted_bead_updates_per_s=round(rmix["accepted_bead_updates_per_s"], 1),
                    ratio_vs_fp64=round(rmix["bead_updates_per_s"] / r64["bead_updates_per_s"], 3)),
         batched=batched,
         kernel_ms_fp64={k: [round(v[0], 3), v[1]] for k, v in kt.items()},

@@ -109,6 +109,8 @@ typedef struct {
                                              (must be 0; the pass then ran out of order) */
     int64_t fallback_cells;               /* cells of LDS-tile levels whose halo did not fit the
                                              tile, run on the global-list path instead */
+    int64_t accepted_bead_updates;        /* beads displaced by accepted moves (a k = 0 plane
+                                             wave displaces none) */
 } wmc_obs;
 
 /* One trace record per Metropolis test (kind 0 wavelet, 2 plane wave) and per cell phase

@@ -21,7 +21,9 @@ MAX_LEVELS = 16
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (contraction off so the schedule arithmetic is IEEE-plain)."""
-    if force or not os.path.exists(LIB_PATH):
+    stale = not os.path.exists(LIB_PATH) or any(
+        os.path.getmtime(os.path.join(HERE, f)) > os.path.getmtime(LIB_PATH) for f in SOURCES + ["wmc_oracle.h", "wo_internal.h"])
+    if force or stale:
         cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fPIC", "-shared", "-o", LIB_PATH]
         cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
         subprocess.run(cmd, check=True)
@@ -47,7 +49,7 @@ class Obs(C.Structure):
         for name in ("trials", "hits", "attempts", "accepts", "caps", "redraws", "bead_updates")
     ] + [(name, C.c_int64) for name in (
         "pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates",
-        "violations", "accepted_total")]
+        "violations", "accepted_total", "accepted_bead_updates")]
 
 
 class TraceRec(C.Structure):
@@ -200,7 +202,7 @@ class Oracle:
         for name in ("trials", "hits", "attempts", "accepts", "caps", "redraws", "bead_updates"):
             d[name] = np.array(getattr(o, name)[:], dtype=np.int64)
         for name in ("pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates",
-                     "violations", "accepted_total"):
+                     "violations", "accepted_total", "accepted_bead_updates"):
             d[name] = getattr(o, name)
         return d
 

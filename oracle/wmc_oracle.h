@@ -69,6 +69,7 @@ typedef struct {
     int64_t pw_chains, pw_attempts, pw_accepts, pw_k0, pw_caps, pw_bead_updates;
     int64_t violations;                 /* bonds longer than the halo width (harmonic) */
     int64_t accepted_total;             /* wavelet + plane-wave accepted chains */
+    int64_t accepted_bead_updates;      /* beads displaced by accepted moves (k = 0: none) */
 } wo_obs;
 
 typedef struct {

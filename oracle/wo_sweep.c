@@ -374,6 +374,7 @@ static int wavelet_attempt(wo_ctx* c, wo_system* s, int sysid, int level, int64_
             cl_moved(c, s, j);
         }
         c->obs.accepts[level]++;
+        c->obs.accepted_bead_updates += n;
     }
     return acc;
 }
@@ -538,6 +539,7 @@ static int pw_attempt(wo_ctx* c, wo_system* s, int sysid, int64_t h, int r, cons
     c->obs.pw_bead_updates += s->N;
     trace_push(c, 2, sysid, -1, h, 0, r, s->N, acc, extra, dU, thr);
     if (acc) {
+        c->obs.accepted_bead_updates += s->N;
         for (int64_t j = s->b0; j < s->b1; ++j) {
             c->x[j] = c->nx[j];
             c->y[j] = c->ny[j];

@@ -985,6 +985,7 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
             d_local = block_max<W>(d_local, sh.red);  // barrier: writes visible
             if (accept) {
                 ++c_acc;
+                if (tid == 0) atomicAdd(&D.cnt[CNT_ACC_BEADS], (unsigned long long)n);
                 break;
             }
             if (++r >= P.retry_cap) {
@@ -1688,6 +1689,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             __syncthreads();
             if (accept) {
                 ++c_acc;
+                if (tid == 0) atomicAdd(&D.cnt[CNT_ACC_BEADS], (unsigned long long)n);
                 E += dmax;
                 if (E > 0.5 * tg.f) {
                     tile_index<W, CAPH, CAPM, NCD>(sh, nH, g, tg);
@@ -2167,6 +2169,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                 group_barrier(bar, G, gen);  // 4: accepted positions
                 dloc = fmax(dloc, coop_max(c_dl, G, sh));
                 ++c_acc_n;
+                if (wg == 0 && tid == 0) atomicAdd(&D.cnt[CNT_ACC_BEADS], (unsigned long long)n);
                 break;
             }
             __syncthreads();
@@ -2447,6 +2450,7 @@ __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t swe
                 }
                 Dg += AF;
                 ++c_acc;
+                if (tid == 0) atomicAdd(&D.cnt[CNT_ACC_BEADS], (unsigned long long)s.N);
                 __syncthreads();
                 break;
             }
@@ -2609,6 +2613,7 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
                 }
                 Dg += AF;
                 ++c_acc;
+                if (rank == 0 && tid == 0) atomicAdd(&D.cnt[CNT_ACC_BEADS], (unsigned long long)s.N);
                 group_barrier(bar, G, gen);
                 break;
             }

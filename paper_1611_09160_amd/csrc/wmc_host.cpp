@@ -1128,6 +1128,7 @@ extern "C" int wmc_observables(wmc_ctx* c, wmc_obs* o) {
     o->accepted_total = cnt[CNT_ACCEPTED];
     o->wait_timeouts = cnt[CNT_FLOWWAIT];
     o->fallback_cells = cnt[CNT_FALLBACK];
+    o->accepted_bead_updates = cnt[CNT_ACC_BEADS];
     return 0;
 }
 

@@ -23,6 +23,7 @@ constexpr int CNT_RECHECK = 138;
 constexpr int CNT_REBUILD = 139;
 constexpr int CNT_ACCEPTED = 140;
 constexpr int CNT_FLOWWAIT = 141;   // dependency waits that hit their spin limit (must be 0)
+constexpr int CNT_ACC_BEADS = 143;  // beads displaced by accepted moves, wavelet and plane wave
 constexpr int CNT_FALLBACK = 142;   // LDS-tile cells whose halo did not fit: run on the global-list path
 constexpr int CNT_TOTAL = 160;
 

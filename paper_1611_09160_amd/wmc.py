@@ -39,7 +39,7 @@ class Obs(C.Structure):
     ] + [(name, C.c_int64) for name in (
         "pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates",
         "violations", "accepted_total", "rechecks", "overflows", "grid_rebuilds", "wait_timeouts",
-        "fallback_cells")]
+        "fallback_cells", "accepted_bead_updates")]
 
 
 class TraceRec(C.Structure):
@@ -206,7 +206,8 @@ class WMC:
         for name in ("trials", "hits", "attempts", "accepts", "caps", "redraws", "bead_updates"):
             d[name] = np.array(getattr(o, name)[:], dtype=np.int64)
         for name in ("pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates", "violations",
-                     "accepted_total", "rechecks", "overflows", "grid_rebuilds", "wait_timeouts", "fallback_cells"):
+                     "accepted_total", "rechecks", "overflows", "grid_rebuilds", "wait_timeouts", "fallback_cells",
+                     "accepted_bead_updates"):
             d[name] = getattr(o, name)
         return d
 

@@ -61,7 +61,7 @@ def compare_counters(og, oo):
     for k in ("trials", "hits", "attempts", "accepts", "caps", "redraws", "bead_updates"):
         np.testing.assert_array_equal(og[k], oo[k], err_msg=k)
     for k in ("pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates", "violations",
-              "accepted_total"):
+              "accepted_total", "accepted_bead_updates"):
         assert og[k] == oo[k], (k, og[k], oo[k])
     assert og["overflows"] == 0
     assert og.get("wait_timeouts", 0) == 0

@@ -319,3 +319,30 @@ def test_periodic_k_recycling_bias_is_visible(oracle_mod):
     balanced; the oracle implements it as written and the bias shows at the 2 % level here."""
     z = dimer_bond_z(oracle_mod, retry_cap=64, samples=120)
     assert np.max(np.abs(z)) > 5.0, z
+
+
+def test_accepted_bead_updates_count(oracle_mod):
+    """The accepted-bead counter (the paper's cost unit, particles per move, counted for accepted
+    moves only) equals the sum of n over the accepted tests of the trace (a k = 0 plane wave moves
+    no bead), and bounds the number of beads whose position changed."""
+    from paper_1611_09160_amd import workloads as W
+
+    sysd = W.make_solution(n_chains=12, n_beads=16, box_L=9.0, seed=5)
+    pos, coff = sysd["pos"], sysd["chain_offset"]
+    p = dict(periodic=1, plane_waves=1, box_L=9.0, lambda_min=1.0, lambda_max=2.25, bond_type="fene",
+             k_bond=30.0, R0=1.5, wca=1, A0=0.5, seed=67)
+    o = oracle_mod.Oracle(p, [0, len(pos)], coff, pos, trace_capacity=2_000_000)
+    o.sweep(2)
+    o.trace()
+    ob0 = o.observables()
+    before = o.positions()
+    o.sweep(2)
+    after = o.positions()
+    tr = o.trace()
+    ob1 = o.observables()
+    moves = tr[(tr["kind"] != 1) & (tr["accepted"] == 1)]
+    counted = ob1["accepted_bead_updates"] - ob0["accepted_bead_updates"]
+    assert counted == int(moves["n"].sum())
+    assert np.any(tr[tr["kind"] == 2]["accepted"] == 1)
+    changed = int(np.sum(np.any(after != before, axis=1)))
+    assert 0 < changed <= counted
