@@ -1804,7 +1804,7 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
                   const int32_t* bmap, int nblocks, hipStream_t st) {
     if (nblocks <= 0) return;
     if (variant == V64)
-        hipLaunchKernelGGL((k_phase<64, 1024, 256, 512, 128, 8>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour,
+        hipLaunchKernelGGL((k_phase<64, 1024, 256, 512, 32, 8>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour,
                            sweep, bmap, nblocks);
     else if (variant == V256)
         hipLaunchKernelGGL((k_phase<256, 4096, 1024, 1024, 512, 12>), dim3(nblocks), dim3(256), 0, st, P, D, level,
@@ -1891,10 +1891,10 @@ void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int le
     // per cell, since the pass is its longest chain of cells; many more cells (a batch) fill the
     // GPU better with one wave per cell
     if (variant == V64 && fa.nitems <= 4096)
-        hipLaunchKernelGGL((k_level_flow<256, 1024, 256, 512, 128, 8>), dim3(fa.nitems), dim3(256), 0, st, P, D,
+        hipLaunchKernelGGL((k_level_flow<256, 1024, 256, 512, 32, 8>), dim3(fa.nitems), dim3(256), 0, st, P, D,
                            level, sweep, items, fa);
     else if (variant == V64)
-        hipLaunchKernelGGL((k_level_flow<64, 1024, 256, 512, 128, 8>), dim3(fa.nitems), dim3(64), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_level_flow<64, 1024, 256, 512, 32, 8>), dim3(fa.nitems), dim3(64), 0, st, P, D, level,
                            sweep, items, fa);
     else if (variant == V256)
         hipLaunchKernelGGL((k_level_flow<256, 4096, 1024, 1024, 512, 12>), dim3(fa.nitems), dim3(256), 0, st, P, D,
