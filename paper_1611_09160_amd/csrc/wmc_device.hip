@@ -1366,8 +1366,17 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                         int nH, int n, int mode, double& acc, double& sens, unsigned long long& viol) {
     const int tid = threadIdx.x;
     const double L = s.L, invL = s.invL;
+    const int NR = min(tg.nc, (int)floor(2.0 * R * tg.invf) + 2);
+    const int per = NR * NR;
+    const int items = n * per;
+    // in a 256-thread tile, bonds on the last wave and pair items on the others when the items
+    // fit there: the two chains of dependent loads then run on different SIMDs at once (in the
+    // 512-thread tile the pair items need every lane)
+    const bool split = W == 256 && P.bond_type != WMC_BOND_NONE && P.wca && items <= W - 64;
+    const int b0 = split ? tid - (W - 64) : tid, bstride = split ? 64 : W;
+    const int p0 = split ? (tid < W - 64 ? tid : items) : tid, pstride = split ? W - 64 : W;
     if (P.bond_type != WMC_BOND_NONE) {
-        for (int k = tid; k < n; k += W) {
+        for (int k = b0 < 0 ? n : b0; k < n; k += bstride) {
             const int sl = sh.M[k];
             const int32_t raw = sh.id[sl];
             const int32_t j = raw & ID_MASK;
@@ -1411,10 +1420,7 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
         }
     }
     if (P.wca) {
-        const int NR = min(tg.nc, (int)floor(2.0 * R * tg.invf) + 2);
-        const int per = NR * NR;
-        const int items = n * per;
-        for (int it = tid; it < items; it += W) {
+        for (int it = p0; it < items; it += pstride) {
             const int k = it / per, q = it - k * per;
             const int qy = q % NR, qz = q / NR;
             const int sl = sh.M[k];
