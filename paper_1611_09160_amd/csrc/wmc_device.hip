@@ -1615,21 +1615,41 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             const double u_acc = cs.oc();
             __syncthreads();
             int n = 0;
-            for (int c0 = 0; c0 < nS; c0 += W) {
-                int i = c0 + tid;
-                bool f = false;
-                int sl = 0;
-                if (i < nS) {
-                    sl = sh.S[i];
-                    double dx = minimg(g, sh.x[sl] - b[0]), dy = minimg(g, sh.y[sl] - b[1]),
-                           dz = minimg(g, sh.z[sl] - b[2]);
-                    double d2 = (dx * dx + dy * dy) + dz * dz;
-                    f = d2 <= lam2 || sl == as;
+            if (W >= 256 && nS > W && nS <= 32 * W) {
+                // q consecutive reach entries per thread, one workgroup scan (member order kept);
+                // a one-wave tile keeps the round-by-round scan, which measured faster there
+                const int q = (nS + W - 1) / W, i0 = tid * q;
+                uint32_t mask = 0;
+                for (int u = 0; u < q; ++u) {
+                    const int i = i0 + u;
+                    if (i < nS) {
+                        const int sl = sh.S[i];
+                        const double dx = minimg(g, sh.x[sl] - b[0]), dy = minimg(g, sh.y[sl] - b[1]),
+                                     dz = minimg(g, sh.z[sl] - b[2]);
+                        if (((dx * dx + dy * dy) + dz * dz) <= lam2 || sl == as) mask |= 1u << u;
+                    }
                 }
                 int before;
-                int tot = block_scan_flag<W>(f, before, sh.redi);
-                if (f) sh.M[n + before] = (int16_t)sl;
-                n += tot;
+                n = block_scan_count<W>(__popc(mask), before, sh.redi);
+                for (int u = 0; u < q; ++u)
+                    if ((mask >> u) & 1u) sh.M[before++] = sh.S[i0 + u];
+            } else {
+                for (int c0 = 0; c0 < nS; c0 += W) {
+                    int i = c0 + tid;
+                    bool f = false;
+                    int sl = 0;
+                    if (i < nS) {
+                        sl = sh.S[i];
+                        double dx = minimg(g, sh.x[sl] - b[0]), dy = minimg(g, sh.y[sl] - b[1]),
+                               dz = minimg(g, sh.z[sl] - b[2]);
+                        double d2 = (dx * dx + dy * dy) + dz * dz;
+                        f = d2 <= lam2 || sl == as;
+                    }
+                    int before;
+                    int tot = block_scan_flag<W>(f, before, sh.redi);
+                    if (f) sh.M[n + before] = (int16_t)sl;
+                    n += tot;
+                }
             }
             __syncthreads();
             WaveDesc wv;
