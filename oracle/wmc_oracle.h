@@ -21,7 +21,8 @@
  * (levels of octave bands, cells of side >= 2 lambda_hi + r_int, 8 colours, per-cell
  * trial counts by stochastic rounding, per-cell retry chains), drawing every random
  * number from the same counter-based Philox4x32-10 streams. The schedule is a reading
- * of the paper (which is serial); its parts are listed in the design doc.
+ * of the paper, which is serial: it fixes neither the cells, nor the colours, nor the
+ * per-cell trial counts, only the distributions the moves are drawn from.
  */
 #ifndef WMC_ORACLE_H
 #define WMC_ORACLE_H
