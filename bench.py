@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by a plain copy of
 # known size (profiles/traffic_sweep_semidilute32k.md); valid only for the device source they
 # were measured on, otherwise the bench reports null
-TRAFFIC_SOURCE_SHA16 = "ec73dbe813dc201d"
-TRAFFIC_BYTES_PER_LAUNCH = {"level0": 193.34e6, "level1": 32.18e6, "level2": 18.78e6, "level3": 29.40e6, "level4": 5.80e6, "plane_waves": 28.94e6, "grid": 9.59e6}
+TRAFFIC_SOURCE_SHA16 = "ab0f705cc33bdf44"
+TRAFFIC_BYTES_PER_LAUNCH = {"level0": 191.42e6, "level1": 31.40e6, "level2": 18.89e6, "level3": 29.69e6, "level4": 5.82e6, "plane_waves": 28.96e6, "grid": 9.59e6}
 
 
 def measured_traffic(cls: str):

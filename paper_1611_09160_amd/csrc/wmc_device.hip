@@ -1493,16 +1493,64 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             double lo = g.o[a] + (double)ic[a] * g.h - R;
             fine_range(lo, lo + g.h + 2.0 * R, s.invg, s.nf, f0[a], cn[a]);
         }
-        const int total = cn[0] * cn[1] * cn[2];
-        for (int q = tid; q < total; q += W) {
-            int qx = q % cn[0], qy = (q / cn[0]) % cn[1], qz = q / (cn[0] * cn[1]);
-            int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
-            int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
-            for (int k = D.fstart[fc]; k < D.fstart[fc + 1]; ++k) {
-                int32_t j = D.fidx[k];
+        // each (y, z) row of the box is one run of consecutive fine cells in x, so its beads are
+        // one contiguous range of the sorted index (two where the box wraps in x): the ranges and
+        // their prefix go into the position arrays (free until the sort below), then every
+        // thread takes beads t, t + W, ... of the concatenation
+        const bool wrapx = f0[0] + cn[0] > s.nf;
+        const int nseg = cn[1] * cn[2] * (wrapx ? 2 : 1);
+        int32_t* segB = reinterpret_cast<int32_t*>(sh.x);  // first index entry of each range
+        int32_t* segP = reinterpret_cast<int32_t*>(sh.y);  // exclusive prefix of the range lengths
+        if (nseg + 1 <= 2 * CAPH) {
+            for (int q = tid; q < nseg; q += W) {
+                const int r = wrapx ? (q >> 1) : q, part = wrapx ? (q & 1) : 0;
+                const int fy = (f0[1] + r % cn[1]) % s.nf, fz = (f0[2] + r / cn[1]) % s.nf;
+                const int64_t rowb = s.fine_off + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
+                const int xa = part ? 0 : f0[0];
+                const int xb = wrapx ? (part ? f0[0] + cn[0] - 1 - s.nf : s.nf - 1) : f0[0] + cn[0] - 1;
+                const int a = D.fstart[rowb + xa];
+                segB[q] = a;
+                segP[q] = D.fstart[rowb + xb + 1] - a;
+            }
+            __syncthreads();
+            const int per = (nseg + W - 1) / W;
+            const int c0 = min(nseg, tid * per), c1 = min(nseg, c0 + per);
+            int run = 0;
+            for (int c = c0; c < c1; ++c) run += segP[c];
+            int before;
+            const int total = block_scan_count<W>(run, before, sh.redi);
+            for (int c = c0; c < c1; ++c) {
+                const int v = segP[c];
+                segP[c] = before;
+                before += v;
+            }
+            if (tid == 0) segP[nseg] = total;
+            __syncthreads();
+            for (int t = tid; t < total; t += W) {
+                // the last range starting at or before t (it holds t: the next one starts after it)
+                int lo = 0, hi = nseg - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (segP[mid] <= t) lo = mid; else hi = mid - 1;
+                }
+                const int32_t j = D.fidx[segB[lo] + (t - segP[lo])];
                 if (dist2_cell(g, ic, D.x[j], D.y[j], D.z[j]) <= rh2) {
                     int idx = atomicAdd(&sh.count, 1);
                     if (idx < CAPH) sh.id[idx] = j;
+                }
+            }
+        } else {
+            const int total = cn[0] * cn[1] * cn[2];
+            for (int q = tid; q < total; q += W) {
+                int qx = q % cn[0], qy = (q / cn[0]) % cn[1], qz = q / (cn[0] * cn[1]);
+                int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
+                int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
+                for (int k = D.fstart[fc]; k < D.fstart[fc + 1]; ++k) {
+                    int32_t j = D.fidx[k];
+                    if (dist2_cell(g, ic, D.x[j], D.y[j], D.z[j]) <= rh2) {
+                        int idx = atomicAdd(&sh.count, 1);
+                        if (idx < CAPH) sh.id[idx] = j;
+                    }
                 }
             }
         }
