@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by a plain copy of
 # known size (profiles/traffic_sweep_semidilute32k.md); valid only for the device source they
 # were measured on, otherwise the bench reports null
-TRAFFIC_SOURCE_SHA16 = "ab0f705cc33bdf44"
-TRAFFIC_BYTES_PER_LAUNCH = {"level0": 191.42e6, "level1": 31.40e6, "level2": 18.89e6, "level3": 29.69e6, "level4": 5.82e6, "plane_waves": 28.96e6, "grid": 9.59e6}
+TRAFFIC_SOURCE_SHA16 = "77de08ebf619f2f8"
+TRAFFIC_BYTES_PER_LAUNCH = {"level0": 205.40e6, "level1": 31.59e6, "level2": 18.96e6, "level3": 29.74e6, "level4": 5.82e6, "plane_waves": 28.91e6, "grid": 9.59e6}
 
 
 def measured_traffic(cls: str):

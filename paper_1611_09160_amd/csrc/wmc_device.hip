@@ -2493,18 +2493,26 @@ __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t swe
                     fine_range(cy - R, cy + R, s.invg, s.nf, f0[1], cn[1]);
                     fine_range(cz - R, cz + R, s.invg, s.nf, f0[2], cn[2]);
                     for (int qz = 0; qz < cn[2]; ++qz)
-                        for (int qy = 0; qy < cn[1]; ++qy)
-                            for (int qx = 0; qx < cn[0]; ++qx) {
-                                int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
-                                int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
-                                for (int q = D.fstart[fc]; q < D.fstart[fc + 1]; ++q) {
+                        for (int qy = 0; qy < cn[1]; ++qy) {
+                            // the row's cells f0[0] .. f0[0] + cn[0] - 1 (mod nf) are one range of
+                            // the sorted index, two where they wrap, visited in the same order
+                            const int fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
+                            const int64_t rowb = s.fine_off + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
+                            const int xe = f0[0] + cn[0];
+                            int q = D.fstart[rowb + f0[0]], qend = D.fstart[rowb + min(xe, s.nf)];
+                            for (int part = 0; part < 2; ++part) {
+                                for (; q < qend; ++q) {
                                     int32_t m = D.fidx[q];
                                     if (m <= j) continue;
                                     double r2o = pair_r2(P, invL, L, jx, jy, jz, D.x[m], D.y[m], D.z[m]);
                                     double r2n = pair_r2(P, invL, L, NX[j], NY[j], NZ[j], NX[m], NY[m], NZ[m]);
                                     if (r2o < P.rc2 || r2n < P.rc2) acc += u_pair(P, r2n) - u_pair(P, r2o);
                                 }
+                                if (xe <= s.nf) break;
+                                q = D.fstart[rowb];
+                                qend = D.fstart[rowb + (xe - s.nf)];
                             }
+                        }
                 }
             }
             const double dU = block_sum<1024>(acc, red);
@@ -2650,18 +2658,26 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
                     fine_range(cy - R, cy + R, s.invg, s.nf, f0[1], cn[1]);
                     fine_range(cz - R, cz + R, s.invg, s.nf, f0[2], cn[2]);
                     for (int qz = 0; qz < cn[2]; ++qz)
-                        for (int qy = 0; qy < cn[1]; ++qy)
-                            for (int qx = 0; qx < cn[0]; ++qx) {
-                                int fx = (f0[0] + qx) % s.nf, fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
-                                int64_t fc = s.fine_off + fx + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
-                                for (int q = D.fstart[fc]; q < D.fstart[fc + 1]; ++q) {
+                        for (int qy = 0; qy < cn[1]; ++qy) {
+                            // the row's cells f0[0] .. f0[0] + cn[0] - 1 (mod nf) are one range of
+                            // the sorted index, two where they wrap, visited in the same order
+                            const int fy = (f0[1] + qy) % s.nf, fz = (f0[2] + qz) % s.nf;
+                            const int64_t rowb = s.fine_off + (int64_t)s.nf * (fy + (int64_t)s.nf * fz);
+                            const int xe = f0[0] + cn[0];
+                            int q = D.fstart[rowb + f0[0]], qend = D.fstart[rowb + min(xe, s.nf)];
+                            for (int part = 0; part < 2; ++part) {
+                                for (; q < qend; ++q) {
                                     int32_t m = D.fidx[q];
                                     if (m <= j) continue;
                                     double r2o = pair_r2(P, invL, L, jx, jy, jz, D.x[m], D.y[m], D.z[m]);
                                     double r2n = pair_r2(P, invL, L, NX[j], NY[j], NZ[j], NX[m], NY[m], NZ[m]);
                                     if (r2o < P.rc2 || r2n < P.rc2) acc += u_pair(P, r2n) - u_pair(P, r2o);
                                 }
+                                if (xe <= s.nf) break;
+                                q = D.fstart[rowb];
+                                qend = D.fstart[rowb + (xe - s.nf)];
                             }
+                        }
                 }
             }
             double part = block_sum<256>(acc, red);
