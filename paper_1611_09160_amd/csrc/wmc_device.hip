@@ -700,7 +700,7 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
     }
 }
 
-template <int W, int CAPS, int CAPM>
+template <int W, int CAPS, int CAPM, bool MIXED>
 __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& D,
                                                        PhaseShared<W, CAPS, CAPM>& sh, int sys,
                              int level, int colour, int64_t local, int64_t sweep, const Grid& g) {
@@ -833,7 +833,7 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
     unsigned long long c_hits = 0, c_att = 0, c_acc = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0;
     double d_local = 0.0;  // max drift of beads moved in this phase
 
-    const bool mixed = P.precision == WMC_MIXED;
+    constexpr bool mixed = MIXED;
     const double L = s.L, invL = s.invL;
     const double lam_hi = lv.hi;
 
@@ -1459,7 +1459,7 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
 
 // returns false (before any move) when the halo does not fit; the caller then uses the
 // global path for this cell
-template <int W, int CAPH, int CAPM, int NCD>
+template <int W, int CAPH, int CAPM, int NCD, bool MIXED>
 __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShared<W, CAPH, CAPM, NCD>& sh, int sys,
                                   int level, int colour, int64_t local, int64_t sweep, const Grid& g) {
     const SysDesc& s = D.sys[sys];
@@ -1608,7 +1608,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     }
     unsigned long long c_hits = 0, c_att = 0, c_acc = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0;
     double d_local = 0.0;
-    const bool mixed = P.precision == WMC_MIXED;
+    constexpr bool mixed = MIXED;
     // trials are drawn W at a time (one per lane); the draws (lambda, anchor, ball vector, stream
     // position) do not depend on positions, so a lane keeps its trial across the chains of earlier
     // hits and only its hit test, which reads the anchor's current position, is repeated
@@ -1847,7 +1847,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     return true;
 }
 
-template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD>
+template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, bool MIXED>
 __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, int colour, int64_t sweep,
                                              const int32_t* bmap, int nblocks) {
     __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD> sh;
@@ -1857,9 +1857,9 @@ __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, 
         const LevelDesc& lv = D.lev[s.lvl_off + level];
         Grid g;
         make_grid(P, D, s, lv, sys, level, sweep, g);
-        if (lv.use_global || !process_cell_tile<W, CAPH, CAPMT, NCD>(P, D, sh.t, sys, level, colour, local, sweep, g)) {
+        if (lv.use_global || !process_cell_tile<W, CAPH, CAPMT, NCD, MIXED>(P, D, sh.t, sys, level, colour, local, sweep, g)) {
             __syncthreads();
-            process_cell<W, CAPS, CAPM>(P, D, sh.g, sys, level, colour, local, sweep, g);
+            process_cell<W, CAPS, CAPM, MIXED>(P, D, sh.g, sys, level, colour, local, sweep, g);
         }
     } else {
         const SysDesc& s = D.sys[0];
@@ -1870,22 +1870,33 @@ __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, 
                 mz = (g.n[2] - ((colour >> 2) & 1) + 1) / 2;
         int64_t cells = mx * my * mz;
         for (int64_t local = blockIdx.x; local < cells; local += gridDim.x)
-            process_cell<W, CAPS, CAPM>(P, D, sh.g, 0, level, colour, local, sweep, g);
+            process_cell<W, CAPS, CAPM, MIXED>(P, D, sh.g, 0, level, colour, local, sweep, g);
     }
 }
 
-void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
+template <bool M>
+static void launch_phase_t(int variant, const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
                   const int32_t* bmap, int nblocks, hipStream_t st) {
     if (nblocks <= 0) return;
     if (variant == V64)
-        hipLaunchKernelGGL((k_phase<64, 1024, 256, 512, 32, 8>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour,
+        hipLaunchKernelGGL((k_phase<64, 1024, 256, 512, 32, 8, M>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour,
                            sweep, bmap, nblocks);
     else if (variant == V256)
-        hipLaunchKernelGGL((k_phase<256, 4096, 1024, 1024, 512, 12>), dim3(nblocks), dim3(256), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_phase<256, 4096, 1024, 1024, 512, 12, M>), dim3(nblocks), dim3(256), 0, st, P, D, level,
                            colour, sweep, bmap, nblocks);
     else
-        hipLaunchKernelGGL((k_phase<512, 8192, 4096, 4096, 128, 18>), dim3(nblocks), dim3(512), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_phase<512, 8192, 4096, 4096, 128, 18, M>), dim3(nblocks), dim3(512), 0, st, P, D, level,
                            colour, sweep, bmap, nblocks);
+}
+
+// one kernel per precision: the FP32 terms and their recheck cost registers the FP64 path
+// does not need
+void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
+                  const int32_t* bmap, int nblocks, hipStream_t st) {
+    if (P.precision == WMC_MIXED)
+        launch_phase_t<true>(variant, P, D, level, colour, sweep, bmap, nblocks, st);
+    else
+        launch_phase_t<false>(variant, P, D, level, colour, sweep, bmap, nblocks, st);
 }
 
 // ------------------------------------------- level pass in dependency order (LDS tiles)
@@ -1898,7 +1909,7 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
 // (counted in CNT_FLOWWAIT when the bound is hit). Same result as eight colour phases.
 constexpr unsigned FLOW_SPIN_LIMIT = 1u << 24;
 
-template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD>
+template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, bool MIXED>
 __global__ __launch_bounds__(W, 2) void k_level_flow(DevParams P, DevPtrs D, int level, int64_t sweep,
                                                      const int32_t* items, FlowArgs fa) {
     __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD> sh;
@@ -1942,12 +1953,12 @@ __global__ __launch_bounds__(W, 2) void k_level_flow(DevParams P, DevPtrs D, int
     }
     __syncthreads();
     if (tid == 0 && s_timeout) atomicAdd(&D.cnt[CNT_FLOWWAIT], 1ull);
-    if (!process_cell_tile<W, CAPH, CAPMT, NCD>(P, D, sh.t, sys, level, colour, local, sweep, g)) {
+    if (!process_cell_tile<W, CAPH, CAPMT, NCD, MIXED>(P, D, sh.t, sys, level, colour, local, sweep, g)) {
         // the halo does not fit the tile: the global-list path, inline (a call would cost a stack
         // frame and the registers saved around it, for every cell)
         __syncthreads();
         if (tid == 0) atomicAdd(&D.cnt[CNT_FALLBACK], 1ull);
-        process_cell<W, CAPS, CAPM>(P, D, sh.g, sys, level, colour, local, sweep, g);
+        process_cell<W, CAPS, CAPM, MIXED>(P, D, sh.g, sys, level, colour, local, sweep, g);
     }
     // publish: every wave's stores complete, then one release of the epoch
     __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -1958,24 +1969,33 @@ __global__ __launch_bounds__(W, 2) void k_level_flow(DevParams P, DevPtrs D, int
     }
 }
 
-void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
+template <bool M>
+static void launch_level_flow_t(int variant, const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
                        const int32_t* items, const FlowArgs& fa, hipStream_t st) {
     if (fa.nitems <= 0) return;
     // the smallest tile: a few thousand cells (one large system) finish sooner with four waves
     // per cell, since the pass is its longest chain of cells; many more cells (a batch) fill the
     // GPU better with one wave per cell
     if (variant == V64 && fa.nitems <= 4096)
-        hipLaunchKernelGGL((k_level_flow<256, 1024, 256, 512, 32, 8>), dim3(fa.nitems), dim3(256), 0, st, P, D,
+        hipLaunchKernelGGL((k_level_flow<256, 1024, 256, 512, 32, 8, M>), dim3(fa.nitems), dim3(256), 0, st, P, D,
                            level, sweep, items, fa);
     else if (variant == V64)
-        hipLaunchKernelGGL((k_level_flow<64, 1024, 256, 512, 32, 8>), dim3(fa.nitems), dim3(64), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_level_flow<64, 1024, 256, 512, 32, 8, M>), dim3(fa.nitems), dim3(64), 0, st, P, D, level,
                            sweep, items, fa);
     else if (variant == V256)
-        hipLaunchKernelGGL((k_level_flow<256, 4096, 1024, 1024, 512, 12>), dim3(fa.nitems), dim3(256), 0, st, P, D,
+        hipLaunchKernelGGL((k_level_flow<256, 4096, 1024, 1024, 512, 12, M>), dim3(fa.nitems), dim3(256), 0, st, P, D,
                            level, sweep, items, fa);
     else
-        hipLaunchKernelGGL((k_level_flow<512, 8192, 4096, 4096, 128, 18>), dim3(fa.nitems), dim3(512), 0, st, P, D,
+        hipLaunchKernelGGL((k_level_flow<512, 8192, 4096, 4096, 128, 18, M>), dim3(fa.nitems), dim3(512), 0, st, P, D,
                            level, sweep, items, fa);
+}
+
+void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
+                       const int32_t* items, const FlowArgs& fa, hipStream_t st) {
+    if (P.precision == WMC_MIXED)
+        launch_level_flow_t<true>(variant, P, D, level, sweep, items, fa, st);
+    else
+        launch_level_flow_t<false>(variant, P, D, level, sweep, items, fa, st);
 }
 
 // ------------------------------------------------- cell phase of a large level, grid-wide
@@ -2027,6 +2047,7 @@ __device__ __forceinline__ double coop_max(const double* part, int G, CoopShared
 
 // one cell of colour `colour` for the group `grp` (index gi); gen is the group's barrier
 // generation and Dg its system's drift bound, both carried from colour to colour
+template <bool MIXED>
 __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
                           const CoopGroup grp, int gi, int rank, CoopShared& sh, unsigned& gen, double& Dg) {
     const int sys = grp.sys;
@@ -2092,7 +2113,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
     unsigned long long c_hits = 0, c_att = 0, c_acc_n = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0,
                        c_rechk = 0;
     double dloc = 0.0;  // largest drift of beads moved in this phase (same in every workgroup)
-    const bool mixed = P.precision == WMC_MIXED;
+    constexpr bool mixed = MIXED;
     const int qS = (nS + G - 1) / G;
     const int slo = wg * qS, shi = min(nS, slo + qS);
 
@@ -2326,6 +2347,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
     Dg = fmax(Dg, dloc);
 }
 
+template <bool MIXED>
 __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int level, CoopColours cc, int64_t sweep,
                                                   const CoopGroup* groups, const int32_t* wg_group) {
     __shared__ CoopShared sh;
@@ -2337,7 +2359,7 @@ __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int le
     double Dg = __longlong_as_double((long long)D.drift[sys]);
     for (int i = 0; i < cc.n; ++i) {
         const CoopGroup* gt = (const CoopGroup*)((const int32_t*)groups + cc.goff[i]);
-        coop_cell(P, D, level, cc.col[i], sweep, gt[gi], gi, rank, sh, gen, Dg);
+        coop_cell<MIXED>(P, D, level, cc.col[i], sweep, gt[gi], gi, rank, sh, gen, Dg);
     }
 }
 
@@ -2346,11 +2368,15 @@ int cell_coop_blocks() {
     if (nb < 0) {
         int dev = 0, per_cu = 0;
         hipDeviceProp_t prop;
+        int per_cu64 = 0;
+        // the smaller occupancy of the two precision variants, so either launch is co-resident
         if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cell_coop, CW, 0) != hipSuccess || per_cu < 1)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cell_coop<true>, CW, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_cell_coop<false>, CW, 0) != hipSuccess ||
+            std::min(per_cu, per_cu64) < 1)
             nb = 0;
         else
-            nb = std::min(per_cu * prop.multiProcessorCount, COOP_SLOTS);
+            nb = std::min(std::min(per_cu, per_cu64) * prop.multiProcessorCount, COOP_SLOTS);
     }
     return nb;
 }
@@ -2366,7 +2392,8 @@ bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, const Coo
     const CoopGroup* gp = groups;
     const int32_t* wp = wg_group;
     void* args[] = {&Pc, &Dc, &lv, &ccc, &sw, &gp, &wp};
-    return hipLaunchCooperativeKernel((const void*)k_cell_coop, dim3(nwg), dim3(CW), args, 0, st) == hipSuccess;
+    const void* k = P.precision == WMC_MIXED ? (const void*)k_cell_coop<true> : (const void*)k_cell_coop<false>;
+    return hipLaunchCooperativeKernel(k, dim3(nwg), dim3(CW), args, 0, st) == hipSuccess;
 }
 
 // ------------------------------------------------------------------- plane waves
