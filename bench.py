@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by a plain copy of
 # known size (profiles/traffic_sweep_semidilute32k.md); valid only for the device source they
 # were measured on, otherwise the bench reports null
-TRAFFIC_SOURCE_SHA16 = "b9269c4ba07c91bb"
-TRAFFIC_BYTES_PER_LAUNCH = {"level0": 76.76e6, "level1": 19.89e6, "level2": 16.93e6, "level3": 8.92e6, "level4": 3.68e6, "plane_waves": 28.93e6, "grid": 9.59e6}
+TRAFFIC_SOURCE_SHA16 = "6511875e6b2ec5f1"
+TRAFFIC_BYTES_PER_LAUNCH = {"level0": 47.77e6, "level1": 18.13e6, "level2": 16.86e6, "level3": 8.92e6, "level4": 3.68e6, "plane_waves": 28.93e6, "grid": 9.59e6}
 
 
 def measured_traffic(cls: str):

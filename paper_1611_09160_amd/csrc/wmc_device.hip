@@ -1910,7 +1910,7 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
 constexpr unsigned FLOW_SPIN_LIMIT = 1u << 24;
 
 template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, bool MIXED>
-__global__ __launch_bounds__(W, 2) void k_level_flow(DevParams P, DevPtrs D, int level, int64_t sweep,
+__global__ __launch_bounds__(W, (W == 64 || MIXED) ? 2 : 1) void k_level_flow(DevParams P, DevPtrs D, int level, int64_t sweep,
                                                      const int32_t* items, FlowArgs fa) {
     __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD> sh;
     __shared__ int s_idx;
