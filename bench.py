@@ -99,7 +99,7 @@ def run_gpu(cfg, precision: str, equilibrate: int, warmup: int, steps: int, star
         acceptance=[round(float(a) / max(1, b), 4) for a, b in
                     zip(o1["accepts"] - o0["accepts"], o1["attempts"] - o0["attempts"]) if b > 0],
         pw_attempts=int(o1["pw_attempts"] - o0["pw_attempts"]), overflows=int(o1["overflows"]),
-        violations=int(o1["violations"]), rechecks=int(o1["rechecks"] - o0["rechecks"]), kernel_ms=kt,
+        violations=int(o1["violations"]), wait_timeouts=int(o1["wait_timeouts"]), rechecks=int(o1["rechecks"] - o0["rechecks"]), kernel_ms=kt,
     )
     return g, res
 
@@ -213,10 +213,11 @@ def main():
                 avg_launch_us=round(avg_s * 1e6, 2),
                 launches=launches, algorithmic_bytes_per_launch=int(alg),
                 share_of_step=round(ms / (r64["seconds"] * 1000.0), 3))
+    # every context is closed explicitly before the process ends (none is left to a finaliser)
+    g64.close()
+    gm.close()
     batched = None
     if not args.no_batched:
-        g64.close()
-        gm.close()
         copies = run_batched(W.replicas(3, 8), "mixed", args.batch_equilibrate, args.warmup, args.steps)
         split = run_batched(W.batch_semidilute(8, 32), "mixed", args.batch_equilibrate, args.warmup, args.steps)
         ref = r64["bead_updates_per_s"]
@@ -245,9 +246,14 @@ def main():
                    ratio_vs_fp64=round(rmix["bead_updates_per_s"] / r64["bead_updates_per_s"], 3)),
         batched=batched,
         kernel_ms_fp64={k: [round(v[0], 3), v[1]] for k, v in kt.items()},
-        checks=dict(overflows=r64["overflows"] + rmix["overflows"], violations=r64["violations"]),
+        checks=dict(overflows=r64["overflows"] + rmix["overflows"], violations=r64["violations"],
+                    wait_timeouts=r64["wait_timeouts"] + rmix["wait_timeouts"]),
     )
     print(json.dumps(line))
+    bad = {k: v for k, v in line["checks"].items() if v}
+    if bad:
+        print(f"bench.py: the run is invalid: {bad} (every count must be 0)", file=sys.stderr)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -177,6 +178,10 @@ class WMC:
             self._h = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be gone: leave the context to the
+        # process exit instead of calling into it (close() contexts explicitly before exiting)
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
