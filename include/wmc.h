@@ -134,6 +134,27 @@ int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t n_systems, const int64_
              const int64_t* chain_offset, const double* pos_xyz, int64_t trace_capacity,
              void* device_arena, size_t arena_bytes, void* hip_stream);
 
+/* Size of the library-held device arena that wmc_init_static uses (one per device). */
+#define WMC_STATIC_ARENA_BYTES (16u << 20)
+
+/* wmc_init without a caller-supplied arena, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops or harnesses that forbid hipMalloc). The
+ * context lives in a device array of WMC_STATIC_ARENA_BYTES that the library holds per device
+ * until the process ends; no call allocates device memory (no hipMalloc, hipFree or allocating
+ * library routine). Arguments as wmc_init, on the current device. Errors:
+ *   WMC_EARENA  the problem needs more than WMC_STATIC_ARENA_BYTES (wmc_arena_bytes), or the
+ *               device's array is held by a live context made here (at most one per device;
+ *               wmc_free releases it);
+ *   others      as wmc_init.
+ * wmc_init clears the part of the array the problem uses; the array keeps the last context's
+ * contents otherwise. All such contexts of a process on one device share that device's array:
+ * the guard above admits one at a time, and calls on it that overlap in time (two host threads
+ * sweeping it on different streams) race on the array, as they would on any arena. */
+int wmc_init_static(wmc_ctx** out, const wmc_params* p, int32_t n_systems, const int64_t* sys_bead_offset,
+                    const double* sys_box_L, const double* sys_lambda_max, int64_t n_chains,
+                    const int64_t* chain_offset, const double* pos_xyz, int64_t trace_capacity,
+                    void* hip_stream);
+
 /* Run n_sweeps sweeps, asynchronously on hip_stream. One sweep = every wavelet level band
  * in colour phases, then the plane-wave chains (Sec. IV-V as summarised above). */
 int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* hip_stream);

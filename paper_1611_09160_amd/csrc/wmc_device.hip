@@ -15,6 +15,7 @@
 #include <stdint.h>
 #include <math.h>
 #include <algorithm>
+#include <mutex>
 #include "wmc_internal.h"
 
 namespace wmc {
@@ -2818,6 +2819,34 @@ void launch_rg2(const DevPtrs& D, const int64_t* chain_off, int64_t n_chains, do
     if (n_chains <= 0) return;
     hipLaunchKernelGGL(k_rg2, dim3((unsigned)((n_chains + 255) / 256)), dim3(256), 0, st, D, chain_off, n_chains,
                        out);
+}
+
+// ------------------------------------------------------------ library-held arena
+// Device memory of the contexts made by wmc_init_static, for callers that cannot allocate device
+// memory (code under graph capture, serving loops that forbid allocation). One array per device,
+// held until the process ends. In host code `scratch` names a host-side stand-in, not a device
+// address: only the pointer hipGetSymbolAddress returns (kept per device) is ever passed on.
+static __device__ __align__(256) unsigned char scratch[WMC_STATIC_ARENA_BYTES];
+
+void* static_arena(int device, hipError_t* err) {
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {nullptr};
+    *err = hipSuccess;
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        ptr[device] = p;
+    }
+    return ptr[device];
 }
 
 // ------------------------------------------------------------------- debug kernels

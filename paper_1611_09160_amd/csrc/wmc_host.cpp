@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,7 @@ struct wmc_ctx {
     int64_t t_n[WMC_TIMING_CLASSES] = {0};
     char* arena;
     size_t arena_bytes;
+    int static_dev = -1;  // device whose library-held arena this context uses (wmc_init_static), else -1
     std::string err;
 };
 
@@ -915,6 +917,66 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     return 0;
 }
 
+// devices whose library-held arena a live context occupies
+static std::mutex g_static_mu;
+static bool g_static_busy[kMaxDevices] = {false};
+
+extern "C" int wmc_init_static(wmc_ctx** out, const wmc_params* p, int32_t nsys, const int64_t* so,
+                               const double* sL, const double* sl, int64_t n_chains, const int64_t* co,
+                               const double* pos, int64_t trace_cap, void* stream) {
+    if (!out) return WMC_EINVAL;
+    size_t need = 0;
+    int rc = wmc_arena_bytes(p, nsys, so, sL, sl, n_chains, co, trace_cap, &need);
+    if (rc) {
+        wmc_ctx* c = new wmc_ctx();
+        *out = c;
+        validate(c, p, nsys, so, sL, sl, n_chains, co);
+        if (c->err.empty()) c->err = "invalid problem";
+        return rc;
+    }
+    if (need > (size_t)WMC_STATIC_ARENA_BYTES) {
+        wmc_ctx* c = new wmc_ctx();
+        *out = c;
+        c->err = "problem needs " + std::to_string(need) + " bytes of device arena, more than the " +
+                 std::to_string((size_t)WMC_STATIC_ARENA_BYTES) + " bytes of the library-held arena";
+        return WMC_EARENA;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= kMaxDevices)) e = hipErrorInvalidDevice;
+    if (e != hipSuccess) {
+        wmc_ctx* c = new wmc_ctx();
+        *out = c;
+        c->err = std::string("HIP error: ") + hipGetErrorString(e) + " at hipGetDevice";
+        return WMC_EHIP;
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static_busy[dev]) {
+            wmc_ctx* c = new wmc_ctx();
+            *out = c;
+            c->err = "the library-held arena of this device is in use by another context (wmc_free it first)";
+            return WMC_EARENA;
+        }
+        g_static_busy[dev] = true;
+    }
+    void* base = static_arena(dev, &e);
+    if (!base) {
+        {
+            std::lock_guard<std::mutex> lock(g_static_mu);
+            g_static_busy[dev] = false;
+        }
+        wmc_ctx* c = new wmc_ctx();
+        *out = c;
+        c->err = std::string("HIP error: ") + hipGetErrorString(e) + " at hipGetSymbolAddress";
+        return WMC_EHIP;
+    }
+    rc = wmc_init(out, p, nsys, so, sL, sl, n_chains, co, pos, trace_cap, base, (size_t)WMC_STATIC_ARENA_BYTES,
+                  stream);
+    if (*out) (*out)->static_dev = dev;  // wmc_free releases the arena, also after a failed init
+    return rc;
+}
+
 static hipEvent_t take_event(wmc_ctx* c) {
     if (!c->ev_pool.empty()) {
         hipEvent_t e = c->ev_pool.back();
@@ -1201,5 +1263,9 @@ extern "C" void wmc_free(wmc_ctx* c) {
     if (!c) return;
     drain_events(c);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_busy[c->static_dev] = false;
+    }
     delete c;
 }

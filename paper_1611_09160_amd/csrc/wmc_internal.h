@@ -160,5 +160,9 @@ void launch_rg2(const DevPtrs& D, const int64_t* chain_off, int64_t n_chains, do
 void launch_cell_ids(const DevParams& P, const DevPtrs& D, int sys, int level, int64_t sweep, int64_t n, int32_t* out,
                      hipStream_t st);
 void launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out, hipStream_t st);
+// Device address of the library-held arena on `device` (the current device), looked up once per
+// device; nullptr with *err set when the lookup fails.
+constexpr int kMaxDevices = 64;
+void* static_arena(int device, hipError_t* err);
 
 }  // namespace wmc

@@ -66,6 +66,7 @@ def lib():
         vp, i32, i64, dp, lp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int64)
         L.wmc_arena_bytes.argtypes = [C.POINTER(Params), i32, lp, dp, dp, i64, lp, i64, C.POINTER(C.c_size_t)]
         L.wmc_init.argtypes = [C.POINTER(vp), C.POINTER(Params), i32, lp, dp, dp, i64, lp, dp, i64, vp, C.c_size_t, vp]
+        L.wmc_init_static.argtypes = [C.POINTER(vp), C.POINTER(Params), i32, lp, dp, dp, i64, lp, dp, i64, vp]
         L.wmc_sweep.argtypes = [vp, i64, vp]
         L.wmc_positions.argtypes = [vp, dp, i32, vp]
         L.wmc_set_state.argtypes = [vp, dp, i64, vp]
@@ -82,7 +83,7 @@ def lib():
         L.wmc_last_error.argtypes = [vp]
         L.wmc_last_error.restype = C.c_char_p
         L.wmc_free.argtypes = [vp]
-        for f in ("wmc_arena_bytes", "wmc_init", "wmc_sweep", "wmc_positions", "wmc_set_state", "wmc_observables",
+        for f in ("wmc_arena_bytes", "wmc_init", "wmc_init_static", "wmc_sweep", "wmc_positions", "wmc_set_state", "wmc_observables",
                   "wmc_system_tau", "wmc_chain_rg2", "wmc_trace", "wmc_system_info", "wmc_cell_ids", "wmc_philox",
                   "wmc_set_timing", "wmc_kernel_times"):
             getattr(L, f).restype = C.c_int
@@ -136,7 +137,9 @@ class WMC:
     """A set of systems advanced by libwmc on the current GPU."""
 
     def __init__(self, params: dict, sys_bead_offset, chain_offset, pos, sys_box_L=None, sys_lambda_max=None,
-                 trace_capacity: int = 0, stream=None, device="cuda"):
+                 trace_capacity: int = 0, stream=None, device="cuda", static_arena: bool = False):
+        """static_arena: place the context in the library-held device arena (wmc_init_static)
+        instead of a torch tensor; nothing is allocated on the device then."""
         import torch
 
         L = lib()
@@ -150,6 +153,19 @@ class WMC:
         self.n_chains = len(self.chain_off) - 1
         self.sys_box_L = None if sys_box_L is None else np.ascontiguousarray(sys_box_L, dtype=np.float64)
         self.sys_lambda_max = None if sys_lambda_max is None else np.ascontiguousarray(sys_lambda_max, dtype=np.float64)
+        if static_arena:
+            self.arena = None
+            h = C.c_void_p()
+            rc = L.wmc_init_static(C.byref(h), C.byref(self._p), self.n_systems, _lp(self.sys_off),
+                                   _dp(self.sys_box_L), _dp(self.sys_lambda_max), self.n_chains, _lp(self.chain_off),
+                                   _dp(pos), int(trace_capacity), _stream(stream))
+            self._h = h
+            if rc != 0:
+                msg = L.wmc_last_error(h).decode()
+                L.wmc_free(h)
+                self._h = None
+                raise RuntimeError(f"wmc_init_static failed ({rc}): {msg}")
+            return
         nbytes = C.c_size_t()
         rc = L.wmc_arena_bytes(C.byref(self._p), self.n_systems, _lp(self.sys_off), _dp(self.sys_box_L),
                                _dp(self.sys_lambda_max), self.n_chains, _lp(self.chain_off), int(trace_capacity),
