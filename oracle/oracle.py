@@ -17,6 +17,10 @@ SOURCES = ["wo_tables.c", "wo_sweep.c"]
 
 BOND = {"none": 0, "fene": 1, "harmonic": 2}
 MAX_LEVELS = 16
+K_SHELLS = 16
+ACCEPT = {"metropolis": 0, "glauber": 1}
+WAVELET_MAP = {"linear": 0, "rotation": 1}
+CENTRING = {"anchor": 0, "uniform": 1}
 
 
 def build(force: bool = False) -> str:
@@ -24,7 +28,7 @@ def build(force: bool = False) -> str:
     stale = not os.path.exists(LIB_PATH) or any(
         os.path.getmtime(os.path.join(HERE, f)) > os.path.getmtime(LIB_PATH) for f in SOURCES + ["wmc_oracle.h", "wo_internal.h"])
     if force or stale:
-        cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fPIC", "-shared", "-o", LIB_PATH]
+        cmd = ["gcc", "-O3", "-std=gnu11", "-ffp-contract=off", "-fPIC", "-shared", "-o", LIB_PATH]
         cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
         subprocess.run(cmd, check=True)
     return LIB_PATH
@@ -40,6 +44,7 @@ class Params(C.Structure):
         ("r_int_harmonic", C.c_double),
         ("n_layers", C.c_int32), ("retry_cap", C.c_int32),
         ("seed", C.c_uint64),
+        ("accept_rule", C.c_int32), ("wavelet_map", C.c_int32), ("centring", C.c_int32), ("pad1", C.c_int32),
     ]
 
 
@@ -49,7 +54,8 @@ class Obs(C.Structure):
         for name in ("trials", "hits", "attempts", "accepts", "caps", "redraws", "bead_updates")
     ] + [(name, C.c_int64) for name in (
         "pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates",
-        "violations", "accepted_total", "accepted_bead_updates")]
+        "violations", "accepted_total", "accepted_bead_updates")] + [
+        ("pw_shell_attempts", C.c_int64 * K_SHELLS), ("pw_shell_accepts", C.c_int64 * K_SHELLS)]
 
 
 class TraceRec(C.Structure):
@@ -88,6 +94,12 @@ def lib():
         L.wo_observables.argtypes = [vp, C.POINTER(Obs)]
         L.wo_system_tau.argtypes = [vp, dp]
         L.wo_chain_rg2.argtypes = [vp, dp]
+        L.wo_chain_com.argtypes = [vp, dp]
+        L.wo_inf_table.argtypes = [vp, i32, dp, i32]
+        L.wo_inf_k_of_v.argtypes = [vp, i32, C.c_double]
+        L.wo_inf_k_of_v.restype = C.c_double
+        L.wo_G.argtypes = [C.c_double]
+        L.wo_G.restype = C.c_double
         L.wo_trace.argtypes = [vp, C.POINTER(TraceRec), i64]
         L.wo_trace.restype = i64
         L.wo_get_level_info.argtypes = [vp, i32, C.POINTER(LevelInfo), i32]
@@ -142,6 +154,9 @@ def make_params(d: dict) -> Params:
     p.n_layers = int(d.get("n_layers", 15))
     p.retry_cap = int(d.get("retry_cap", 64))
     p.seed = int(d.get("seed", 1))
+    p.accept_rule = ACCEPT[d.get("accept", "metropolis")]
+    p.wavelet_map = WAVELET_MAP[d.get("wavelet_map", "linear")]
+    p.centring = CENTRING[d.get("centring", "anchor")]
     return p
 
 
@@ -204,6 +219,8 @@ class Oracle:
         for name in ("pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates",
                      "violations", "accepted_total", "accepted_bead_updates"):
             d[name] = getattr(o, name)
+        for name in ("pw_shell_attempts", "pw_shell_accepts"):
+            d[name] = np.array(getattr(o, name)[:], dtype=np.int64)
         return d
 
     def tau(self) -> np.ndarray:
@@ -215,6 +232,21 @@ class Oracle:
         out = np.empty(self.n_chains, dtype=np.float64)
         lib().wo_chain_rg2(self._h, _dptr(out))
         return out
+
+    def chain_com(self) -> np.ndarray:
+        out = np.empty((self.n_chains, 3), dtype=np.float64)
+        lib().wo_chain_com(self._h, _dptr(out))
+        return out
+
+    def inf_table(self, system: int = 0) -> np.ndarray:
+        out = np.empty(8193, dtype=np.float64)
+        n = lib().wo_inf_table(self._h, system, _dptr(out), 8193)
+        if n < 0:
+            raise RuntimeError("no infinite-system plane-wave table")
+        return out[:n].copy()
+
+    def inf_x_of_v(self, v: float, system: int = 0) -> float:
+        return lib().wo_inf_k_of_v(self._h, system, float(v))
 
     def trace(self, max_records: int = 1 << 22) -> np.ndarray:
         buf = (TraceRec * max_records)()
@@ -305,6 +337,10 @@ def stream_doubles(seed, system, sweep, tag, cell, t, r, j, n):
     oc = np.empty(n)
     lib().wo_stream_doubles(int(seed), system, sweep, tag, cell, t, r, j, n, _dptr(co), _dptr(oc))
     return co, oc
+
+
+def G(x: float) -> float:
+    return lib().wo_G(float(x))
 
 
 def draw_lambda(u, lo, hi):

@@ -16,7 +16,21 @@
  *   - plane-wave moves for periodic boxes (Sec. V, App. D "Generating a plane wave"):
  *     amplitude A_F = (2/k) sqrt(dU_est/(mu N)), discrete k-cube plus quasi-continuous
  *     shell, P_F from R, k recycling by permuting and sign-flipping components;
+ *   - plane waves in an infinite system (Sec. V "Distributions of wavevectors", App. D
+ *     "Choosing k for an infinite system"): |k| from P(k) ~ k^2 I(k lambda_max) by a tabulated
+ *     inverse CDF, isotropic k-hat, P_F = (lambda_min/lambda_max)^3 (Eq. "P(Fourier) infinite"),
+ *     |k| kept and k-hat redrawn after a rejection;
  *   - time advanced only on accepted moves (Eqs. "Time step per wavelet", "dt w+F").
+ * Variants the paper names or implies, selected in wo_params:
+ *   - Glauber acceptance 1/(1 + exp(dU/kT)) (Sec. IV "Choosing the wavelet amplitude", last
+ *     paragraph, which anticipates it);
+ *   - the exact-rotation wavelet map: each member rotated about the axis p through b by the
+ *     angle A (1 - |x|) / lambda, which equals x + A w(x) to first order and is an exact
+ *     involution (p -> -p) with unit Jacobian, so "no Jacobian needed" (Sec. IV) holds exactly;
+ *   - uniform centring for homogeneous periodic systems (Sec. IV "Distribution of wavelet
+ *     radii", last paragraph): b uniform in the box, A_w = A0 lambda / sqrt(<n>) with
+ *     <n> = (4 pi/3) lambda^3 N / L^3 (the printed A_w is dimensionally garbled; this is the
+ *     form that keeps P_b A_w^2 of the anchored scheme).
  * The serial paper loop is replayed in the coloured cell schedule of the GPU path
  * (levels of octave bands, cells of side >= 2 lambda_hi + r_int, 8 colours, per-cell
  * trial counts by stochastic rounding, per-cell retry chains), drawing every random
@@ -56,7 +70,16 @@ typedef struct {
     int32_t n_layers;        /* half-width of the discrete k cube (15 in the paper) */
     int32_t retry_cap;       /* max attempts of one recycling chain (64) */
     uint64_t seed;           /* Philox key */
+    int32_t accept_rule;     /* WO_ACCEPT_METROPOLIS (Eq. "Metropolis test") or WO_ACCEPT_GLAUBER */
+    int32_t wavelet_map;     /* WO_MAP_LINEAR (x + A w, as printed) or WO_MAP_ROTATION (exact) */
+    int32_t centring;        /* WO_CENTRE_ANCHOR (Eq. "PDF for b") or WO_CENTRE_UNIFORM (periodic) */
+    int32_t pad1;
 } wo_params;
+
+enum { WO_ACCEPT_METROPOLIS = 0, WO_ACCEPT_GLAUBER = 1 };
+enum { WO_MAP_LINEAR = 0, WO_MAP_ROTATION = 1 };
+enum { WO_CENTRE_ANCHOR = 0, WO_CENTRE_UNIFORM = 1 };
+#define WO_K_SHELLS 16
 
 typedef struct {
     int64_t sweeps;
@@ -71,6 +94,10 @@ typedef struct {
     int64_t violations;                 /* bonds longer than the halo width (harmonic) */
     int64_t accepted_total;             /* wavelet + plane-wave accepted chains */
     int64_t accepted_bead_updates;      /* beads displaced by accepted moves (k = 0: none) */
+    /* plane-wave tests and accepts per |k| shell: periodic floor(|l|) (l the lattice index),
+     * infinite floor(|k| lambda_max), both capped at WO_K_SHELLS - 1 */
+    int64_t pw_shell_attempts[WO_K_SHELLS];
+    int64_t pw_shell_accepts[WO_K_SHELLS];
 } wo_obs;
 
 typedef struct {
@@ -103,12 +130,18 @@ int wo_set_sweep(void* ctx, int64_t sweep);
 int wo_observables(void* ctx, wo_obs* out);
 int wo_system_tau(void* ctx, double* out);
 int wo_chain_rg2(void* ctx, double* out);
+int wo_chain_com(void* ctx, double* out);  /* [n_chains][3] centre of mass, unwrapped positions */
 int64_t wo_trace(void* ctx, wo_trace_rec* out, int64_t max);
 int wo_get_level_info(void* ctx, int32_t system, wo_level_info* out, int32_t max);
 int wo_get_system_info(void* ctx, int32_t system, wo_system_info* out);
 int wo_cell_ids(void* ctx, int32_t system, int64_t sweep, int32_t level, int32_t* out);
 int wo_cube_weights(void* ctx, int32_t system, double* out);
 int wo_shell_table(void* ctx, int32_t system, double* out, int32_t max);
+/* infinite system: s(t) = x v at t = i/M, v = 1 - t^3 the tail probability G(x)/G(0) */
+int wo_inf_table(void* ctx, int32_t system, double* out, int32_t max);
+/* |k| lambda_max of an infinite-system plane wave from its tail probability v in (0, 1] */
+double wo_inf_k_of_v(void* ctx, int32_t system, double v);
+double wo_G(double x);
 const char* wo_last_error(void* ctx);
 void wo_free(void* ctx);
 

@@ -33,6 +33,8 @@ typedef struct {
     double* shell_s;    /* [n_shell + 1] s = x_s/x at u = i/n_shell */
     int32_t n_shell;
     double x_s;
+    double* inf_s;      /* infinite system: [n_inf + 1] s = x v at t = i/n_inf, v = 1 - t^3 */
+    int32_t n_inf;
     int64_t accepted;
     /* linked-cell list for pair search (the cell index method), periodic systems only */
     int32_t nc;          /* cells per axis, 0 = no list (scan every bead) */

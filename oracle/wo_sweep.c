@@ -4,7 +4,8 @@
  * One sweep of one system, in order:
  *  for each level band (ascending lambda):
  *    grid shift u from stream (tag 32+l); periodic grid of side h = L/n, or for an
- *    infinite system a grid over the bounding box of the positions;
+ *    infinite system the cells of the lattice h (k + u) that cover the bounding box of the
+ *    positions (colour = parity of k, stream key = k mod 256 per axis);
  *    for colour 0..7, for each cell of that colour in ascending id:
  *      S_c = particles within hi of the cell, H_c = within hi + r_int (ascending id);
  *      K_c = stochastic rounding of T_l |S_c| / N (stream tag 16+l);
@@ -18,11 +19,14 @@
  *        (Eq. "Metropolis test"); after a rejection the same lambda is reused with a
  *        new anchor, b (redrawn until it lies in the cell) and p (App. D recycling),
  *        up to retry_cap attempts.
- *  plane waves (periodic): H_F = stochastic rounding of N P_F chains; k from the cube
- *  or the quasi-continuous shell (App. D), phase Phi and e-hat perpendicular to k,
+ *  plane waves: H_F = stochastic rounding of N P_F chains; periodic k from the cube or the
+ *  quasi-continuous shell (App. D), infinite |k| from its tabulated inverse CDF and k-hat
+ *  isotropic (App. D); phase Phi and e-hat perpendicular to k,
  *  displacement A_F cos(k.r + Phi) e-hat on every particle (Eq. "Oseen as <FF>"),
  *  A_F = 2 A0 / (k sqrt(5 N)) (Eq. "Fourier strain energy" with dU_est/mu = A0^2 M6/(2pi)^3),
- *  k = 0 accepted without displacement; a rejection permutes and sign-flips k.
+ *  k = 0 accepted without displacement; a rejection permutes and sign-flips k (periodic) or
+ *  redraws k-hat (infinite).
+ *  Variants (wmc_oracle.h): Glauber acceptance, the exact-rotation map, uniform centring.
  *  time advances by dt per accepted chain (App. D, last paragraph).
  */
 #include <math.h>
@@ -73,6 +77,15 @@ static double u_pair(const wo_ctx* c, double r2) {
     return 4.0 * c->p.eps * (s6 * s6 - s6 + 0.25);
 }
 
+/* Acceptance threshold on dU for a uniform u in (0, 1]: Metropolis (Eq. "Metropolis test")
+ * accepts with probability min(1, exp(-dU/kT)), i.e. iff dU <= -kT ln u; Glauber accepts
+ * with probability 1/(1 + exp(dU/kT)), i.e. iff dU <= kT ln((1 - u)/u). (1 - u is exact for
+ * u = m 2^-53.) */
+static double threshold(const wo_ctx* c, double u) {
+    if (c->p.accept_rule == WO_ACCEPT_GLAUBER) return c->p.kT * (log(1.0 - u) - log(u));
+    return -c->p.kT * log(u);
+}
+
 /* ------------------------------------------------------------------ geometry ------ */
 typedef struct {
     int periodic;
@@ -80,6 +93,7 @@ typedef struct {
     double o[3];
     double h, invh, half;
     int64_t n[3];
+    int64_t k0[3];   /* infinite system: lattice index of local cell 0 along each axis */
     double hi, rh;
 } grid_t;
 
@@ -118,6 +132,7 @@ static void make_grid(wo_ctx* c, wo_system* s, int sysid, int level, grid_t* g) 
         for (int a = 0; a < 3; ++a) {
             g->o[a] = lv->h * u[a];
             g->n[a] = lv->ncell;
+            g->k0[a] = 0;
         }
     } else {
         g->L = 0.0;
@@ -130,11 +145,29 @@ static void make_grid(wo_ctx* c, wo_system* s, int sysid, int level, grid_t* g) 
                 if (v[a] > mx[a]) mx[a] = v[a];
             }
         }
+        /* cells of the fixed lattice h (k + u), k integer, that cover the bounding box grown by
+         * hi: the lattice, the colour of a cell (parity of k) and its stream key do not depend
+         * on the positions, so the sweep is the same mixture of moves from every state */
         for (int a = 0; a < 3; ++a) {
-            g->o[a] = mn[a] - lv->hi - lv->h * u[a];
-            g->n[a] = (int64_t)floor((mx[a] + lv->hi - g->o[a]) * g->invh) + 1;
+            int64_t kmin = (int64_t)floor((mn[a] - lv->hi) * g->invh - u[a]);
+            int64_t kmax = (int64_t)floor((mx[a] + lv->hi) * g->invh - u[a]);
+            g->k0[a] = kmin;
+            g->o[a] = ((double)kmin + u[a]) * lv->h;
+            g->n[a] = kmax - kmin + 1;
         }
     }
+}
+
+/* colour of a cell: parity of its lattice index along each axis */
+static int cell_colour(const grid_t* g, const int64_t ic[3]) {
+    return (int)(((g->k0[0] + ic[0]) & 1) | (((g->k0[1] + ic[1]) & 1) << 1) | (((g->k0[2] + ic[2]) & 1) << 2));
+}
+
+/* stream key of a cell: its index (periodic), or its lattice index modulo 256 per axis
+ * (infinite system; distinct for systems spanning fewer than 256 cells per axis) */
+static int64_t cell_key(const grid_t* g, const int64_t ic[3]) {
+    if (g->periodic) return ic[0] + g->n[0] * (ic[1] + g->n[1] * ic[2]);
+    return ((g->k0[0] + ic[0]) & 255) | (((g->k0[1] + ic[1]) & 255) << 8) | (((g->k0[2] + ic[2]) & 255) << 16);
 }
 
 static int64_t cell_of_point(const grid_t* g, double bx, double by, double bz) {
@@ -256,6 +289,13 @@ static int draw_centre(wo_ctx* c, wo_stream* st, const grid_t* g, int64_t cell, 
     return cell_of_point(g, b[0], b[1], b[2]) == cell;
 }
 
+/* uniform centring: b uniform in the cell (homogeneous variant, Sec. IV "Distribution of
+ * wavelet radii"); returns whether b rounds into the cell */
+static int draw_uniform_centre(wo_stream* st, const grid_t* g, int64_t cell, const int64_t ic[3], double b[3]) {
+    for (int a = 0; a < 3; ++a) b[a] = g->o[a] + ((double)ic[a] + wo_next_co(st)) * g->h;
+    return cell_of_point(g, b[0], b[1], b[2]) == cell;
+}
+
 static void draw_direction(wo_stream* st, double p[3]) {
     double vx, vy, vz, ss;
     do {
@@ -284,7 +324,7 @@ static void pair_nonmember(wo_ctx* c, wo_system* s, int64_t m, void* vp) {
 }
 
 /* one Metropolis test of a wavelet move; returns 1 if accepted (positions updated) */
-static int wavelet_attempt(wo_ctx* c, wo_system* s, int sysid, int level, int64_t cell,
+static int wavelet_attempt(wo_ctx* c, wo_system* s, int sysid, int level, int64_t key,
                            int64_t t, int r, int64_t nS, double lam, int64_t anchor,
                            const double b[3], const double p[3], double u_acc) {
     double L = s->L, invL = c->p.periodic ? 1.0 / s->L : 0.0;
@@ -310,15 +350,33 @@ static int wavelet_attempt(wo_ctx* c, wo_system* s, int sysid, int level, int64_
             ++n;
         }
     }
-    double A = c->p.A0 * lam / sqrt((double)n);
+    /* amplitude: Eq. "Wavelet amplitude" with the local count n; uniform centring uses the mean
+     * count <n> = (4 pi/3) lambda^3 N / L^3 of the homogeneous system instead */
+    double A;
+    if (c->p.centring == WO_CENTRE_UNIFORM)
+        A = c->p.A0 * lam / sqrt((4.0 * WO_PI / 3.0) * lam * lam * lam * (double)s->N / (L * L * L));
+    else
+        A = c->p.A0 * lam / sqrt((double)n);
     for (int64_t q = 0; q < n; ++q) {
         int64_t j = c->M[q];
         double xr[3] = {c->nx[j], c->ny[j], c->nz[j]}, w[3];
         double rr = sqrt((xr[0] * xr[0] + xr[1] * xr[1]) + xr[2] * xr[2]);
-        double f = rr < 1.0 ? A * (1.0 - rr) : 0.0;
-        w[0] = f * (p[1] * xr[2] - p[2] * xr[1]);
-        w[1] = f * (p[2] * xr[0] - p[0] * xr[2]);
-        w[2] = f * (p[0] * xr[1] - p[1] * xr[0]);
+        if (c->p.wavelet_map == WO_MAP_ROTATION) {
+            /* rotation of x about the axis p through b by the angle a = (A/lambda)(1 - |x|),
+             * Rodrigues' formula: x' - x = sin a (p x x) + (1 - cos a)(p (p.x) - x), with
+             * 1 - cos a = 2 sin^2(a/2); to first order in a it is A (1 - |x|) p x x */
+            double a = rr < 1.0 ? (A / lam) * (1.0 - rr) : 0.0;
+            double sa = sin(a), hs = sin(0.5 * a), omc = 2.0 * hs * hs;
+            double pd = (p[0] * xr[0] + p[1] * xr[1]) + p[2] * xr[2];
+            w[0] = lam * (sa * (p[1] * xr[2] - p[2] * xr[1]) + omc * (p[0] * pd - xr[0]));
+            w[1] = lam * (sa * (p[2] * xr[0] - p[0] * xr[2]) + omc * (p[1] * pd - xr[1]));
+            w[2] = lam * (sa * (p[0] * xr[1] - p[1] * xr[0]) + omc * (p[2] * pd - xr[2]));
+        } else {
+            double f = rr < 1.0 ? A * (1.0 - rr) : 0.0;
+            w[0] = f * (p[1] * xr[2] - p[2] * xr[1]);
+            w[1] = f * (p[2] * xr[0] - p[0] * xr[2]);
+            w[2] = f * (p[0] * xr[1] - p[1] * xr[0]);
+        }
         c->nx[j] = c->x[j] + w[0];
         c->ny[j] = c->y[j] + w[1];
         c->nz[j] = c->z[j] + w[2];
@@ -360,11 +418,11 @@ static int wavelet_attempt(wo_ctx* c, wo_system* s, int sysid, int level, int64_
             }
         }
     }
-    double thr = -c->p.kT * log(u_acc);
+    double thr = threshold(c, u_acc);
     int acc = dU <= thr;
     c->obs.attempts[level]++;
     c->obs.bead_updates[level] += n;
-    trace_push(c, 0, sysid, level, cell, t, r, n, acc, (int)anchor, dU, thr);
+    trace_push(c, 0, sysid, level, key, t, r, n, acc, (int)anchor, dU, thr);
     if (acc) {
         for (int64_t q = 0; q < n; ++q) {
             int64_t j = c->M[q];
@@ -386,29 +444,34 @@ static void process_cell(wo_ctx* c, wo_system* s, int sysid, int level, const gr
     double hi2 = g->hi * g->hi;
     for (int64_t j = s->b0; j < s->b1; ++j)
         if (dist2_cell(g, ic, c->x[j], c->y[j], c->z[j]) <= hi2) c->S[nS++] = j;
-    /* number of trials: stochastic rounding of T_l |S_c| / N */
-    double mu = (lv->T * (double)nS) / (double)s->N;
+    /* number of trials: stochastic rounding of T_l |S_c| / N (anchored centres), or of T_l times
+     * the cell's share of the box volume, T_l / n^3 (uniform centres) */
+    const int uni = c->p.centring == WO_CENTRE_UNIFORM;
+    double mu = uni ? lv->T / ((double)g->n[0] * (double)g->n[1] * (double)g->n[2])
+                    : (lv->T * (double)nS) / (double)s->N;
     int64_t K = (int64_t)floor(mu);
     wo_stream ms;
-    wo_stream_init(&ms, c->p.seed, sysid, c->sweep, TAG_META + level, cell, 0, 0, 0);
+    const int64_t key = cell_key(g, ic);
+    wo_stream_init(&ms, c->p.seed, sysid, c->sweep, TAG_META + level, key, 0, 0, 0);
     if (wo_next_co(&ms) < mu - (double)K) K += 1;
     if (K > 0xFFFFF) { K = 0xFFFFF; c->obs.violations++; }
     int64_t hits = 0;
     for (int64_t t = 0; t < K; ++t) {
         wo_stream st;
-        wo_stream_init(&st, c->p.seed, sysid, c->sweep, level, cell, t, 0, 0);
+        wo_stream_init(&st, c->p.seed, sysid, c->sweep, level, key, t, 0, 0);
         double lam = wo_draw_lambda(wo_next_co(&st), lv->lo, lv->hi);
-        int64_t anchor;
+        int64_t anchor = -1;
         double b[3];
         c->obs.trials[level]++;
-        if (!draw_centre(c, &st, g, cell, nS, lam, &anchor, b)) continue;
+        if (uni ? !draw_uniform_centre(&st, g, cell, ic, b) : !draw_centre(c, &st, g, cell, nS, lam, &anchor, b))
+            continue;
         c->obs.hits[level]++;
         ++hits;
         for (int r = 0;;) {
             double p[3];
             draw_direction(&st, p);
             double u_acc = wo_next_oc(&st);
-            if (wavelet_attempt(c, s, sysid, level, cell, t, r, nS, lam, anchor, b, p, u_acc)) {
+            if (wavelet_attempt(c, s, sysid, level, key, t, r, nS, lam, anchor, b, p, u_acc)) {
                 s->accepted++;
                 c->obs.accepted_total++;
                 break;
@@ -416,14 +479,17 @@ static void process_cell(wo_ctx* c, wo_system* s, int sysid, int level, const gr
             if (++r >= c->p.retry_cap) { c->obs.caps[level]++; break; }
             int found = 0;
             for (int j = 0; j < 4096; ++j) {
-                wo_stream_init(&st, c->p.seed, sysid, c->sweep, level, cell, t, r, j);
-                if (draw_centre(c, &st, g, cell, nS, lam, &anchor, b)) { found = 1; break; }
+                wo_stream_init(&st, c->p.seed, sysid, c->sweep, level, key, t, r, j);
+                if (uni ? draw_uniform_centre(&st, g, cell, ic, b) : draw_centre(c, &st, g, cell, nS, lam, &anchor, b)) {
+                    found = 1;
+                    break;
+                }
                 c->obs.redraws[level]++;
             }
             if (!found) { c->obs.caps[level]++; break; }
         }
     }
-    trace_push(c, 1, sysid, level, cell, K, (int)nS, 0, (int)hits, 0, 0.0, 0.0);
+    trace_push(c, 1, sysid, level, key, K, (int)nS, 0, (int)hits, 0, 0.0, 0.0);
 }
 
 /* ------------------------------------------------------------- plane waves -------- */
@@ -485,10 +551,10 @@ static void pw_pair(wo_ctx* c, wo_system* s, int64_t m, void* vp) {
     if (r2o < c->rc2 || r2n < c->rc2) a->acc += u_pair(c, r2n) - u_pair(c, r2o);
 }
 
-static int pw_attempt(wo_ctx* c, wo_system* s, int sysid, int64_t h, int r, const int l[3],
-                      double Phi, double psi, double u_acc) {
-    double ks = 2.0 * WO_PI / s->L;
-    double k[3] = {ks * (double)l[0], ks * (double)l[1], ks * (double)l[2]};
+/* one Metropolis test of the plane wave of wavevector k (nonzero); shell is its |k| shell and
+ * extra its trace tag */
+static int pw_attempt(wo_ctx* c, wo_system* s, int sysid, int64_t h, int r, const double k[3], int shell,
+                      int extra, double Phi, double psi, double u_acc) {
     double kmag = sqrt((k[0] * k[0] + k[1] * k[1]) + k[2] * k[2]);
     double kh[3] = {k[0] / kmag, k[1] / kmag, k[2] / kmag};
     int ax = 0;
@@ -531,12 +597,12 @@ static int pw_attempt(wo_ctx* c, wo_system* s, int sysid, int64_t h, int r, cons
             dU += pa.acc;
         }
     }
-    double thr = -c->p.kT * log(u_acc);
+    double thr = threshold(c, u_acc);
     int acc = dU <= thr;
-    int extra = (int)((((uint32_t)(l[0] + 512) & 0x3FFu) << 20) | (((uint32_t)(l[1] + 512) & 0x3FFu) << 10) |
-                      ((uint32_t)(l[2] + 512) & 0x3FFu));
     c->obs.pw_attempts++;
     c->obs.pw_bead_updates += s->N;
+    c->obs.pw_shell_attempts[shell]++;
+    if (acc) c->obs.pw_shell_accepts[shell]++;
     trace_push(c, 2, sysid, -1, h, 0, r, s->N, acc, extra, dU, thr);
     if (acc) {
         c->obs.accepted_bead_updates += s->N;
@@ -551,7 +617,19 @@ static int pw_attempt(wo_ctx* c, wo_system* s, int sysid, int64_t h, int r, cons
     return acc;
 }
 
+/* x = |k| lambda_max of an infinite-system plane wave from its tail probability v in (0, 1]
+ * (App. D "Choosing k for an infinite system": the tabulated inverse, interpolated) */
+static double inf_x_of_v(const wo_system* s, double v) {
+    double t = cbrt(1.0 - v), u = t * (double)s->n_inf;
+    int64_t i = (int64_t)floor(u);
+    if (i >= s->n_inf) i = s->n_inf - 1;
+    double fr = u - (double)i;
+    double sv = s->inf_s[i] + fr * (s->inf_s[i + 1] - s->inf_s[i]);
+    return sv / v;
+}
+
 static void plane_waves(wo_ctx* c, wo_system* s, int sysid) {
+    const int per = c->p.periodic;
     wo_stream cs;
     wo_stream_init(&cs, c->p.seed, sysid, c->sweep, TAG_PWCOUNT, 0, 0, 0, 0);
     double mu = (double)s->N * s->info.P_F;
@@ -561,31 +639,62 @@ static void plane_waves(wo_ctx* c, wo_system* s, int sysid) {
         c->obs.pw_chains++;
         wo_stream st;
         wo_stream_init(&st, c->p.seed, sysid, c->sweep, TAG_PW, 0, h, 0, 0);
-        int l[3];
-        sample_k(c, s, &st, l);
+        /* periodic: a lattice mode l (App. D "Choosing k for a periodic system");
+         * infinite: |k| lambda_max = x from its tail probability, direction isotropic */
+        int l[3] = {0, 0, 0};
+        double x = 0.0, kh[3] = {0.0, 0.0, 0.0};
+        if (per) {
+            sample_k(c, s, &st, l);
+        } else {
+            x = inf_x_of_v(s, wo_next_oc(&st));
+            draw_direction(&st, kh);
+        }
         for (int r = 0;;) {
             double Phi = 2.0 * WO_PI * wo_next_co(&st);
             double psi = 2.0 * WO_PI * wo_next_co(&st);
             double u_acc = wo_next_oc(&st);
-            if (l[0] == 0 && l[1] == 0 && l[2] == 0) {
+            int zero = per ? (l[0] == 0 && l[1] == 0 && l[2] == 0) : x == 0.0;
+            if (zero) {
+                /* k = 0: no displacement, deemed accepted (Sec. V "Choosing plane wave amplitude") */
                 c->obs.pw_k0++;
                 c->obs.pw_accepts++;
                 s->accepted++;
                 c->obs.accepted_total++;
-                trace_push(c, 2, sysid, -1, h, 0, r, 0, 1, (512 << 20) | (512 << 10) | 512, 0.0,
-                           -c->p.kT * log(u_acc));
+                trace_push(c, 2, sysid, -1, h, 0, r, 0, 1, per ? (512 << 20) | (512 << 10) | 512 : 0, 0.0,
+                           threshold(c, u_acc));
                 break;
             }
-            if (pw_attempt(c, s, sysid, h, r, l, Phi, psi, u_acc)) {
+            double k[3];
+            int shell, extra;
+            if (per) {
+                double ks = 2.0 * WO_PI / s->L;
+                for (int a = 0; a < 3; ++a) k[a] = ks * (double)l[a];
+                double lm = sqrt((double)(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]));
+                shell = lm < WO_K_SHELLS - 1 ? (int)lm : WO_K_SHELLS - 1;
+                extra = (int)((((uint32_t)(l[0] + 512) & 0x3FFu) << 20) | (((uint32_t)(l[1] + 512) & 0x3FFu) << 10) |
+                              ((uint32_t)(l[2] + 512) & 0x3FFu));
+            } else {
+                double km = x / s->lmax;
+                for (int a = 0; a < 3; ++a) k[a] = km * kh[a];
+                shell = x < WO_K_SHELLS - 1 ? (int)x : WO_K_SHELLS - 1;
+                extra = shell;
+            }
+            if (pw_attempt(c, s, sysid, h, r, k, shell, extra, Phi, psi, u_acc)) {
                 s->accepted++;
                 c->obs.accepted_total++;
                 break;
             }
             if (++r >= c->p.retry_cap) { c->obs.pw_caps++; break; }
+            /* recycling (App. D): keep |k|; periodic permutes and sign-flips l, infinite redraws
+             * the direction; Phi and e-hat are redrawn either way */
             wo_stream_init(&st, c->p.seed, sysid, c->sweep, TAG_PW, 0, h, r, 0);
-            int pi = (int)wo_next_index(&st, 6);
-            int nl[3] = {l[PERM[pi][0]], l[PERM[pi][1]], l[PERM[pi][2]]};
-            for (int a = 0; a < 3; ++a) l[a] = wo_next_co(&st) < 0.5 ? -nl[a] : nl[a];
+            if (per) {
+                int pi = (int)wo_next_index(&st, 6);
+                int nl[3] = {l[PERM[pi][0]], l[PERM[pi][1]], l[PERM[pi][2]]};
+                for (int a = 0; a < 3; ++a) l[a] = wo_next_co(&st) < 0.5 ? -nl[a] : nl[a];
+            } else {
+                draw_direction(&st, kh);
+            }
         }
     }
 }
@@ -600,13 +709,12 @@ static void sweep_system(wo_ctx* c, int sysid) {
         for (int colour = 0; colour < 8; ++colour) {
             for (int64_t cell = 0; cell < ncell; ++cell) {
                 int64_t ic[3] = {cell % g.n[0], (cell / g.n[0]) % g.n[1], cell / (g.n[0] * g.n[1])};
-                int col = (int)((ic[0] & 1) | ((ic[1] & 1) << 1) | ((ic[2] & 1) << 2));
-                if (col != colour) continue;
+                if (cell_colour(&g, ic) != colour) continue;
                 process_cell(c, s, sysid, level, &g, cell, ic);
             }
         }
     }
-    if (c->p.periodic && c->p.plane_waves) plane_waves(c, s, sysid);
+    if (c->p.plane_waves) plane_waves(c, s, sysid);
 }
 
 int wo_sweep(void* vctx, int64_t n_sweeps) {
@@ -666,6 +774,9 @@ int wo_init(void** out, const wo_params* p, int32_t n_systems, const int64_t* sy
     *out = c;
     if (!(p->band_ratio > 1.0 && p->band_ratio <= 2.0)) { strcpy(c->err, "band_ratio must lie in (1, 2]"); return -2; }
     if (!(p->lambda_min > 0.0)) { strcpy(c->err, "lambda_min must be positive"); return -2; }
+    if (p->accept_rule < 0 || p->accept_rule > 1 || p->wavelet_map < 0 || p->wavelet_map > 1 ||
+        p->centring < 0 || p->centring > 1) { strcpy(c->err, "bad variant selector"); return -2; }
+    if (p->centring == WO_CENTRE_UNIFORM && !p->periodic) { strcpy(c->err, "uniform centring needs a periodic box"); return -2; }
     for (int si = 0; si < n_systems; ++si) {
         wo_system* s = &c->sys[si];
         s->b0 = sys_bead_offset[si];
@@ -676,9 +787,10 @@ int wo_init(void** out, const wo_params* p, int32_t n_systems, const int64_t* sy
         if (!(s->lmax > p->lambda_min)) { strcpy(c->err, "lambda_max must exceed lambda_min"); return -2; }
         if (p->periodic && s->lmax > 0.5 * s->L) { strcpy(c->err, "lambda_max must not exceed L/2"); return -2; }
         /* systems with the same L/lambda_max share their plane-wave tables */
+        /* periodic tables depend on L/lambda_max only; the infinite-system table on nothing */
         const wo_system* donor = NULL;
-        for (int sj = 0; sj < si && p->periodic && p->plane_waves; ++sj)
-            if (c->sys[sj].L / c->sys[sj].lmax == s->L / s->lmax) { donor = &c->sys[sj]; break; }
+        for (int sj = 0; sj < si && p->plane_waves; ++sj)
+            if (!p->periodic || c->sys[sj].L / c->sys[sj].lmax == s->L / s->lmax) { donor = &c->sys[sj]; break; }
         int rc_ = wo_build_system_tables(c, s, donor);
         if (rc_) return rc_;
         /* linked cells: side >= r_cut + 2 x the largest plane-wave amplitude (k = 2 pi / L) */
@@ -759,6 +871,37 @@ int wo_chain_rg2(void* vctx, double* out) {
         out[ch] = acc / (2.0 * nb * nb);
     }
     return 0;
+}
+
+int wo_chain_com(void* vctx, double* out) {
+    wo_ctx* c = (wo_ctx*)vctx;
+    for (int64_t ch = 0; ch < c->n_chains; ++ch) {
+        int64_t a = c->chain_off[ch], b = c->chain_off[ch + 1];
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int64_t i = a; i < b; ++i) {
+            sx += c->x[i];
+            sy += c->y[i];
+            sz += c->z[i];
+        }
+        double nb = (double)(b - a);
+        out[3 * ch] = sx / nb;
+        out[3 * ch + 1] = sy / nb;
+        out[3 * ch + 2] = sz / nb;
+    }
+    return 0;
+}
+
+int wo_inf_table(void* vctx, int32_t system, double* out, int32_t max) {
+    wo_system* s = &((wo_ctx*)vctx)->sys[system];
+    if (!s->inf_s) return -1;
+    int n = s->n_inf + 1 < max ? s->n_inf + 1 : max;
+    memcpy(out, s->inf_s, sizeof(double) * n);
+    return s->n_inf + 1;
+}
+
+double wo_inf_k_of_v(void* vctx, int32_t system, double v) {
+    wo_system* s = &((wo_ctx*)vctx)->sys[system];
+    return s->inf_s ? inf_x_of_v(s, v) : NAN;
 }
 
 int64_t wo_trace(void* vctx, wo_trace_rec* out, int64_t max) {

@@ -238,7 +238,7 @@ double wo_J6(double x) {
 }
 
 /* G(x) = int_x^inf t^2 I(t) dt = (J6(x) - x^3 I(x)) / 3 (integration by parts) */
-static double wo_G(double x) {
+double wo_G(double x) {
     quad_tables();
     double I, J;
     if (x >= WO_QMAX) {
@@ -280,6 +280,7 @@ double wo_u_wca(double r2, double sigma, double eps) {
  *          W_tot = sum over the cube of I(|k_l| lmax) + quasi-continuous shell outside the
  *          cube (continuum integral beyond k_s = (2pi/L)(N_layers + 1/2) minus the cube's
  *          corner modes beyond k_s).
+ *          Infinite system: P_F = (lambda_min/lambda_max)^3 (Eq. "P(Fourier) infinite").
  *  dt:     Eq. "dt w+F" with plane waves; Eq. "Time step per wavelet" without.
  * ---------------------------------------------------------------------------------- */
 int wo_build_system_tables(wo_ctx* c, wo_system* s, const wo_system* donor) {
@@ -366,11 +367,51 @@ int wo_build_system_tables(wo_ctx* c, wo_system* s, const wo_system* donor) {
             s->shell_s[k] = 0.5 * (a + b);
         }
     }
+    s->inf_s = NULL;
+    s->n_inf = 0;
+    if (!p->periodic && p->plane_waves && donor) {
+        double q = lmin / lmax;
+        PF = q * q * q;
+        s->n_inf = donor->n_inf;
+        s->inf_s = (double*)malloc(sizeof(double) * (s->n_inf + 1));
+        memcpy(s->inf_s, donor->inf_s, sizeof(double) * (s->n_inf + 1));
+        info->N_k = 3.0 * lmax * lmax * lmax / M6;
+        info->R = 1.0;
+    } else if (!p->periodic && p->plane_waves) {
+        /* Infinite system (Sec. V "Distributions of wavevectors"): P(k) = N_k k^2 I(k lmax) with
+         * N_k = 3 lmax^3 / M6 (Eq. "k normalisation infinite"), so x = k lmax has the tail
+         * probability v(x) = G(x) / G(0), G(0) = M6 / 3. The inverse (App. D: a table of
+         * pre-calculated values, interpolated) is kept as s = x v at t = i/M with v = 1 - t^3:
+         * s is smooth in t at both ends (x grows like t from 0, and x v -> 2 pi^2 / G(0) as
+         * v -> 0 because I(x) ~ 2 pi^2 x^-4). A plane wave is made with the probability of a
+         * wavelet above lmax, P_F = (lmin/lmax)^3 (Eq. "P(Fourier) infinite"). */
+        double q = lmin / lmax;
+        PF = q * q * q;
+        int M = 4096;
+        s->n_inf = M;
+        s->inf_s = (double*)malloc(sizeof(double) * (M + 1));
+        double G0 = wo_G(0.0), xprev = 0.0;
+        s->inf_s[0] = 0.0;
+        for (int i = 1; i < M; ++i) {
+            double t = (double)i / M, v = 1.0 - t * t * t, target = v * G0;
+            double a = xprev, b = xprev + 1.0;
+            while (wo_G(b) > target) b *= 2.0;
+            for (int it = 0; it < 80; ++it) {
+                double m = 0.5 * (a + b);
+                if (wo_G(m) > target) a = m; else b = m;
+            }
+            xprev = 0.5 * (a + b);
+            s->inf_s[i] = xprev * v;
+        }
+        s->inf_s[M] = 2.0 * WO_PI * WO_PI / G0;
+        info->N_k = 3.0 * lmax * lmax * lmax / M6;
+        info->R = 1.0;
+    }
     info->P_F = PF;
 
     /* time step per accepted move */
     double dt = 6.0 * p->A0 * p->A0 * M4 * lam_a * lam_a / (twopi3 * N);
-    if (!(p->periodic && p->plane_waves)) {
+    if (!p->plane_waves) {
         double q = lmin / lmax;
         dt *= (1.0 - q) / (1.0 - q * q * q);
     }
@@ -418,5 +459,6 @@ void wo_free_system_tables(wo_system* s) {
     free(s->cube_w);
     free(s->cube_cdf);
     free(s->shell_s);
-    s->cube_w = s->cube_cdf = s->shell_s = NULL;
+    free(s->inf_s);
+    s->cube_w = s->cube_cdf = s->shell_s = s->inf_s = NULL;
 }

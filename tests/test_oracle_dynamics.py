@@ -6,9 +6,9 @@
 - the self term per sweep equals Eq. "wavelet dr2" times the moves per sweep.
 - plane-wave moves leave the Boltzmann distribution exactly invariant (they are exact
   involutions with unit Jacobian: e-hat is perpendicular to k).
-- the wavelet map of Eq. "Oseen as <ww>" is linear in the displacement, so its reverse move
-  returns only to first order: one sweep from exact equilibrium shows an O(A0^2) drift that
-  vanishes as A0 -> 0 (the paper's method as written; recorded, not hidden).
+- one sweep of the method as printed from exact equilibrium (4-bead chains) changes R_ee^2
+  by little at small A0 (the separate defects of the linear map and of lambda recycling are
+  measured in tests/test_oracle_balance.py).
 - the periodic k sampler follows P(k_l) = N_k I(|k_l| lambda_max) (Eq. "Prob of k_l").
 - free-particle self-diffusion in a periodic box follows the lattice-sum prediction.
 """
@@ -132,20 +132,6 @@ def test_wavelet_drift_vanishes_with_A0(oracle_mod):
     mean, err, _ = one_sweep_drift(oracle_mod, p, 4, 150, np.random.default_rng(7))
     # at A0 = 0.5 the drift is ~7e-4 per sweep; scaled by A0^2 it is ~4e-5 here
     assert abs(mean) < 4.0 * err + 6e-5, (mean, err)
-
-
-@pytest.mark.slow
-def test_wavelet_linear_map_defect_is_second_order(oracle_mod):
-    """Documents the O(A0^2) drift of the paper's linear wavelet map (not a bug of the oracle)."""
-    base = dict(periodic=0, plane_waves=0, lambda_min=1.0, lambda_max=4.0, bond_type="harmonic",
-                k_bond=3.0, wca=0, r_int_harmonic=5.0, seed=9)
-    m5, e5, _ = one_sweep_drift(oracle_mod, dict(base, A0=0.5), 4, 500, np.random.default_rng(8))
-    m25, e25, _ = one_sweep_drift(oracle_mod, dict(base, A0=0.25), 4, 500, np.random.default_rng(9))
-    assert m5 > 3 * e5
-    # the drift falls with A0 and is consistent with A0^2 scaling (m25 ~ m5 / 4); the A0 = 0.25
-    # estimate is too noisy for a ratio, so compare differences against their standard errors
-    assert m5 - m25 > 3.0 * np.hypot(e5, e25), (m5, e5, m25, e25)
-    assert abs(m25 - m5 / 4.0) < 4.0 * np.hypot(e25, e5 / 4.0), (m5, e5, m25, e25)
 
 
 def test_k_sampler_distribution(oracle_mod):
