@@ -56,11 +56,27 @@ enum {
     WMC_ESTATE = -2,     /* initial state has infinite energy (overstretched bond, overlap) */
     WMC_EARENA = -3,     /* device arena missing or too small */
     WMC_EHIP = -4,       /* a HIP runtime call failed */
-    WMC_ECAPACITY = -5   /* a per-cell list overflowed its capacity during a sweep */
+    WMC_ECAPACITY = -5,  /* a per-cell list overflowed its capacity during a sweep (the cell's
+                            remaining moves were skipped; the sweep is not a valid sample) */
+    WMC_ESCHEDULE = -6   /* a dependency wait between cells hit its bound (the cell was skipped;
+                            the sweep is not a valid sample) */
 };
 
 enum { WMC_BOND_NONE = 0, WMC_BOND_FENE = 1, WMC_BOND_HARMONIC = 2 };
 enum { WMC_FP64 = 0, WMC_MIXED = 1 };
+/* acceptance test: Metropolis min(1, e^(-dU/kT)) (Eq. "Metropolis test"), or Glauber
+ * 1/(1 + e^(dU/kT)) (anticipated at the end of Sec. IV "Choosing the wavelet amplitude") */
+enum { WMC_ACCEPT_METROPOLIS = 0, WMC_ACCEPT_GLAUBER = 1 };
+/* wavelet displacement: the linear map r + A w((r - b)/lambda, p) as printed (Eq. "Oseen as
+ * <ww>"), or the exact rotation of r about the axis p through b by the angle
+ * A (1 - |x|)/lambda, equal to it to first order, an exact involution (p -> -p) with unit
+ * Jacobian, so that no Jacobian term is needed in the test (Sec. IV) */
+enum { WMC_MAP_LINEAR = 0, WMC_MAP_ROTATION = 1 };
+/* wavelet centres: uniform around a uniformly picked bead (Eq. "PDF for b"), or uniform in a
+ * homogeneous periodic box with A_w = A0 lambda / sqrt(<n>), <n> = (4 pi/3) lambda^3 N/L^3 (Sec. IV
+ * "Distribution of wavelet radii", last paragraph; the printed amplitude is read this way) */
+enum { WMC_CENTRE_ANCHOR = 0, WMC_CENTRE_UNIFORM = 1 };
+#define WMC_K_SHELLS 16
 
 #define WMC_MAX_LEVELS 16
 
@@ -69,7 +85,9 @@ typedef struct wmc_ctx wmc_ctx;
 /* Run parameters (Sec. II units: lengths in sigma, energies in epsilon). */
 typedef struct {
     int32_t periodic;        /* 1: cubic periodic box; 0: infinite system (single system only) */
-    int32_t plane_waves;     /* 1: plane-wave moves (periodic only), Sec. V */
+    int32_t plane_waves;     /* 1: plane-wave moves, Sec. V: the periodic lattice of k, or in an
+                                infinite system k from P(k) ~ k^2 I(k lambda_max) (Eq. "PDF of k")
+                                with P_F = (lambda_min/lambda_max)^3 (Eq. "P(Fourier) infinite") */
     int32_t wavelets;        /* 1: wavelet moves (0 only for plane-wave-only checks) */
     int32_t precision;       /* WMC_FP64, or WMC_MIXED: FP32 energy terms with FP64 recheck */
     double box_L;            /* box side, used when sys_box_L is NULL */
@@ -87,6 +105,10 @@ typedef struct {
     int32_t n_layers;        /* half-width of the discrete k cube (App. D, 15) */
     int32_t retry_cap;       /* attempts per recycling chain before giving up (64) */
     uint64_t seed;           /* Philox key */
+    int32_t accept_rule;     /* WMC_ACCEPT_* */
+    int32_t wavelet_map;     /* WMC_MAP_* */
+    int32_t centring;        /* WMC_CENTRE_* (UNIFORM needs a periodic box) */
+    int32_t pad;
 } wmc_params;
 
 /* Counters summed over systems (wmc_observables). */
@@ -111,6 +133,10 @@ typedef struct {
                                              tile, run on the global-list path instead */
     int64_t accepted_bead_updates;        /* beads displaced by accepted moves (a k = 0 plane
                                              wave displaces none) */
+    /* plane-wave tests and accepts per |k| shell (Fig. "k acceptance prob"): periodic
+     * floor(|l|) of the lattice index l, infinite floor(|k| lambda_max), capped at 15 */
+    int64_t pw_shell_attempts[WMC_K_SHELLS];
+    int64_t pw_shell_accepts[WMC_K_SHELLS];
 } wmc_obs;
 
 /* One trace record per Metropolis test (kind 0 wavelet, 2 plane wave) and per cell phase
@@ -125,10 +151,17 @@ int wmc_arena_bytes(const wmc_params* p, int32_t n_systems, const int64_t* sys_b
                     const double* sys_box_L, const double* sys_lambda_max, int64_t n_chains,
                     const int64_t* chain_offset, int64_t trace_capacity, size_t* out_bytes);
 
-/* Validate parameters, build the per-system schedule tables (levels, P_F, k tables, dt),
- * copy the positions [N][3] to the device arena, check that the initial energy is finite.
- * sys_box_L / sys_lambda_max may be NULL (then params.box_L / params.lambda_max apply to
- * every system). trace_capacity > 0 reserves room for that many trace records. */
+/* Set up the problem of Sec. II: N_b-bead chains with FENE (Eq. "FENE potential") or harmonic
+ * bonds and WCA pairs (Eq. "WCA potential") in periodic boxes or an infinite system. Validates
+ * the parameters, builds the per-system schedule tables (levels of Eq. "PDF for lambda", P_F of
+ * Eqs. "P(Fourier)" / "P(Fourier) infinite", the k tables of App. D, dt of Eqs. "Time step per
+ * wavelet" / "dt w+F"), copies the positions [N][3] (host, FP64, caller-owned, read only) into
+ * the device arena and checks that the initial energy is finite. sys_box_L / sys_lambda_max may
+ * be NULL (then params.box_L / params.lambda_max apply to every system). trace_capacity > 0
+ * reserves room for that many trace records. Errors: WMC_EINVAL (parameters, topology),
+ * WMC_ESTATE (an overstretched FENE bond or two beads of one system at the same point, whose
+ * energy is infinite), WMC_EARENA (arena missing or smaller than wmc_arena_bytes), WMC_EHIP.
+ * *out is set even on failure (for wmc_last_error) and must be freed with wmc_free. */
 int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t n_systems, const int64_t* sys_bead_offset,
              const double* sys_box_L, const double* sys_lambda_max, int64_t n_chains,
              const int64_t* chain_offset, const double* pos_xyz, int64_t trace_capacity,
@@ -159,14 +192,21 @@ int wmc_init_static(wmc_ctx** out, const wmc_params* p, int32_t n_systems, const
  * in colour phases, then the plane-wave chains (Sec. IV-V as summarised above). */
 int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* hip_stream);
 
-/* Copy positions [N][3] FP64 to out_xyz: host memory (to_device = 0, synchronous) or device
- * memory (to_device = 1, asynchronous on hip_stream). */
+/* The state of Sec. II: bead positions r_i, [N][3] FP64 unwrapped, copied to out_xyz (caller-owned)
+ * in host memory (to_device = 0, synchronous) or device memory (to_device = 1, asynchronous on
+ * hip_stream). */
 int wmc_positions(wmc_ctx* c, double* out_xyz, int32_t to_device, void* hip_stream);
 
 /* Replace the positions (host [N][3]) and set the sweep counter (which keys the streams). */
 int wmc_set_state(wmc_ctx* c, const double* pos_xyz, int64_t sweep, void* hip_stream);
 
-/* Counters (synchronises the stream). */
+/* Counters of the moves (synchronises the device): per wavelet level the trials, hits, Metropolis
+ * tests and accepts whose ratio is the acceptance of Fig. "wavelet acceptance plot", per |k| shell
+ * the plane-wave tests and accepts of Fig. "k acceptance prob", and the bead-updates that measure
+ * the cost per move (Sec. IV "Computational cost"). out is filled in every case. Returns
+ * WMC_ECAPACITY when a cell list overflowed (overflows > 0) and WMC_ESCHEDULE when a dependency
+ * wait hit its bound (wait_timeouts > 0) since wmc_init: the sweeps concerned are then not
+ * valid samples of the method. */
 int wmc_observables(wmc_ctx* c, wmc_obs* out);
 
 /* Physical time per system in units of tau (Eq. "Unit of Time"): dt x accepted chains. */
@@ -174,6 +214,13 @@ int wmc_system_tau(wmc_ctx* c, double* out /* [n_systems] */);
 
 /* Mean-square radius of gyration of every chain (Eq. "Radius of gyration"). */
 int wmc_chain_rg2(wmc_ctx* c, double* out /* [n_chains] */);
+
+/* Centre of mass of every chain from the unwrapped positions (Sec. VI.B), host [n_chains][3]. */
+int wmc_chain_com(wmc_ctx* c, double* out);
+
+/* Squared displacement of every chain's centre of mass since the positions of wmc_init or the
+ * last wmc_set_state, host [n_chains]; <.>/(6 t) over chains is D of Sec. VI.B. */
+int wmc_chain_msd(wmc_ctx* c, double* out);
 
 /* Move up to max trace records to out (host) and clear the trace; returns the count in
  * *n_out. Records are in completion order; sort by (sweep, system, level, cell, trial, retry). */

@@ -669,7 +669,7 @@ static void plane_waves(wo_ctx* c, wo_system* s, int sysid) {
             if (per) {
                 double ks = 2.0 * WO_PI / s->L;
                 for (int a = 0; a < 3; ++a) k[a] = ks * (double)l[a];
-                double lm = sqrt((double)(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]));
+                double lm = sqrt(((double)l[0] * (double)l[0] + (double)l[1] * (double)l[1]) + (double)l[2] * (double)l[2]);
                 shell = lm < WO_K_SHELLS - 1 ? (int)lm : WO_K_SHELLS - 1;
                 extra = (int)((((uint32_t)(l[0] + 512) & 0x3FFu) << 20) | (((uint32_t)(l[1] + 512) & 0x3FFu) << 10) |
                               ((uint32_t)(l[2] + 512) & 0x3FFu));

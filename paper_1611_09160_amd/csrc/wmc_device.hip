@@ -154,6 +154,16 @@ __device__ __forceinline__ double u_pair(const DevParams& P, double r2) {
     return 4.0 * P.eps * (s6 * s6 - s6 + 0.25);
 }
 
+// Acceptance threshold on dU for a uniform u in (0, 1]: Metropolis (Eq. "Metropolis test") accepts
+// iff dU <= -kT ln u, probability min(1, e^(-dU/kT)); Glauber iff dU <= kT ln((1 - u)/u), probability
+// 1/(1 + e^(dU/kT)) (1 - u is exact for u = m 2^-53)
+// VAR = false compiles the paper's defaults only (no register cost for the variants)
+template <bool VAR>
+__device__ __forceinline__ double accept_threshold(const DevParams& P, double u) {
+    if (VAR && P.accept_rule == WMC_ACCEPT_GLAUBER) return P.kT * (log(1.0 - u) - log(u));
+    return -P.kT * log(u);
+}
+
 // FP32 term and its sensitivity together (mixed precision). The cut-off and the FENE limit are
 // applied to the FP64 r2, exactly as in the FP64 terms; the term is then evaluated in FP32. The
 // sensitivity only scales the recheck margin (64 ulp of it, about ten times the rounding it
@@ -196,8 +206,22 @@ struct Grid {
     double o[3];
     double h, invh, half, L, invL;
     int64_t n[3];
+    int64_t k0[3];  // infinite system: lattice index of local cell 0 along each axis
     int periodic;
 };
+
+// Colour parity of local cell 0: cells are coloured by the parity of their lattice index, which in an
+// infinite system starts at k0 (a periodic grid starts at 0)
+__device__ __forceinline__ int grid_parity(const Grid& g) {
+    return (int)((g.k0[0] & 1) | ((g.k0[1] & 1) << 1) | ((g.k0[2] & 1) << 2));
+}
+
+// Stream key of a cell: its index in a periodic grid, or its lattice index modulo 256 per axis in an
+// infinite system, so that neither the colours nor the random streams depend on the positions
+__device__ __forceinline__ int64_t cell_key(const Grid& g, const int64_t ic[3]) {
+    if (g.periodic) return ic[0] + g.n[0] * (ic[1] + g.n[1] * ic[2]);
+    return ((g.k0[0] + ic[0]) & 255) | (((g.k0[1] + ic[1]) & 255) << 8) | (((g.k0[2] + ic[2]) & 255) << 16);
+}
 
 __device__ __forceinline__ double minimg(const Grid& g, double d) {
     return g.periodic ? d - g.L * rint(d * g.invL) : d;
@@ -249,6 +273,7 @@ __device__ __forceinline__ void make_grid(const DevParams& P, const DevPtrs& D, 
         for (int a = 0; a < 3; ++a) {
             g.o[a] = lv.h * st.co();
             g.n[a] = lv.n;
+            g.k0[a] = 0;
         }
     } else {
         g.L = 0.0;
@@ -256,6 +281,7 @@ __device__ __forceinline__ void make_grid(const DevParams& P, const DevPtrs& D, 
         for (int a = 0; a < 3; ++a) {
             g.o[a] = D.igrid[a];
             g.n[a] = (int64_t)D.igrid[3 + a];
+            g.k0[a] = (int64_t)D.igrid[6 + a];
         }
     }
 }
@@ -286,6 +312,71 @@ __device__ __forceinline__ void fine_range(double lo, double hi, double invg, in
     } else {
         f0 = ((a % nf) + nf) % nf;
     }
+}
+
+// the wavelet of the current test: centre, polarisation, radius and amplitude
+struct WaveDesc {
+    double b[3], p[3], lam, A;
+    int rot;  // WMC_MAP_ROTATION: the exact-rotation map
+};
+
+// Displacement of a bead at (x, y, z) by the wavelet, x_r = minimg(r - b)/lambda:
+//  linear map (Eqs. "Oseen as <ww>", "Tapered wavelet"): A w(x_r, p) = A (1 - |x_r|) p x x_r;
+//  rotation map: lambda x_r turned about p by the angle a = (A/lambda)(1 - |x_r|), by Rodrigues'
+//  formula lambda [sin a (p x x_r) + (1 - cos a)(p (p.x_r) - x_r)] with 1 - cos a = 2 sin^2(a/2).
+__device__ __forceinline__ void wavelet_disp(const Grid& g, const WaveDesc& wv, double x, double y, double z,
+                                             double& w0, double& w1, double& w2) {
+    const double xr0 = minimg(g, x - wv.b[0]) / wv.lam;
+    const double xr1 = minimg(g, y - wv.b[1]) / wv.lam;
+    const double xr2 = minimg(g, z - wv.b[2]) / wv.lam;
+    const double rr = sqrt((xr0 * xr0 + xr1 * xr1) + xr2 * xr2);
+    if (wv.rot) {
+        const double a = rr < 1.0 ? (wv.A / wv.lam) * (1.0 - rr) : 0.0;
+        const double sa = sin(a), hs = sin(0.5 * a), omc = 2.0 * hs * hs;
+        const double pd = (wv.p[0] * xr0 + wv.p[1] * xr1) + wv.p[2] * xr2;
+        w0 = wv.lam * (sa * (wv.p[1] * xr2 - wv.p[2] * xr1) + omc * (wv.p[0] * pd - xr0));
+        w1 = wv.lam * (sa * (wv.p[2] * xr0 - wv.p[0] * xr2) + omc * (wv.p[1] * pd - xr1));
+        w2 = wv.lam * (sa * (wv.p[0] * xr1 - wv.p[1] * xr0) + omc * (wv.p[2] * pd - xr2));
+        return;
+    }
+    const double f = rr < 1.0 ? wv.A * (1.0 - rr) : 0.0;
+    w0 = f * (wv.p[1] * xr2 - wv.p[2] * xr1);
+    w1 = f * (wv.p[2] * xr0 - wv.p[0] * xr2);
+    w2 = f * (wv.p[0] * xr1 - wv.p[1] * xr0);
+}
+
+// Amplitude of a wavelet of radius lam holding n beads (Eq. "Wavelet amplitude"); uniform centres
+// use the mean count <n> = (4 pi/3) lam^3 N/L^3 of the homogeneous box instead of n
+template <bool VAR>
+__device__ __forceinline__ double wavelet_amp(const DevParams& P, const SysDesc& s, double lam, int n) {
+    if (VAR && P.centring == WMC_CENTRE_UNIFORM)
+        return P.A0 * lam / sqrt((4.0 * kPi / 3.0) * lam * lam * lam * (double)s.N / (s.L * s.L * s.L));
+    return P.A0 * lam / sqrt((double)n);
+}
+
+// Trial centre of a wavelet from stream st: anchored, b = r_a + lam V with a uniform in the reach list
+// (its slot or bead via pick) and V uniform in the unit ball (Eq. "PDF for b", App. D); uniform, b
+// uniform in the cell. Returns whether b lies in the cell; a = -1 for uniform centres.
+template <bool VAR, class Pick, class Pos>
+__device__ __forceinline__ bool draw_trial_centre(const DevParams& P, Stream& st, const Grid& g, const int64_t ic[3],
+                                                  int64_t cell, double lam, int nS, Pick pick, Pos pos, int32_t& a,
+                                                  double& bx, double& by, double& bz) {
+    if (VAR && P.centring == WMC_CENTRE_UNIFORM) {
+        a = -1;
+        bx = g.o[0] + ((double)ic[0] + st.co()) * g.h;
+        by = g.o[1] + ((double)ic[1] + st.co()) * g.h;
+        bz = g.o[2] + ((double)ic[2] + st.co()) * g.h;
+    } else {
+        a = pick(st.index(nS));
+        double vx, vy, vz;
+        ball(st, vx, vy, vz);
+        double ax, ay, az;
+        pos(a, ax, ay, az);
+        bx = ax + lam * vx;
+        by = ay + lam * vy;
+        bz = az + lam * vz;
+    }
+    return cell_of_point(g, bx, by, bz) == cell;
 }
 
 // ------------------------------------------------------------------- workgroup helpers
@@ -465,6 +556,7 @@ __global__ __launch_bounds__(1024) void k_scan_apply(DevPtrs D, int nsys, int nc
     if ((int)blockIdx.x == nchunks - 1 && tid == 1023) D.fstart[D.total_fine] = base + part[1023];
     if (blockIdx.x == 0) {
         for (int s = tid; s < nsys; s += 1024) D.drift[s] = 0ull;
+        for (int s = tid; s < 8 * nsys; s += 1024) D.drift_col[s] = 0ull;
         if (tid == 0) atomicAdd(&D.cnt[CNT_REBUILD], 1ull);
     }
 }
@@ -525,13 +617,19 @@ __global__ __launch_bounds__(1024) void k_bbox(DevParams P, DevPtrs D, int level
         gmx[a] = block_max<1024>(mx[a], red);
     }
     if (threadIdx.x == 0) {
+        // the cells of the fixed lattice h (k + u), k integer, that cover the bounding box grown
+        // by lambda_hi: the lattice, the colour of a cell (parity of k) and its stream key do not
+        // depend on the positions
         Stream st;
         st.init(P, 0, sweep, TAG_SHIFT + level, 0, 0, 0, 0);
         double invh = 1.0 / lv.h;
         for (int a = 0; a < 3; ++a) {
-            double o = gmn[a] - lv.hi - lv.h * st.co();
-            D.igrid[a] = o;
-            D.igrid[3 + a] = (double)((int64_t)floor((gmx[a] + lv.hi - o) * invh) + 1);
+            const double u = st.co();
+            const int64_t kmin = (int64_t)floor((gmn[a] - lv.hi) * invh - u);
+            const int64_t kmax = (int64_t)floor((gmx[a] + lv.hi) * invh - u);
+            D.igrid[a] = ((double)kmin + u) * lv.h;
+            D.igrid[3 + a] = (double)(kmax - kmin + 1);
+            D.igrid[6 + a] = (double)kmin;
         }
     }
 }
@@ -599,6 +697,24 @@ struct PhaseShared {
     int32_t pub_a;
     uint32_t pub_next;
 };
+
+// grid coordinates of the local-th cell of a colour (in an infinite system the colour is the parity of
+// the lattice index k0 + ic, so local parities are the colour's bits flipped by those of k0)
+__device__ __forceinline__ void cell_coords(const DevParams& P, const LevelDesc& lv, const Grid& g, int colour,
+                                            int64_t local, int64_t ic[3]) {
+    if (P.periodic) {
+        int64_t m = lv.n >= 2 ? lv.n / 2 : 1;
+        ic[0] = 2 * (local % m) + (lv.n >= 2 ? (colour & 1) : 0);
+        ic[1] = 2 * ((local / m) % m) + (lv.n >= 2 ? ((colour >> 1) & 1) : 0);
+        ic[2] = 2 * (local / (m * m)) + (lv.n >= 2 ? ((colour >> 2) & 1) : 0);
+    } else {
+        const int lc = colour ^ grid_parity(g);
+        int64_t mx = (g.n[0] - (lc & 1) + 1) / 2, my = (g.n[1] - ((lc >> 1) & 1) + 1) / 2;
+        ic[0] = 2 * (local % mx) + (lc & 1);
+        ic[1] = 2 * ((local / mx) % my) + ((lc >> 1) & 1);
+        ic[2] = 2 * (local / (mx * my)) + ((lc >> 2) & 1);
+    }
+}
 
 // energy change of the current test, global-memory form: bonds and WCA pairs with >= 1
 // member, each once. Members Ml[0..n) with trial positions MXl/MYl/MZl (LDS or global) and
@@ -701,29 +817,23 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
     }
 }
 
-template <int W, int CAPS, int CAPM, bool MIXED>
+// Dg bounds the drift, since the neighbour grid was built, of every bead this cell can meet; the
+// largest drift of the beads the cell moves is returned in dl_out.
+template <int W, int CAPS, int CAPM, bool MIXED, bool VAR>
 __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& D,
                                                        PhaseShared<W, CAPS, CAPM>& sh, int sys,
-                             int level, int colour, int64_t local, int64_t sweep, const Grid& g) {
+                             int level, int colour, int64_t local, int64_t sweep, const Grid& g,
+                             const double Dg, double& dl_out) {
     const SysDesc& s = D.sys[sys];
     const LevelDesc& lv = D.lev[s.lvl_off + level];
     const int tid = threadIdx.x;
     // cell coordinates of the local-th cell of this colour
     int64_t ic[3];
-    if (P.periodic) {
-        int64_t m = lv.n >= 2 ? lv.n / 2 : 1;
-        ic[0] = 2 * (local % m) + (lv.n >= 2 ? (colour & 1) : 0);
-        ic[1] = 2 * ((local / m) % m) + (lv.n >= 2 ? ((colour >> 1) & 1) : 0);
-        ic[2] = 2 * (local / (m * m)) + (lv.n >= 2 ? ((colour >> 2) & 1) : 0);
-    } else {
-        int64_t mx = (g.n[0] - (colour & 1) + 1) / 2, my = (g.n[1] - ((colour >> 1) & 1) + 1) / 2;
-        ic[0] = 2 * (local % mx) + (colour & 1);
-        ic[1] = 2 * ((local / mx) % my) + ((colour >> 1) & 1);
-        ic[2] = 2 * (local / (mx * my)) + ((colour >> 2) & 1);
-    }
+    cell_coords(P, lv, g, colour, local, ic);
     const int64_t cell = ic[0] + g.n[0] * (ic[1] + g.n[1] * ic[2]);
+    const int64_t key = cell_key(g, ic);
     const double hi2 = lv.hi * lv.hi;
-    const double Dg = __longlong_as_double((long long)D.drift[sys]);
+    dl_out = 0.0;
     const bool glob = lv.use_global != 0;
     int32_t* Sg = D.slot_S + (lv.slot_base + local) * D.slot_len;
     int32_t* Mg = D.slot_M + (lv.slot_base + local) * D.slot_len;
@@ -819,12 +929,13 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
     const int32_t* S = lv.identity ? nullptr : (glob ? Sg : sh.S);
     auto Sat = [&](int64_t i) -> int32_t { return S ? S[i] : (int32_t)(s.b0 + i); };
 
-    // ---- 2. number of trials
-    double mu = (lv.T * (double)nS) / (double)s.N;
+    // ---- 2. number of trials: T_l |S_c| / N (anchored centres) or T_l / n^3 (uniform centres)
+    const bool uni = VAR && P.centring == WMC_CENTRE_UNIFORM;
+    double mu = uni ? lv.T / ((double)g.n[0] * (double)g.n[1] * (double)g.n[2]) : (lv.T * (double)nS) / (double)s.N;
     int64_t K = (int64_t)floor(mu);
     {
         Stream ms;
-        ms.init(P, sys, sweep, TAG_META + level, cell, 0, 0, 0);
+        ms.init(P, sys, sweep, TAG_META + level, key, 0, 0, 0);
         if (ms.co() < mu - (double)K) K += 1;
     }
     if (K > 0xFFFFF) {
@@ -838,6 +949,13 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
     const double L = s.L, invL = s.invL;
     const double lam_hi = lv.hi;
 
+    auto pos_of = [&](int32_t j, double& px, double& py, double& pz) {
+        px = D.x[j];
+        py = D.y[j];
+        pz = D.z[j];
+    };
+    bool stop = false;  // a member list overflowed: the cell's remaining moves are skipped
+
     // ---- 3. trials and chains
     for (int64_t t0 = 0; t0 < K;) {
         int64_t t = t0 + tid;
@@ -845,16 +963,10 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
         double lam = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
         int32_t a = 0;
         Stream st;
-        if (t < K && nS > 0) {
-            st.init(P, sys, sweep, level, cell, t, 0, 0);
+        if (t < K && (nS > 0 || uni)) {
+            st.init(P, sys, sweep, level, key, t, 0, 0);
             lam = draw_lambda(st.co(), lv.lo, lam_hi);
-            a = Sat(st.index(nS));
-            double vx, vy, vz;
-            ball(st, vx, vy, vz);
-            bx = D.x[a] + lam * vx;
-            by = D.y[a] + lam * vy;
-            bz = D.z[a] + lam * vz;
-            hit = cell_of_point(g, bx, by, bz) == cell;
+            hit = draw_trial_centre<VAR>(P, st, g, ic, cell, lam, nS, Sat, pos_of, a, bx, by, bz);
         }
         int first = block_min_int<W>(hit ? (int)(t - t0) : 0x7FFFFFFF, sh.redi);
         if (first == 0x7FFFFFFF) {
@@ -881,7 +993,7 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
         for (int r = 0;;) {
             // direction and acceptance draw continue the stream of (tc, r, jtry)
             Stream cs;
-            cs.init(P, sys, sweep, level, cell, tc, r, jtry);
+            cs.init(P, sys, sweep, level, key, tc, r, jtry);
             cs.next = nxt;
             double px, py, pz;
             direction(cs, px, py, pz);
@@ -921,25 +1033,30 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
             __syncthreads();
             const bool inL = n <= CAPM;
             if (!inL && !glob) {
+                // nothing of this test has moved yet: count it and end the cell here, publishing
+                // the drift and counters of the moves made so far
                 if (tid == 0) atomicAdd(&D.cnt[CNT_OVERFLOW], 1ull);
-                __syncthreads();
-                return;
+                stop = true;
+                break;
             }
             const int32_t* Ml = inL ? sh.M : Mg;
             double *MXl = inL ? sh.MX : MXg, *MYl = inL ? sh.MY : MXg + D.slot_len,
                    *MZl = inL ? sh.MZ : MXg + 2 * D.slot_len;
-            const double A = P.A0 * lam / sqrt((double)n);
+            WaveDesc wv;
+            wv.b[0] = b[0];
+            wv.b[1] = b[1];
+            wv.b[2] = b[2];
+            wv.p[0] = px;
+            wv.p[1] = py;
+            wv.p[2] = pz;
+            wv.lam = lam;
+            wv.A = wavelet_amp<VAR>(P, s, lam, n);
+            wv.rot = VAR && P.wavelet_map == WMC_MAP_ROTATION;
             double dmax_l = 0.0;
             for (int k = tid; k < n; k += W) {
                 int32_t j = Ml[k];
-                double xr0 = minimg(g, D.x[j] - b[0]) / lam;
-                double xr1 = minimg(g, D.y[j] - b[1]) / lam;
-                double xr2 = minimg(g, D.z[j] - b[2]) / lam;
-                double rr = sqrt((xr0 * xr0 + xr1 * xr1) + xr2 * xr2);
-                double f = rr < 1.0 ? A * (1.0 - rr) : 0.0;
-                double w0 = f * (py * xr2 - pz * xr1);
-                double w1 = f * (pz * xr0 - px * xr2);
-                double w2 = f * (px * xr1 - py * xr0);
+                double w0, w1, w2;
+                wavelet_disp(g, wv, D.x[j], D.y[j], D.z[j], w0, w1, w2);
                 MXl[k] = D.x[j] + w0;
                 MYl[k] = D.y[j] + w1;
                 MZl[k] = D.z[j] + w2;
@@ -949,7 +1066,7 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
             const double dmax = block_max<W>(dmax_l, sh.red);  // includes a barrier: tags visible
             const double Rq = P.rc + 2.0 * dmax + fmax(Dg, d_local) + 1e-9 * L;
             double dU;
-            const double thr = -P.kT * log(u_acc);
+            const double thr = accept_threshold<VAR>(P, u_acc);
             {
                 double acc = 0.0, sens = 0.0;
                 glob_dU(P, D, s, Ml, MXl, MYl, MZl, n, Rq, mixed ? 1 : 0, tid, W, acc, sens, c_viol);
@@ -968,7 +1085,7 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
                 }
             }
             const bool accept = dU <= thr;
-            if (tid == 0) trace_push(D, 0, sys, sweep, level, cell, tc, r, n, accept ? 1 : 0, a, dU, thr);
+            if (tid == 0) trace_push(D, 0, sys, sweep, level, key, tc, r, n, accept ? 1 : 0, a, dU, thr);
             ++c_att;
             c_beads += n;
             for (int k = tid; k < n; k += W) {
@@ -1002,14 +1119,8 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
                 int32_t a2 = 0;
                 Stream rs;
                 if (jj < 4096) {
-                    rs.init(P, sys, sweep, level, cell, tc, r, jj);
-                    a2 = Sat(rs.index(nS));
-                    double vx, vy, vz;
-                    ball(rs, vx, vy, vz);
-                    ex = D.x[a2] + lam * vx;
-                    ey = D.y[a2] + lam * vy;
-                    ez = D.z[a2] + lam * vz;
-                    h2 = cell_of_point(g, ex, ey, ez) == cell;
+                    rs.init(P, sys, sweep, level, key, tc, r, jj);
+                    h2 = draw_trial_centre<VAR>(P, rs, g, ic, cell, lam, nS, Sat, pos_of, a2, ex, ey, ez);
                 }
                 int fj = block_min_int<W>(h2 ? jj : 0x7FFFFFFF, sh.redi);
                 if (fj != 0x7FFFFFFF) {
@@ -1038,8 +1149,10 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
             jtry = found;
             __syncthreads();
         }
+        if (stop) break;
         t0 = tc + 1;
     }
+    __syncthreads();
     // ---- counters
     unsigned long long viol_all = (unsigned long long)block_sum<W>((double)c_viol, sh.red);
     if (tid == 0) {
@@ -1057,8 +1170,9 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
             atomicAdd(&D.sys_acc[sys], c_acc);
         }
         if (d_local > 0.0) atomic_max_double(&D.drift[sys], d_local);
-        trace_push(D, 1, sys, sweep, level, cell, K, nS, 0, (int)c_hits, 0, 0.0, 0.0);
+        trace_push(D, 1, sys, sweep, level, key, K, nS, 0, (int)c_hits, 0, 0.0, 0.0);
     }
+    dl_out = d_local;
     __syncthreads();
 }
 
@@ -1139,24 +1253,6 @@ __device__ __forceinline__ int tile_clamp(const TileGeo& tg, double u) {
 
 __device__ __forceinline__ double tile_u(const Grid& g, const TileGeo& tg, double v, int a) {
     return minimg(g, v - tg.c[a]) + tg.He;
-}
-
-// the wavelet of the current test: centre, polarisation, radius and amplitude
-struct WaveDesc {
-    double b[3], p[3], lam, A;
-};
-
-// displacement A w((r - b) / lambda, p) of a bead at (x, y, z), Eq. "Tapered wavelet"
-__device__ __forceinline__ void wavelet_disp(const Grid& g, const WaveDesc& wv, double x, double y, double z,
-                                             double& w0, double& w1, double& w2) {
-    const double xr0 = minimg(g, x - wv.b[0]) / wv.lam;
-    const double xr1 = minimg(g, y - wv.b[1]) / wv.lam;
-    const double xr2 = minimg(g, z - wv.b[2]) / wv.lam;
-    const double rr = sqrt((xr0 * xr0 + xr1 * xr1) + xr2 * xr2);
-    const double f = rr < 1.0 ? wv.A * (1.0 - rr) : 0.0;
-    w0 = f * (wv.p[1] * xr2 - wv.p[2] * xr1);
-    w1 = f * (wv.p[2] * xr0 - wv.p[0] * xr2);
-    w2 = f * (wv.p[0] * xr1 - wv.p[1] * xr0);
 }
 
 // trial position of member k (tile slot sl)
@@ -1338,21 +1434,6 @@ __device__ __forceinline__ int tile_find(const TileShared<W, CAPH, CAPM, NCD>& s
     return -1;
 }
 
-__device__ __forceinline__ void cell_coords(const DevParams& P, const LevelDesc& lv, const Grid& g, int colour,
-                                            int64_t local, int64_t ic[3]) {
-    if (P.periodic) {
-        int64_t m = lv.n >= 2 ? lv.n / 2 : 1;
-        ic[0] = 2 * (local % m) + (lv.n >= 2 ? (colour & 1) : 0);
-        ic[1] = 2 * ((local / m) % m) + (lv.n >= 2 ? ((colour >> 1) & 1) : 0);
-        ic[2] = 2 * (local / (m * m)) + (lv.n >= 2 ? ((colour >> 2) & 1) : 0);
-    } else {
-        int64_t mx = (g.n[0] - (colour & 1) + 1) / 2, my = (g.n[1] - ((colour >> 1) & 1) + 1) / 2;
-        ic[0] = 2 * (local % mx) + (colour & 1);
-        ic[1] = 2 * ((local / mx) % my) + ((colour >> 1) & 1);
-        ic[2] = 2 * (local / (mx * my)) + ((colour >> 2) & 1);
-    }
-}
-
 // energy change of the current test over the tile: bonds and WCA pairs with >= 1 member, each
 // once; members are tile slots sh.M[0..n) with tags set (trial positions via member_new).
 // WCA partners come from the tile cell list: every bead within R (tile coordinates, per
@@ -1459,20 +1540,23 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
 }
 
 // returns false (before any move) when the halo does not fit; the caller then uses the
-// global path for this cell
-template <int W, int CAPH, int CAPM, int NCD, bool MIXED>
+// global path for this cell. Dg bounds the drift, since the neighbour grid was built, of every bead
+// the cell can meet; the largest drift of the beads the cell moves is returned in dl_out.
+template <int W, int CAPH, int CAPM, int NCD, bool MIXED, bool VAR>
 __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShared<W, CAPH, CAPM, NCD>& sh, int sys,
-                                  int level, int colour, int64_t local, int64_t sweep, const Grid& g) {
+                                  int level, int colour, int64_t local, int64_t sweep, const Grid& g,
+                                  const double Dg, double& dl_out) {
     const SysDesc& s = D.sys[sys];
     const LevelDesc& lv = D.lev[s.lvl_off + level];
     const int tid = threadIdx.x;
     int64_t ic[3];
     cell_coords(P, lv, g, colour, local, ic);
     const int64_t cell = ic[0] + g.n[0] * (ic[1] + g.n[1] * ic[2]);
+    const int64_t key = cell_key(g, ic);
     const double hi2 = lv.hi * lv.hi;
     const double rh = lv.hi + lv.r_int, rh2 = rh * rh;
-    const double Dg = __longlong_as_double((long long)D.drift[sys]);
     const double L = s.L, invL = s.invL;
+    dl_out = 0.0;
 
     // tile cell list geometry; relative tile coordinates identify pairs only while the tile
     // (plus a cut-off and a margin for moves) is shorter than the box
@@ -1596,11 +1680,12 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     double E = 0.0;  // bound on any tile bead's displacement since the cell list was built
 
     // ---- 3. trials and chains (as the global path, on LDS)
-    double mu = (lv.T * (double)nS) / (double)s.N;
+    const bool uni = VAR && P.centring == WMC_CENTRE_UNIFORM;
+    double mu = uni ? lv.T / ((double)g.n[0] * (double)g.n[1] * (double)g.n[2]) : (lv.T * (double)nS) / (double)s.N;
     int64_t K = (int64_t)floor(mu);
     {
         Stream ms;
-        ms.init(P, sys, sweep, TAG_META + level, cell, 0, 0, 0);
+        ms.init(P, sys, sweep, TAG_META + level, key, 0, 0, 0);
         if (ms.co() < mu - (double)K) K += 1;
     }
     if (K > 0xFFFFF) {
@@ -1612,28 +1697,48 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     constexpr bool mixed = MIXED;
     // trials are drawn W at a time (one per lane); the draws (lambda, anchor, ball vector, stream
     // position) do not depend on positions, so a lane keeps its trial across the chains of earlier
-    // hits and only its hit test, which reads the anchor's current position, is repeated
+    // hits and only its hit test, which reads the anchor's current position, is repeated (a uniform
+    // centre is drawn whole and kept in the ball vector's place)
+    auto slot_of = [&](int64_t i) -> int32_t { return (int32_t)sh.S[i]; };
+    auto slot_pos = [&](int32_t sl, double& px, double& py, double& pz) {
+        px = sh.x[sl];
+        py = sh.y[sl];
+        pz = sh.z[sl];
+    };
     for (int64_t t0 = 0; t0 < K; t0 += W) {
         const int64_t t = t0 + tid;
-        const bool drawn = t < K && nS > 0;
+        const bool drawn = t < K && (nS > 0 || uni);
         double lam_t = 0.0, vx_t = 0.0, vy_t = 0.0, vz_t = 0.0;
         int as_t = 0;
         uint32_t next_t = 0;
         if (drawn) {
             Stream st;
-            st.init(P, sys, sweep, level, cell, t, 0, 0);
+            st.init(P, sys, sweep, level, key, t, 0, 0);
             lam_t = draw_lambda(st.co(), lv.lo, lv.hi);
-            as_t = sh.S[st.index(nS)];
-            ball(st, vx_t, vy_t, vz_t);
+            if (uni) {
+                as_t = -1;
+                vx_t = g.o[0] + ((double)ic[0] + st.co()) * g.h;
+                vy_t = g.o[1] + ((double)ic[1] + st.co()) * g.h;
+                vz_t = g.o[2] + ((double)ic[2] + st.co()) * g.h;
+            } else {
+                as_t = sh.S[st.index(nS)];
+                ball(st, vx_t, vy_t, vz_t);
+            }
             next_t = st.next;
         }
       for (int from = 0;;) {
         bool hit = false;
         double bx = 0.0, by = 0.0, bz = 0.0;
         if (drawn && tid >= from) {
-            bx = sh.x[as_t] + lam_t * vx_t;
-            by = sh.y[as_t] + lam_t * vy_t;
-            bz = sh.z[as_t] + lam_t * vz_t;
+            if (uni) {
+                bx = vx_t;
+                by = vy_t;
+                bz = vz_t;
+            } else {
+                bx = sh.x[as_t] + lam_t * vx_t;
+                by = sh.y[as_t] + lam_t * vy_t;
+                bz = sh.z[as_t] + lam_t * vz_t;
+            }
             hit = cell_of_point(g, bx, by, bz) == cell;
         }
         int first = block_min_int<W>(hit ? tid : 0x7FFFFFFF, sh.redi);
@@ -1657,7 +1762,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
         const double lam2 = lam * lam;
         for (int r = 0;;) {
             Stream cs;
-            cs.init(P, sys, sweep, level, cell, tc, r, jtry);
+            cs.init(P, sys, sweep, level, key, tc, r, jtry);
             cs.next = nxt;
             double px, py, pz;
             direction(cs, px, py, pz);
@@ -1709,7 +1814,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             wv.p[1] = py;
             wv.p[2] = pz;
             wv.lam = lam;
-            wv.A = P.A0 * lam / sqrt((double)n);
+            wv.A = wavelet_amp<VAR>(P, s, lam, n);
+            wv.rot = VAR && P.wavelet_map == WMC_MAP_ROTATION;
             double dmax_l = 0.0;
             for (int k = tid; k < n; k += W) {
                 const int sl = sh.M[k];
@@ -1727,7 +1833,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             const double Rq = P.rc + 2.0 * dmax + E + 1e-9 * L;
             double acc = 0.0, sens = 0.0;
             tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, mixed ? 1 : 0, acc, sens, c_viol);
-            const double thr = -P.kT * log(u_acc);
+            const double thr = accept_threshold<VAR>(P, u_acc);
             double dU = block_sum<W>(acc, sh.red);
             if (mixed) {
                 double bound = 64.0 * 0x1.0p-23 * block_sum<W>(sens, sh.red) + 1e-12;
@@ -1741,7 +1847,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             }
             const bool accept = dU <= thr;
             if (tid == 0)
-                trace_push(D, 0, sys, sweep, level, cell, tc, r, n, accept ? 1 : 0, sh.id[as] & ID_MASK, dU, thr);
+                trace_push(D, 0, sys, sweep, level, key, tc, r, n, accept ? 1 : 0, as >= 0 ? (sh.id[as] & ID_MASK) : -1,
+                           dU, thr);
             ++c_att;
             c_beads += n;
             for (int k = tid; k < n; k += W) {
@@ -1786,14 +1893,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 int a2 = 0;
                 Stream rs;
                 if (tid < len && jj < 4096) {
-                    rs.init(P, sys, sweep, level, cell, tc, r, jj);
-                    a2 = sh.S[rs.index(nS)];
-                    double vx, vy, vz;
-                    ball(rs, vx, vy, vz);
-                    ex = sh.x[a2] + lam * vx;
-                    ey = sh.y[a2] + lam * vy;
-                    ez = sh.z[a2] + lam * vz;
-                    h2 = cell_of_point(g, ex, ey, ez) == cell;
+                    rs.init(P, sys, sweep, level, key, tc, r, jj);
+                    h2 = draw_trial_centre<VAR>(P, rs, g, ic, cell, lam, nS, slot_of, slot_pos, a2, ex, ey, ez);
                 }
                 int fj = block_min_int<W>(h2 ? jj : 0x7FFFFFFF, sh.redi);
                 if (fj != 0x7FFFFFFF) {
@@ -1842,13 +1943,14 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             atomicAdd(&D.sys_acc[sys], c_acc);
         }
         if (d_local > 0.0) atomic_max_double(&D.drift[sys], d_local);
-        trace_push(D, 1, sys, sweep, level, cell, K, nS, 0, (int)c_hits, 0, 0.0, 0.0);
+        trace_push(D, 1, sys, sweep, level, key, K, nS, 0, (int)c_hits, 0, 0.0, 0.0);
     }
+    dl_out = d_local;
     __syncthreads();
     return true;
 }
 
-template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, bool MIXED>
+template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, bool MIXED, bool VAR>
 __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, int colour, int64_t sweep,
                                              const int32_t* bmap, int nblocks) {
     __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD> sh;
@@ -1858,46 +1960,66 @@ __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, 
         const LevelDesc& lv = D.lev[s.lvl_off + level];
         Grid g;
         make_grid(P, D, s, lv, sys, level, sweep, g);
-        if (lv.use_global || !process_cell_tile<W, CAPH, CAPMT, NCD, MIXED>(P, D, sh.t, sys, level, colour, local, sweep, g)) {
+        // the drift bound is what the earlier colours of this level published (all complete: one
+        // launch per colour); cells of this colour publish into their own colour's slot, so no
+        // cell reads a value that a cell of its own launch may still raise
+        double Dg = 0.0;
+        for (int c = 0; c < colour; ++c) Dg = fmax(Dg, __longlong_as_double((long long)D.drift_col[8 * sys + c]));
+        double dl = 0.0;
+        if (lv.use_global || !process_cell_tile<W, CAPH, CAPMT, NCD, MIXED, VAR>(P, D, sh.t, sys, level, colour, local, sweep, g,
+                                                                            Dg, dl)) {
             __syncthreads();
-            process_cell<W, CAPS, CAPM, MIXED>(P, D, sh.g, sys, level, colour, local, sweep, g);
+            process_cell<W, CAPS, CAPM, MIXED, VAR>(P, D, sh.g, sys, level, colour, local, sweep, g, Dg, dl);
         }
+        if (threadIdx.x == 0 && dl > 0.0) atomic_max_double(&D.drift_col[8 * sys + colour], dl);
     } else {
+        // infinite system: reach lists and pair searches scan every bead, no drift bound is used
         const SysDesc& s = D.sys[0];
         const LevelDesc& lv = D.lev[s.lvl_off + level];
         Grid g;
         make_grid(P, D, s, lv, 0, level, sweep, g);
-        int64_t mx = (g.n[0] - (colour & 1) + 1) / 2, my = (g.n[1] - ((colour >> 1) & 1) + 1) / 2,
-                mz = (g.n[2] - ((colour >> 2) & 1) + 1) / 2;
+        const int lc = colour ^ grid_parity(g);
+        int64_t mx = (g.n[0] - (lc & 1) + 1) / 2, my = (g.n[1] - ((lc >> 1) & 1) + 1) / 2,
+                mz = (g.n[2] - ((lc >> 2) & 1) + 1) / 2;
         int64_t cells = mx * my * mz;
+        double dl = 0.0;
         for (int64_t local = blockIdx.x; local < cells; local += gridDim.x)
-            process_cell<W, CAPS, CAPM, MIXED>(P, D, sh.g, 0, level, colour, local, sweep, g);
+            process_cell<W, CAPS, CAPM, MIXED, VAR>(P, D, sh.g, 0, level, colour, local, sweep, g, 0.0, dl);
     }
 }
 
-template <bool M>
+template <bool M, bool V>
 static void launch_phase_t(int variant, const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
                   const int32_t* bmap, int nblocks, hipStream_t st) {
     if (nblocks <= 0) return;
     if (variant == V64)
-        hipLaunchKernelGGL((k_phase<64, 1024, 256, 512, 32, 8, M>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour,
+        hipLaunchKernelGGL((k_phase<64, 1024, 256, 512, 32, 8, M, V>), dim3(nblocks), dim3(64), 0, st, P, D, level, colour,
                            sweep, bmap, nblocks);
     else if (variant == V256)
-        hipLaunchKernelGGL((k_phase<256, 4096, 1024, 1024, 512, 12, M>), dim3(nblocks), dim3(256), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_phase<256, 4096, 1024, 1024, 512, 12, M, V>), dim3(nblocks), dim3(256), 0, st, P, D, level,
                            colour, sweep, bmap, nblocks);
     else
-        hipLaunchKernelGGL((k_phase<512, 8192, 4096, 4096, 128, 18, M>), dim3(nblocks), dim3(512), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_phase<512, 8192, 4096, 4096, 128, 18, M, V>), dim3(nblocks), dim3(512), 0, st, P, D, level,
                            colour, sweep, bmap, nblocks);
 }
 
-// one kernel per precision: the FP32 terms and their recheck cost registers the FP64 path
-// does not need
+// whether a context uses any of the variants (Glauber, rotation map, uniform centres)
+static bool uses_variants(const DevParams& P) {
+    return P.accept_rule != WMC_ACCEPT_METROPOLIS || P.wavelet_map != WMC_MAP_LINEAR || P.centring != WMC_CENTRE_ANCHOR;
+}
+
+// one kernel per precision and variant set: the FP32 terms and their recheck, and the variants,
+// cost registers the FP64 path of the paper's method does not need
 void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
                   const int32_t* bmap, int nblocks, hipStream_t st) {
-    if (P.precision == WMC_MIXED)
-        launch_phase_t<true>(variant, P, D, level, colour, sweep, bmap, nblocks, st);
-    else
-        launch_phase_t<false>(variant, P, D, level, colour, sweep, bmap, nblocks, st);
+    const bool v = uses_variants(P);
+    if (P.precision == WMC_MIXED) {
+        if (v) launch_phase_t<true, true>(variant, P, D, level, colour, sweep, bmap, nblocks, st);
+        else launch_phase_t<true, false>(variant, P, D, level, colour, sweep, bmap, nblocks, st);
+    } else {
+        if (v) launch_phase_t<false, true>(variant, P, D, level, colour, sweep, bmap, nblocks, st);
+        else launch_phase_t<false, false>(variant, P, D, level, colour, sweep, bmap, nblocks, st);
+    }
 }
 
 // ------------------------------------------- level pass in dependency order (LDS tiles)
@@ -1910,17 +2032,19 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
 // (counted in CNT_FLOWWAIT when the bound is hit). Same result as eight colour phases.
 constexpr unsigned FLOW_SPIN_LIMIT = 1u << 24;
 
-template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, bool MIXED>
+template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, bool MIXED, bool VAR>
 __global__ __launch_bounds__(W, (W == 64 || MIXED) ? 2 : 1) void k_level_flow(DevParams P, DevPtrs D, int level, int64_t sweep,
                                                      const int32_t* items, FlowArgs fa) {
     __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD> sh;
     __shared__ int s_idx;
     __shared__ int s_timeout;
+    __shared__ double s_dg[27];
     const int tid = threadIdx.x;
     if (tid == 0) {
         s_idx = (int)(atomicAdd(&D.flow_ctr[level], 1ull) - fa.qbase);
         s_timeout = 0;
     }
+    if (tid < 27) s_dg[tid] = 0.0;
     __syncthreads();
     const int idx = s_idx;
     if (idx < 0 || idx >= fa.nitems) return;
@@ -1940,7 +2064,8 @@ __global__ __launch_bounds__(W, (W == 64 || MIXED) ? 2 : 1) void k_level_flow(De
         const int jx = (int)((ic[0] + dx + n) % n), jy = (int)((ic[1] + dy + n) % n), jz = (int)((ic[2] + dz + n) % n);
         const int cn = (jx & 1) | ((jy & 1) << 1) | ((jz & 1) << 2);
         if (cn < colour) {
-            const int32_t* f = D.cell_done + lv.flag_base + jx + (int64_t)n * (jy + (int64_t)n * jz);
+            const int64_t fi = lv.flag_base + jx + (int64_t)n * (jy + (int64_t)n * jz);
+            const int32_t* f = D.cell_done + fi;
             unsigned spins = 0;
             while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != fa.epoch) {
                 if (++spins >= FLOW_SPIN_LIMIT) {
@@ -1950,27 +2075,39 @@ __global__ __launch_bounds__(W, (W == 64 || MIXED) ? 2 : 1) void k_level_flow(De
                 __builtin_amdgcn_s_sleep(2);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_dg[tid] = D.cell_drift[fi];
         }
     }
     __syncthreads();
-    if (tid == 0 && s_timeout) atomicAdd(&D.cnt[CNT_FLOWWAIT], 1ull);
-    if (!process_cell_tile<W, CAPH, CAPMT, NCD, MIXED>(P, D, sh.t, sys, level, colour, local, sweep, g)) {
+    // Drift bound of this cell: the beads it can meet were moved, since this level's grid build,
+    // only by itself and by the adjacent cells of lower colours it has just waited for (a bead moved
+    // by a cell further away stays more than lambda_hi + r_int from this one), so the largest drift
+    // those cells published bounds them, independent of the timing of any other cell.
+    double Dg = 0.0;
+    for (int k = 0; k < 27; ++k) Dg = fmax(Dg, s_dg[k]);
+    double dl = 0.0;
+    if (s_timeout) {
+        // a neighbour never published: running now could race with it, so the cell is skipped and
+        // the sweep reported invalid (wmc_observables returns WMC_ESCHEDULE)
+        if (tid == 0) atomicAdd(&D.cnt[CNT_FLOWWAIT], 1ull);
+    } else if (!process_cell_tile<W, CAPH, CAPMT, NCD, MIXED, VAR>(P, D, sh.t, sys, level, colour, local, sweep, g, Dg, dl)) {
         // the halo does not fit the tile: the global-list path, inline (a call would cost a stack
         // frame and the registers saved around it, for every cell)
         __syncthreads();
         if (tid == 0) atomicAdd(&D.cnt[CNT_FALLBACK], 1ull);
-        process_cell<W, CAPS, CAPM, MIXED>(P, D, sh.g, sys, level, colour, local, sweep, g);
+        process_cell<W, CAPS, CAPM, MIXED, VAR>(P, D, sh.g, sys, level, colour, local, sweep, g, Dg, dl);
     }
-    // publish: every wave's stores complete, then one release of the epoch
+    // publish: every wave's stores complete, then this cell's drift and one release of the epoch
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
     if (tid == 0) {
-        int32_t* f = D.cell_done + lv.flag_base + ic[0] + (int64_t)n * (ic[1] + (int64_t)n * ic[2]);
-        __hip_atomic_store(f, fa.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t fi = lv.flag_base + ic[0] + (int64_t)n * (ic[1] + (int64_t)n * ic[2]);
+        D.cell_drift[fi] = dl;
+        __hip_atomic_store(D.cell_done + fi, fa.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-template <bool M>
+template <bool M, bool V>
 static void launch_level_flow_t(int variant, const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
                        const int32_t* items, const FlowArgs& fa, hipStream_t st) {
     if (fa.nitems <= 0) return;
@@ -1978,25 +2115,29 @@ static void launch_level_flow_t(int variant, const DevParams& P, const DevPtrs& 
     // per cell, since the pass is its longest chain of cells; many more cells (a batch) fill the
     // GPU better with one wave per cell
     if (variant == V64 && fa.nitems <= 4096)
-        hipLaunchKernelGGL((k_level_flow<256, 1024, 256, 512, 32, 8, M>), dim3(fa.nitems), dim3(256), 0, st, P, D,
+        hipLaunchKernelGGL((k_level_flow<256, 1024, 256, 512, 32, 8, M, V>), dim3(fa.nitems), dim3(256), 0, st, P, D,
                            level, sweep, items, fa);
     else if (variant == V64)
-        hipLaunchKernelGGL((k_level_flow<64, 1024, 256, 512, 32, 8, M>), dim3(fa.nitems), dim3(64), 0, st, P, D, level,
+        hipLaunchKernelGGL((k_level_flow<64, 1024, 256, 512, 32, 8, M, V>), dim3(fa.nitems), dim3(64), 0, st, P, D, level,
                            sweep, items, fa);
     else if (variant == V256)
-        hipLaunchKernelGGL((k_level_flow<256, 4096, 1024, 1024, 512, 12, M>), dim3(fa.nitems), dim3(256), 0, st, P, D,
+        hipLaunchKernelGGL((k_level_flow<256, 4096, 1024, 1024, 512, 12, M, V>), dim3(fa.nitems), dim3(256), 0, st, P, D,
                            level, sweep, items, fa);
     else
-        hipLaunchKernelGGL((k_level_flow<512, 8192, 4096, 4096, 128, 18, M>), dim3(fa.nitems), dim3(512), 0, st, P, D,
+        hipLaunchKernelGGL((k_level_flow<512, 8192, 4096, 4096, 128, 18, M, V>), dim3(fa.nitems), dim3(512), 0, st, P, D,
                            level, sweep, items, fa);
 }
 
 void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
                        const int32_t* items, const FlowArgs& fa, hipStream_t st) {
-    if (P.precision == WMC_MIXED)
-        launch_level_flow_t<true>(variant, P, D, level, sweep, items, fa, st);
-    else
-        launch_level_flow_t<false>(variant, P, D, level, sweep, items, fa, st);
+    const bool v = uses_variants(P);
+    if (P.precision == WMC_MIXED) {
+        if (v) launch_level_flow_t<true, true>(variant, P, D, level, sweep, items, fa, st);
+        else launch_level_flow_t<true, false>(variant, P, D, level, sweep, items, fa, st);
+    } else {
+        if (v) launch_level_flow_t<false, true>(variant, P, D, level, sweep, items, fa, st);
+        else launch_level_flow_t<false, false>(variant, P, D, level, sweep, items, fa, st);
+    }
 }
 
 // ------------------------------------------------- cell phase of a large level, grid-wide
@@ -2048,7 +2189,7 @@ __device__ __forceinline__ double coop_max(const double* part, int G, CoopShared
 
 // one cell of colour `colour` for the group `grp` (index gi); gen is the group's barrier
 // generation and Dg its system's drift bound, both carried from colour to colour
-template <bool MIXED>
+template <bool MIXED, bool VAR>
 __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
                           const CoopGroup grp, int gi, int rank, CoopShared& sh, unsigned& gen, double& Dg) {
     const int sys = grp.sys;
@@ -2062,6 +2203,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
     int64_t ic[3];
     cell_coords(P, lv, g, colour, grp.local, ic);
     const int64_t cell = ic[0] + g.n[0] * (ic[1] + g.n[1] * ic[2]);
+    const int64_t key = cell_key(g, ic);
     const double hi2 = lv.hi * lv.hi;
     const double L = s.L;
     int32_t* Sg = D.slot_S + (lv.slot_base + grp.local) * D.slot_len;
@@ -2103,11 +2245,12 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
     auto Sat = [&](int64_t i) -> int32_t { return lv.identity ? (int32_t)(s.b0 + i) : Sg[i]; };
 
     // ---- 2. number of trials (every workgroup draws the same)
-    double mu = (lv.T * (double)nS) / (double)s.N;
+    const bool uni = VAR && P.centring == WMC_CENTRE_UNIFORM;
+    double mu = uni ? lv.T / ((double)g.n[0] * (double)g.n[1] * (double)g.n[2]) : (lv.T * (double)nS) / (double)s.N;
     int64_t K = (int64_t)floor(mu);
     {
         Stream ms;
-        ms.init(P, sys, sweep, TAG_META + level, cell, 0, 0, 0);
+        ms.init(P, sys, sweep, TAG_META + level, key, 0, 0, 0);
         if (ms.co() < mu - (double)K) K += 1;
     }
     if (K > 0xFFFFF) K = 0xFFFFF;
@@ -2118,6 +2261,12 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
     const int qS = (nS + G - 1) / G;
     const int slo = wg * qS, shi = min(nS, slo + qS);
 
+    auto pos_of = [&](int32_t j, double& px, double& py, double& pz) {
+        px = D.x[j];
+        py = D.y[j];
+        pz = D.z[j];
+    };
+
     // ---- 3. trials and chains
     for (int64_t t0 = 0; t0 < K;) {
         const int64_t t = t0 + tid;
@@ -2125,16 +2274,10 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
         double lam = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
         int32_t a = 0;
         Stream st;
-        if (t < K && nS > 0) {
-            st.init(P, sys, sweep, level, cell, t, 0, 0);
+        if (t < K && (nS > 0 || uni)) {
+            st.init(P, sys, sweep, level, key, t, 0, 0);
             lam = draw_lambda(st.co(), lv.lo, lv.hi);
-            a = Sat(st.index(nS));
-            double vx, vy, vz;
-            ball(st, vx, vy, vz);
-            bx = D.x[a] + lam * vx;
-            by = D.y[a] + lam * vy;
-            bz = D.z[a] + lam * vz;
-            hit = cell_of_point(g, bx, by, bz) == cell;
+            hit = draw_trial_centre<VAR>(P, st, g, ic, cell, lam, nS, Sat, pos_of, a, bx, by, bz);
         }
         const int first = block_min_int<CW>(hit ? (int)(t - t0) : 0x7FFFFFFF, sh.redi);
         if (first == 0x7FFFFFFF) {
@@ -2160,7 +2303,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
         const double lam2 = lam * lam;
         for (int r = 0;;) {
             Stream cs;
-            cs.init(P, sys, sweep, level, cell, tc, r, jtry);
+            cs.init(P, sys, sweep, level, key, tc, r, jtry);
             cs.next = nxt;
             double px, py, pz;
             direction(cs, px, py, pz);
@@ -2187,20 +2330,23 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
             group_barrier(bar, G, gen);  // 1: member counts
             int off, n;
             coop_prefix(ccnt, G, wg, sh, off, n);
-            const double A = P.A0 * lam / sqrt((double)n);
+            WaveDesc wv;
+            wv.b[0] = b[0];
+            wv.b[1] = b[1];
+            wv.b[2] = b[2];
+            wv.p[0] = px;
+            wv.p[1] = py;
+            wv.p[2] = pz;
+            wv.lam = lam;
+            wv.A = wavelet_amp<VAR>(P, s, lam, n);
+            wv.rot = VAR && P.wavelet_map == WMC_MAP_ROTATION;
             double dmax_l = 0.0;
             for (int i = tid; i < cnt; i += CW) {
                 const int k = off + i;
                 const int32_t j = sh.L[i];
                 const double xj = D.x[j], yj = D.y[j], zj = D.z[j];
-                const double xr0 = minimg(g, xj - b[0]) / lam;
-                const double xr1 = minimg(g, yj - b[1]) / lam;
-                const double xr2 = minimg(g, zj - b[2]) / lam;
-                const double rr = sqrt((xr0 * xr0 + xr1 * xr1) + xr2 * xr2);
-                const double f = rr < 1.0 ? A * (1.0 - rr) : 0.0;
-                const double w0 = f * (py * xr2 - pz * xr1);
-                const double w1 = f * (pz * xr0 - px * xr2);
-                const double w2 = f * (px * xr1 - py * xr0);
+                double w0, w1, w2;
+                wavelet_disp(g, wv, xj, yj, zj, w0, w1, w2);
                 Mg[k] = j;
                 MXg[k] = xj + w0;
                 MYg[k] = yj + w1;
@@ -2215,7 +2361,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
             group_barrier(bar, G, gen);  // 2: members, trial positions, tags
             const double dmax = coop_max(c_dmax, G, sh);
             const double Rq = P.rc + 2.0 * dmax + fmax(Dg, dloc) + 1e-9 * L;
-            const double thr = -P.kT * log(u_acc);
+            const double thr = accept_threshold<VAR>(P, u_acc);
             double dU;
             {
                 double acc = 0.0, sens = 0.0;
@@ -2243,7 +2389,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                 }
             }
             const bool accept = dU <= thr;
-            if (wg == 0 && tid == 0) trace_push(D, 0, sys, sweep, level, cell, tc, r, n, accept ? 1 : 0, a, dU, thr);
+            if (wg == 0 && tid == 0) trace_push(D, 0, sys, sweep, level, key, tc, r, n, accept ? 1 : 0, a, dU, thr);
             ++c_att;
             c_beads += n;
             double dl = 0.0;
@@ -2282,14 +2428,8 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                 int32_t a2 = 0;
                 Stream rs;
                 if (jj < 4096) {
-                    rs.init(P, sys, sweep, level, cell, tc, r, jj);
-                    a2 = Sat(rs.index(nS));
-                    double vx, vy, vz;
-                    ball(rs, vx, vy, vz);
-                    ex = D.x[a2] + lam * vx;
-                    ey = D.y[a2] + lam * vy;
-                    ez = D.z[a2] + lam * vz;
-                    h2 = cell_of_point(g, ex, ey, ez) == cell;
+                    rs.init(P, sys, sweep, level, key, tc, r, jj);
+                    h2 = draw_trial_centre<VAR>(P, rs, g, ic, cell, lam, nS, Sat, pos_of, a2, ex, ey, ez);
                 }
                 const int fj = block_min_int<CW>(h2 ? jj : 0x7FFFFFFF, sh.redi);
                 if (fj != 0x7FFFFFFF) {
@@ -2342,13 +2482,13 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
             atomicAdd(&D.sys_acc[sys], c_acc_n);
         }
         if (dloc > 0.0) atomic_max_double(&D.drift[sys], dloc);
-        trace_push(D, 1, sys, sweep, level, cell, K, nS, 0, (int)c_hits, 0, 0.0, 0.0);
+        trace_push(D, 1, sys, sweep, level, key, K, nS, 0, (int)c_hits, 0, 0.0, 0.0);
     }
     // the next colour's bound: what the drift slot holds once this cell has published
     Dg = fmax(Dg, dloc);
 }
 
-template <bool MIXED>
+template <bool MIXED, bool VAR>
 __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int level, CoopColours cc, int64_t sweep,
                                                   const CoopGroup* groups, const int32_t* wg_group) {
     __shared__ CoopShared sh;
@@ -2360,7 +2500,7 @@ __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int le
     double Dg = __longlong_as_double((long long)D.drift[sys]);
     for (int i = 0; i < cc.n; ++i) {
         const CoopGroup* gt = (const CoopGroup*)((const int32_t*)groups + cc.goff[i]);
-        coop_cell<MIXED>(P, D, level, cc.col[i], sweep, gt[gi], gi, rank, sh, gen, Dg);
+        coop_cell<MIXED, VAR>(P, D, level, cc.col[i], sweep, gt[gi], gi, rank, sh, gen, Dg);
     }
 }
 
@@ -2370,14 +2510,18 @@ int cell_coop_blocks() {
         int dev = 0, per_cu = 0;
         hipDeviceProp_t prop;
         int per_cu64 = 0;
-        // the smaller occupancy of the two precision variants, so either launch is co-resident
+        // the smallest occupancy of the instances (precision, variants), so any launch is co-resident
+        int per_v = 0, per_v64 = 0;
         if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cell_coop<true>, CW, 0) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_cell_coop<false>, CW, 0) != hipSuccess ||
-            std::min(per_cu, per_cu64) < 1)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cell_coop<true, false>, CW, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_cell_coop<false, false>, CW, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_v, k_cell_coop<true, true>, CW, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_v64, k_cell_coop<false, true>, CW, 0) != hipSuccess ||
+            std::min(std::min(per_cu, per_cu64), std::min(per_v, per_v64)) < 1)
             nb = 0;
         else
-            nb = std::min(std::min(per_cu, per_cu64) * prop.multiProcessorCount, COOP_SLOTS);
+            nb = std::min(std::min(std::min(per_cu, per_cu64), std::min(per_v, per_v64)) * prop.multiProcessorCount,
+                          COOP_SLOTS);
     }
     return nb;
 }
@@ -2393,7 +2537,9 @@ bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, const Coo
     const CoopGroup* gp = groups;
     const int32_t* wp = wg_group;
     void* args[] = {&Pc, &Dc, &lv, &ccc, &sw, &gp, &wp};
-    const void* k = P.precision == WMC_MIXED ? (const void*)k_cell_coop<true> : (const void*)k_cell_coop<false>;
+    const bool v = uses_variants(P);
+    const void* k = P.precision == WMC_MIXED ? (v ? (const void*)k_cell_coop<true, true> : (const void*)k_cell_coop<true, false>)
+                                             : (v ? (const void*)k_cell_coop<false, true> : (const void*)k_cell_coop<false, false>);
     return hipLaunchCooperativeKernel(k, dim3(nwg), dim3(CW), args, 0, st) == hipSuccess;
 }
 
@@ -2445,6 +2591,23 @@ __device__ void sample_k(const DevParams& P, const SysDesc& s, const DevPtrs& D,
     }
 }
 
+// Infinite system (App. D "Choosing k for an infinite system"): x = |k| lambda_max from its tail
+// probability v in (0, 1], interpolated in the table s = x v at t = i/M, v = 1 - t^3
+__device__ __forceinline__ double inf_x_of_v(const SysDesc& s, const DevPtrs& D, double v) {
+    const double* tab = D.shell_s + s.shell_off;
+    const double t = cbrt(1.0 - v), u = t * (double)s.n_shell;
+    int i = (int)floor(u);
+    if (i >= s.n_shell) i = s.n_shell - 1;
+    const double fr = u - (double)i;
+    return (tab[i] + fr * (tab[i + 1] - tab[i])) / v;
+}
+
+// |k| shell of a plane wave for the acceptance counters: floor(|l|) (periodic) or floor(x)
+__device__ __forceinline__ int k_shell_periodic(const int l[3]) {
+    const double lm = sqrt(((double)l[0] * (double)l[0] + (double)l[1] * (double)l[1]) + (double)l[2] * (double)l[2]);
+    return lm < (double)(WMC_K_SHELLS - 1) ? (int)lm : WMC_K_SHELLS - 1;
+}
+
 __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t sweep) {
     __shared__ double red[16];
     const int sys = blockIdx.x;
@@ -2465,22 +2628,43 @@ __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t swe
     for (int64_t h = 0; h < HF; ++h) {
         Stream st;
         st.init(P, sys, sweep, TAG_PW, 0, h, 0, 0);
-        int l[3];
-        sample_k(P, s, D, st, l);
+        // periodic: a lattice mode l; infinite: x = |k| lambda_max and an isotropic direction
+        int l[3] = {0, 0, 0};
+        double xk = 0.0, khat[3] = {0.0, 0.0, 0.0};
+        if (P.periodic) {
+            sample_k(P, s, D, st, l);
+        } else {
+            xk = inf_x_of_v(s, D, st.oc());
+            direction(st, khat[0], khat[1], khat[2]);
+        }
         for (int r = 0;;) {
             const double Phi = 2.0 * kPi * st.co();
             const double psi = 2.0 * kPi * st.co();
             const double u_acc = st.oc();
-            const double thr = -P.kT * log(u_acc);
-            if (l[0] == 0 && l[1] == 0 && l[2] == 0) {
+            const double thr = accept_threshold<true>(P, u_acc);
+            const bool zero = P.periodic ? (l[0] == 0 && l[1] == 0 && l[2] == 0) : xk == 0.0;
+            if (zero) {
+                // k = 0: no displacement, deemed accepted (Sec. V "Choosing plane wave amplitude")
                 ++c_k0;
                 ++c_acc;
                 if (tid == 0)
-                    trace_push(D, 2, sys, sweep, -1, h, 0, r, 0, 1, (int)((512u << 20) | (512u << 10) | 512u), 0.0,
-                               thr);
+                    trace_push(D, 2, sys, sweep, -1, h, 0, r, 0, 1,
+                               P.periodic ? (int)((512u << 20) | (512u << 10) | 512u) : 0, 0.0, thr);
                 break;
             }
-            double k[3] = {s.ks * (double)l[0], s.ks * (double)l[1], s.ks * (double)l[2]};
+            double k[3];
+            int shell, extra;
+            if (P.periodic) {
+                for (int q = 0; q < 3; ++q) k[q] = s.ks * (double)l[q];
+                shell = k_shell_periodic(l);
+                extra = (int)((((uint32_t)(l[0] + 512) & 0x3FFu) << 20) | (((uint32_t)(l[1] + 512) & 0x3FFu) << 10) |
+                              ((uint32_t)(l[2] + 512) & 0x3FFu));
+            } else {
+                const double km = xk / s.lmax;
+                for (int q = 0; q < 3; ++q) k[q] = km * khat[q];
+                shell = xk < (double)(WMC_K_SHELLS - 1) ? (int)xk : WMC_K_SHELLS - 1;
+                extra = shell;
+            }
             double kmag = sqrt((k[0] * k[0] + k[1] * k[1]) + k[2] * k[2]);
             double kh[3] = {k[0] / kmag, k[1] / kmag, k[2] / kmag};
             int ax = 0;
@@ -2514,7 +2698,14 @@ __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t swe
                     double r2n = pair_r2(P, invL, L, NX[j], NY[j], NZ[j], NX[j + 1], NY[j + 1], NZ[j + 1]);
                     acc += u_bond_delta(P, r2n, r2o);
                 }
-                if (P.wca) {
+                if (P.wca && !P.periodic) {
+                    // infinite system (at most 8192 beads): every later bead
+                    for (int64_t m = j + 1; m < s.b1; ++m) {
+                        double r2o = pair_r2(P, invL, L, jx, jy, jz, D.x[m], D.y[m], D.z[m]);
+                        double r2n = pair_r2(P, invL, L, NX[j], NY[j], NZ[j], NX[m], NY[m], NZ[m]);
+                        if (r2o < P.rc2 || r2n < P.rc2) acc += u_pair(P, r2n) - u_pair(P, r2o);
+                    }
+                } else if (P.wca) {
                     double cx = wrap01(jx, L, invL), cy = wrap01(jy, L, invL), cz = wrap01(jz, L, invL);
                     int f0[3], cn[3];
                     fine_range(cx - R, cx + R, s.invg, s.nf, f0[0], cn[0]);
@@ -2548,9 +2739,9 @@ __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t swe
             ++c_att;
             c_beads += s.N;
             if (tid == 0) {
-                int extra = (int)((((uint32_t)(l[0] + 512) & 0x3FFu) << 20) | (((uint32_t)(l[1] + 512) & 0x3FFu) << 10) |
-                                  ((uint32_t)(l[2] + 512) & 0x3FFu));
                 trace_push(D, 2, sys, sweep, -1, h, 0, r, s.N, accept ? 1 : 0, extra, dU, thr);
+                atomicAdd(&D.cnt[CNT_SHELL + 2 * shell], 1ull);
+                if (accept) atomicAdd(&D.cnt[CNT_SHELL + 2 * shell + 1], 1ull);
             }
             if (accept) {
                 for (int64_t j = s.b0 + tid; j < s.b1; j += 1024) {
@@ -2569,11 +2760,16 @@ __global__ __launch_bounds__(1024) void k_pw(DevParams P, DevPtrs D, int64_t swe
                 ++c_caps;
                 break;
             }
+            // recycling (App. D): |k| kept; periodic permutes and sign-flips l, infinite redraws k-hat
             st.init(P, sys, sweep, TAG_PW, 0, h, r, 0);
-            int pi = (int)st.index(6);
-            static const int PERM[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-            int nl[3] = {l[PERM[pi][0]], l[PERM[pi][1]], l[PERM[pi][2]]};
-            for (int q = 0; q < 3; ++q) l[q] = st.co() < 0.5 ? -nl[q] : nl[q];
+            if (P.periodic) {
+                int pi = (int)st.index(6);
+                static const int PERM[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+                int nl[3] = {l[PERM[pi][0]], l[PERM[pi][1]], l[PERM[pi][2]]};
+                for (int q = 0; q < 3; ++q) l[q] = st.co() < 0.5 ? -nl[q] : nl[q];
+            } else {
+                direction(st, khat[0], khat[1], khat[2]);
+            }
         }
     }
     if (tid == 0) {
@@ -2636,7 +2832,7 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
             const double Phi = 2.0 * kPi * st.co();
             const double psi = 2.0 * kPi * st.co();
             const double u_acc = st.oc();
-            const double thr = -P.kT * log(u_acc);
+            const double thr = accept_threshold<true>(P, u_acc);
             if (l[0] == 0 && l[1] == 0 && l[2] == 0) {
                 ++c_k0;
                 ++c_acc;
@@ -2722,6 +2918,9 @@ __global__ __launch_bounds__(256) void k_pw_coop(DevParams P, DevPtrs D, int64_t
                 int extra = (int)((((uint32_t)(l[0] + 512) & 0x3FFu) << 20) | (((uint32_t)(l[1] + 512) & 0x3FFu) << 10) |
                                   ((uint32_t)(l[2] + 512) & 0x3FFu));
                 trace_push(D, 2, sys, sweep, -1, h, 0, r, s.N, accept ? 1 : 0, extra, dU, thr);
+                const int shell = k_shell_periodic(l);
+                atomicAdd(&D.cnt[CNT_SHELL + 2 * shell], 1ull);
+                if (accept) atomicAdd(&D.cnt[CNT_SHELL + 2 * shell + 1], 1ull);
             }
             if (accept) {
                 for (int64_t j = g0; j < s.b1; j += stride) {
@@ -2847,6 +3046,39 @@ void* static_arena(int device, hipError_t* err) {
         ptr[device] = p;
     }
     return ptr[device];
+}
+
+// centre of mass of every chain (Sec. VI.B); mode 0 writes it to out [3 n], mode 1 to D.com_ref, mode
+// 2 writes |com - com_ref|^2 to out [n]
+__global__ void k_com(DevPtrs D, const int64_t* chain_off, int64_t n_chains, int mode, double* out) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chains) return;
+    int64_t a = chain_off[c], b = chain_off[c + 1];
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    for (int64_t i = a; i < b; ++i) {
+        cx += D.x[i];
+        cy += D.y[i];
+        cz += D.z[i];
+    }
+    const double nb = (double)(b - a);
+    cx /= nb;
+    cy /= nb;
+    cz /= nb;
+    if (mode == 2) {
+        const double dx = cx - D.com_ref[3 * c], dy = cy - D.com_ref[3 * c + 1], dz = cz - D.com_ref[3 * c + 2];
+        out[c] = (dx * dx + dy * dy) + dz * dz;
+        return;
+    }
+    double* o = mode == 1 ? D.com_ref : out;
+    o[3 * c] = cx;
+    o[3 * c + 1] = cy;
+    o[3 * c + 2] = cz;
+}
+
+void launch_com(const DevPtrs& D, const int64_t* chain_off, int64_t n_chains, int mode, double* out, hipStream_t st) {
+    if (n_chains <= 0) return;
+    hipLaunchKernelGGL(k_com, dim3((unsigned)((n_chains + 255) / 256)), dim3(256), 0, st, D, chain_off, n_chains, mode,
+                       out);
 }
 
 // ------------------------------------------------------------------- debug kernels

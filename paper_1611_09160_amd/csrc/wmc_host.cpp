@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <mutex>
 #include <string>
@@ -219,6 +220,32 @@ PWTables build_pw(double L, double lmax, int NL) {
     return t;
 }
 
+// Infinite system (Sec. V "Distributions of wavevectors"): P(k) = N_k k^2 I(k lmax) with
+// N_k = 3 lmax^3/M6, so x = k lmax has the tail probability v = G(x)/G(0). Its inverse is tabulated
+// as s = x v at t = i/M with v = 1 - t^3 (s is smooth at both ends; s -> 2 pi^2/G(0) as v -> 0),
+// each point solved by bisection on G.
+PWTables build_inf_table() {
+    const Quad& Q = quad();
+    PWTables t;
+    const int M = 4096;
+    const double G0 = Q.G(0.0);
+    t.shell.assign(M + 1, 0.0);
+    double x = 0.0;
+    for (int i = 1; i < M; ++i) {
+        const double ti = (double)i / M, v = 1.0 - ti * ti * ti, want = v * G0;
+        double lo = x, hi = x + 0.5;
+        while (Q.G(hi) > want) hi *= 2.0;
+        for (int it = 0; it < 80; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (Q.G(mid) > want) lo = mid; else hi = mid;
+        }
+        x = 0.5 * (lo + hi);
+        t.shell[i] = x * v;
+    }
+    t.shell[M] = 2.0 * kPi * kPi / G0;
+    return t;
+}
+
 #define HIPCHK(c, expr)                                                                  \
     do {                                                                                 \
         hipError_t e_ = (expr);                                                          \
@@ -241,7 +268,8 @@ struct Layout {
 struct Plan {
     int64_t N = 0, total_fine = 0, slots = 0, slot_len = 0, pool_cube = 0, pool_shell = 0, n_chains = 0, bmap = 0, coop_ints = 0, flags = 0;
     int nsys = 0, total_levels = 0;
-    size_t off_x, off_xb, off_bond, off_sysid, off_tag, off_fcount, off_fstart, off_fidx, off_fcell, off_drift,
+    size_t off_x, off_xb, off_bond, off_sysid, off_tag, off_fcount, off_fstart, off_fidx, off_fcell, off_drift, off_driftcol,
+        off_celldrift, off_comref,
         off_cnt, off_sysacc, off_fblock, off_gbar, off_coop, off_cooptab, off_flags, off_flowctr, off_trace, off_tracen, off_cube, off_shell, off_slotS, off_slotM, off_slotMX, off_pw,
         off_igrid, off_sys, off_lev, off_bmap, off_choff, off_rg2;
     size_t bytes = 0;
@@ -265,7 +293,11 @@ static int validate(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int64_t
     if (p->bond_type == WMC_BOND_HARMONIC && !(p->r_int_harmonic > 0.0)) return fail("harmonic bonds need r_int_harmonic > 0");
     if (p->wca && !(p->sigma > 0.0)) return fail("WCA needs sigma > 0");
     if (p->retry_cap < 1 || p->retry_cap > 255) return fail("retry_cap must be in 1..255");
-    if (p->plane_waves && (p->n_layers < 1 || p->n_layers > 60)) return fail("n_layers must be in 1..60");
+    if (p->plane_waves && p->periodic && (p->n_layers < 1 || p->n_layers > 60)) return fail("n_layers must be in 1..60");
+    if (p->accept_rule < 0 || p->accept_rule > 1) return fail("bad accept_rule");
+    if (p->wavelet_map < 0 || p->wavelet_map > 1) return fail("bad wavelet_map");
+    if (p->centring < 0 || p->centring > 1) return fail("bad centring");
+    if (p->centring == WMC_CENTRE_UNIFORM && !p->periodic) return fail("uniform centres need a periodic box");
     if (!p->periodic && nsys != 1) return fail("an infinite system runs as a single system");
     if (so[0] != 0) return fail("sys_bead_offset[0] must be 0");
     for (int s = 0; s < nsys; ++s) {
@@ -353,12 +385,21 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
             }
             d.ks = 2.0 * kPi / d.L;
             d.invks = d.L / (2.0 * kPi);
+        } else if (p->plane_waves) {
+            // infinite system: one table, P_F = (lambda_min/lambda_max)^3 (Eq. "P(Fourier) infinite")
+            if (pw_pool && pw_pool->empty()) pw_pool->push_back(build_inf_table());
+            const double q = p->lambda_min / d.lmax;
+            PF = q * q * q;
+            d.n_shell = 4096;
+            d.shell_off = 0;
+            shell_pool = std::max<int64_t>(shell_pool, 4097);
+            if (c) c->pw_out.push_back({PF, 1.0, 3.0 * d.lmax * d.lmax * d.lmax / M6(), 0.0, 0.0, 0.0});
         } else if (c) {
             c->pw_out.push_back({0.0, 0.0, 0.0, 0.0, 0.0, 0.0});
         }
         d.PF = PF;
         double dt = 6.0 * p->A0 * p->A0 * M4() * lam_a * lam_a / (8.0 * kPi * kPi * kPi * (double)d.N);
-        if (!(p->periodic && p->plane_waves)) {
+        if (!p->plane_waves) {
             double q = p->lambda_min / d.lmax;
             dt *= (1.0 - q) / (1.0 - q * q * q);
         }
@@ -491,6 +532,7 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
     pl.off_fcell = lay.add(N * 4);
     pl.off_fblock = lay.add((fine / 4096 + 2) * 4);
     pl.off_drift = lay.add(nsys * 8);
+    pl.off_driftcol = lay.add(8 * nsys * 8);
     pl.off_cnt = lay.add(CNT_TOTAL * 8);
     pl.off_sysacc = lay.add(nsys * 8);
     pl.off_trace = lay.add(std::max<int64_t>(trace_cap, 0) * sizeof(wmc_trace_rec));
@@ -500,18 +542,20 @@ static int plan_systems(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int
     pl.off_slotS = lay.add(slots * slot_len * 4);
     pl.off_slotM = lay.add(slots * slot_len * 4);
     pl.off_slotMX = lay.add(slots * slot_len * 3 * 8);
-    pl.off_pw = lay.add((p->periodic && p->plane_waves) ? 3 * N * 8 : 8);
-    pl.off_igrid = lay.add(8 * 8);
+    pl.off_pw = lay.add(p->plane_waves ? 3 * N * 8 : 8);
+    pl.off_igrid = lay.add(16 * 8);
     pl.off_gbar = lay.add(2 * (1 + COOP_SLOTS) * 4);
     pl.off_coop = lay.add(COOP_SLOTS * 4 + 5 * COOP_SLOTS * 8);
     pl.off_cooptab = lay.add(pl.coop_ints * 4);
     pl.off_flags = lay.add(std::max<int64_t>(pl.flags, 1) * 4);
+    pl.off_celldrift = lay.add(std::max<int64_t>(pl.flags, 1) * 8);
     pl.off_flowctr = lay.add(WMC_MAX_LEVELS * 8);
     pl.off_sys = lay.add(nsys * sizeof(SysDesc));
     pl.off_lev = lay.add(lev.size() * sizeof(LevelDesc));
     pl.off_bmap = lay.add(std::max<int64_t>(bm, 1) * 3 * 2 * 4);
     pl.off_choff = lay.add((n_chains + 1) * 8);
-    pl.off_rg2 = lay.add(std::max<int64_t>(n_chains, 1) * 8);
+    pl.off_rg2 = lay.add(std::max<int64_t>(n_chains, 1) * 3 * 8);
+    pl.off_comref = lay.add(std::max<int64_t>(n_chains, 1) * 3 * 8);
     pl.bytes = lay.total + 256;
     if (sys_out) *sys_out = sys;
     if (lev_out) *lev_out = lev;
@@ -713,16 +757,26 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     std::vector<int> pidx;
     rc = plan_systems(c, p, nsys, so, sL, sl, n_chains, trace_cap, pl, &c->sys, &c->lev, &pool, &pidx);
     if (rc) return rc;
-    if (!arena || arena_bytes < pl.bytes) {
-        c->err = "device arena missing or smaller than wmc_arena_bytes";
-        return WMC_EARENA;
-    }
-    char* base = (char*)(((uintptr_t)arena + 255) & ~(uintptr_t)255);
-    c->arena = base;
-    c->arena_bytes = arena_bytes;
-    hipStream_t st = (hipStream_t)stream;
     const int64_t N = c->N;
-    // host-side checks of the initial state: bonds finite
+    // host-side checks of the initial state (before any device work): finite energy needs every
+    // FENE bond shorter than R0 (Eq. "FENE potential") and, with WCA, no two beads of a system at the
+    // same point (Eq. "WCA potential" diverges at r = 0)
+    if (p->wca) {
+        for (int s = 0; s < nsys; ++s) {
+            std::vector<std::array<double, 3>> w((size_t)(so[s + 1] - so[s]));
+            for (int64_t i = so[s]; i < so[s + 1]; ++i)
+                for (int a = 0; a < 3; ++a) {
+                    double v = pos[3 * i + a];
+                    if (p->periodic) v -= c->sys[s].L * floor(v * c->sys[s].invL);
+                    w[(size_t)(i - so[s])][a] = v;
+                }
+            std::sort(w.begin(), w.end());
+            if (std::adjacent_find(w.begin(), w.end()) != w.end()) {
+                c->err = "two beads of one system at the same point (infinite WCA energy)";
+                return WMC_ESTATE;
+            }
+        }
+    }
     std::vector<uint8_t> bond(N, 0);
     for (int64_t ch = 0; ch < n_chains; ++ch)
         for (int64_t i = co[ch]; i + 1 < co[ch + 1]; ++i) bond[i] = 1;
@@ -739,12 +793,23 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
                 return WMC_ESTATE;
             }
         }
+    if (!arena || arena_bytes < pl.bytes) {
+        c->err = "device arena missing or smaller than wmc_arena_bytes";
+        return WMC_EARENA;
+    }
+    char* base = (char*)(((uintptr_t)arena + 255) & ~(uintptr_t)255);
+    c->arena = base;
+    c->arena_bytes = arena_bytes;
+    hipStream_t st = (hipStream_t)stream;
     // device parameters
     DevParams& P = c->P;
     memset(&P, 0, sizeof(P));
     P.periodic = p->periodic;
-    P.plane_waves = p->periodic ? p->plane_waves : 0;
+    P.plane_waves = p->plane_waves;
     P.wavelets = p->wavelets;
+    P.accept_rule = p->accept_rule;
+    P.wavelet_map = p->wavelet_map;
+    P.centring = p->centring;
     P.precision = p->precision;
     P.bond_type = p->bond_type;
     P.wca = p->wca;
@@ -781,6 +846,9 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     D.fcell = (int32_t*)(base + pl.off_fcell);
     D.fblock = (int32_t*)(base + pl.off_fblock);
     D.drift = (unsigned long long*)(base + pl.off_drift);
+    D.drift_col = (unsigned long long*)(base + pl.off_driftcol);
+    D.cell_drift = (double*)(base + pl.off_celldrift);
+    D.com_ref = (double*)(base + pl.off_comref);
     D.cnt = (unsigned long long*)(base + pl.off_cnt);
     D.sys_acc = (unsigned long long*)(base + pl.off_sysacc);
     D.trace = trace_cap > 0 ? (wmc_trace_rec*)(base + pl.off_trace) : nullptr;
@@ -913,6 +981,8 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     if (!c->coop_host.empty())
         HIPCHK(c, hipMemcpyAsync(c->coop_dev, c->coop_host.data(), c->coop_host.size() * 4, hipMemcpyHostToDevice, st));
     HIPCHK(c, hipMemcpyAsync(c->chain_off_dev, co, (n_chains + 1) * 8, hipMemcpyHostToDevice, st));
+    launch_com(D, c->chain_off_dev, n_chains, 1, nullptr, st);  // reference centres of mass
+    HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     return 0;
 }
@@ -1087,7 +1157,11 @@ extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
                 }
             }
         }
-        if (c->P.periodic && c->P.plane_waves) {
+        if (!c->P.periodic && c->P.plane_waves) {
+            // infinite system: one workgroup, every pair of beads (no neighbour grid)
+            Timed t(c, 17, st);
+            launch_pw(c->P, c->D, sw, c->nsys, st);
+        } else if (c->P.plane_waves) {
             {
                 Timed t(c, 0, st);
                 launch_fine_build(c->P, c->D, c->N, st);
@@ -1154,6 +1228,8 @@ extern "C" int wmc_set_state(wmc_ctx* c, const double* pos, int64_t sweep, void*
     for (int64_t i = 0; i < N; ++i)
         for (int a = 0; a < 3; ++a) soa[a * N + i] = pos[3 * i + a];
     HIPCHK(c, hipMemcpyAsync(c->D.x, soa.data(), 3 * N * 8, hipMemcpyHostToDevice, st));
+    launch_com(c->D, c->chain_off_dev, c->n_chains, 1, nullptr, st);  // new reference centres of mass
+    HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     c->sweep = sweep;
     return 0;
@@ -1191,6 +1267,18 @@ extern "C" int wmc_observables(wmc_ctx* c, wmc_obs* o) {
     o->wait_timeouts = cnt[CNT_FLOWWAIT];
     o->fallback_cells = cnt[CNT_FALLBACK];
     o->accepted_bead_updates = cnt[CNT_ACC_BEADS];
+    for (int k = 0; k < WMC_K_SHELLS; ++k) {
+        o->pw_shell_attempts[k] = cnt[CNT_SHELL + 2 * k];
+        o->pw_shell_accepts[k] = cnt[CNT_SHELL + 2 * k + 1];
+    }
+    if (o->overflows > 0) {
+        c->err = "a cell list overflowed its capacity: the sweeps since wmc_init are not valid samples";
+        return WMC_ECAPACITY;
+    }
+    if (o->wait_timeouts > 0) {
+        c->err = "a dependency wait between cells hit its bound: the sweeps since wmc_init are not valid samples";
+        return WMC_ESCHEDULE;
+    }
     return 0;
 }
 
@@ -1207,6 +1295,22 @@ extern "C" int wmc_chain_rg2(wmc_ctx* c, double* out) {
     if (!c || !out) return WMC_EINVAL;
     HIPCHK(c, hipDeviceSynchronize());
     launch_rg2(c->D, c->chain_off_dev, c->n_chains, c->rg2_dev, nullptr);
+    HIPCHK(c, hipMemcpy(out, c->rg2_dev, c->n_chains * 8, hipMemcpyDeviceToHost));
+    return 0;
+}
+
+extern "C" int wmc_chain_com(wmc_ctx* c, double* out) {
+    if (!c || !out) return WMC_EINVAL;
+    HIPCHK(c, hipDeviceSynchronize());
+    launch_com(c->D, c->chain_off_dev, c->n_chains, 0, c->rg2_dev, nullptr);
+    HIPCHK(c, hipMemcpy(out, c->rg2_dev, c->n_chains * 3 * 8, hipMemcpyDeviceToHost));
+    return 0;
+}
+
+extern "C" int wmc_chain_msd(wmc_ctx* c, double* out) {
+    if (!c || !out) return WMC_EINVAL;
+    HIPCHK(c, hipDeviceSynchronize());
+    launch_com(c->D, c->chain_off_dev, c->n_chains, 2, c->rg2_dev, nullptr);
     HIPCHK(c, hipMemcpy(out, c->rg2_dev, c->n_chains * 8, hipMemcpyDeviceToHost));
     return 0;
 }

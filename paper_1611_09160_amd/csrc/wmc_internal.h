@@ -25,7 +25,8 @@ constexpr int CNT_ACCEPTED = 140;
 constexpr int CNT_FLOWWAIT = 141;   // dependency waits that hit their spin limit (must be 0)
 constexpr int CNT_ACC_BEADS = 143;  // beads displaced by accepted moves, wavelet and plane wave
 constexpr int CNT_FALLBACK = 142;   // LDS-tile cells whose halo did not fit: run on the global-list path
-constexpr int CNT_TOTAL = 160;
+constexpr int CNT_SHELL = 144;      // [2 * shell + accepted]: plane-wave tests per |k| shell
+constexpr int CNT_TOTAL = 176;
 
 // Cooperative launches: groups of co-resident workgroups, each group on one (system, cell) of a
 // colour phase or on one system's plane waves. A group owns workgroups [first, first + size)
@@ -76,7 +77,7 @@ struct SysDesc {
     // plane waves
     double PF, P_cube, W_cube, x_s, ks, invks;
     int64_t cube_off;      // offset of this system's cube CDF in the table pool
-    int64_t shell_off;     // offset of its shell table
+    int64_t shell_off;     // offset of its shell table (periodic) or of the infinite-system table
     int32_t n_modes, n_shell;
     // neighbour grid
     int32_t nf, pad0;
@@ -98,6 +99,7 @@ struct LevelDesc {
 struct DevParams {
     int32_t periodic, plane_waves, wavelets, precision;
     int32_t bond_type, wca, retry_cap, n_layers;
+    int32_t accept_rule, wavelet_map, centring, pad1;
     double A0, kT, k_bond, R0, R02, sigma2, eps, rc2, rc, r_int;
     uint32_t seed_lo, seed_hi;
     int32_t nsys, pad;
@@ -114,6 +116,8 @@ struct DevPtrs {
     int32_t *fcount, *fstart, *fidx, *fcell;
     int32_t* fblock;            // per-chunk sums of the grid scan
     unsigned long long* drift;  // per system, bits of the max drift since the grid build
+    unsigned long long* drift_col;  // per (system, colour): drift published by that colour phase
+    double* cell_drift;         // per (system, level, cell): largest drift of the beads it moved
     unsigned long long* cnt;    // CNT_* counters
     unsigned long long* sys_acc;// accepted chains per system
     wmc_trace_rec* trace;
@@ -131,7 +135,8 @@ struct DevPtrs {
     unsigned long long* flow_ctr;  // per level: cells handed out by the dependency-ordered kernel
     int32_t* coop_i;            // per-workgroup counts of the cooperative kernels [COOP_SLOTS]
     double* coop_d;             // per-workgroup partial results [5][COOP_SLOTS]
-    double* igrid;              // infinite-system grid of the current level: o[3], n[3]
+    double* igrid;              // infinite-system grid of the current level: o[3], n[3], k0[3]
+    double* com_ref;            // per chain: centre of mass at the reference positions [3 n_chains]
     int64_t total_fine;
 };
 
@@ -157,6 +162,8 @@ bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, const Coo
 int cell_coop_blocks();
 int pw_coop_blocks();
 void launch_rg2(const DevPtrs& D, const int64_t* chain_off, int64_t n_chains, double* out, hipStream_t st);
+// mode 0: centre of mass [3 n] to out; 1: the same into D.com_ref; 2: |com - com_ref|^2 [n] to out
+void launch_com(const DevPtrs& D, const int64_t* chain_off, int64_t n_chains, int mode, double* out, hipStream_t st);
 void launch_cell_ids(const DevParams& P, const DevPtrs& D, int sys, int level, int64_t sweep, int64_t n, int32_t* out,
                      hipStream_t st);
 void launch_philox(const uint32_t* ctr, const uint32_t* key, int64_t n, uint32_t* out, hipStream_t st);

@@ -16,8 +16,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwmc.so")
 
 MAX_LEVELS = 16
+K_SHELLS = 16
 BOND = {"none": 0, "fene": 1, "harmonic": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
+ACCEPT = {"metropolis": 0, "glauber": 1}
+WAVELET_MAP = {"linear": 0, "rotation": 1}
+CENTRING = {"anchor": 0, "uniform": 1}
+# return codes of include/wmc.h
+ECAPACITY, ESCHEDULE = -5, -6
 
 
 class Params(C.Structure):
@@ -30,6 +36,7 @@ class Params(C.Structure):
         ("r_int_harmonic", C.c_double),
         ("n_layers", C.c_int32), ("retry_cap", C.c_int32),
         ("seed", C.c_uint64),
+        ("accept_rule", C.c_int32), ("wavelet_map", C.c_int32), ("centring", C.c_int32), ("pad", C.c_int32),
     ]
 
 
@@ -40,7 +47,8 @@ class Obs(C.Structure):
     ] + [(name, C.c_int64) for name in (
         "pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates",
         "violations", "accepted_total", "rechecks", "overflows", "grid_rebuilds", "wait_timeouts",
-        "fallback_cells", "accepted_bead_updates")]
+        "fallback_cells", "accepted_bead_updates")] + [
+        ("pw_shell_attempts", C.c_int64 * K_SHELLS), ("pw_shell_accepts", C.c_int64 * K_SHELLS)]
 
 
 class TraceRec(C.Structure):
@@ -73,6 +81,8 @@ def lib():
         L.wmc_observables.argtypes = [vp, C.POINTER(Obs)]
         L.wmc_system_tau.argtypes = [vp, dp]
         L.wmc_chain_rg2.argtypes = [vp, dp]
+        L.wmc_chain_com.argtypes = [vp, dp]
+        L.wmc_chain_msd.argtypes = [vp, dp]
         L.wmc_trace.argtypes = [vp, C.POINTER(TraceRec), i64, lp]
         L.wmc_system_info.argtypes = [vp, i32, dp, C.POINTER(C.c_int32), dp]
         L.wmc_cell_ids.argtypes = [vp, i32, i64, i32, C.POINTER(C.c_int32)]
@@ -84,7 +94,7 @@ def lib():
         L.wmc_last_error.restype = C.c_char_p
         L.wmc_free.argtypes = [vp]
         for f in ("wmc_arena_bytes", "wmc_init", "wmc_init_static", "wmc_sweep", "wmc_positions", "wmc_set_state", "wmc_observables",
-                  "wmc_system_tau", "wmc_chain_rg2", "wmc_trace", "wmc_system_info", "wmc_cell_ids", "wmc_philox",
+                  "wmc_system_tau", "wmc_chain_rg2", "wmc_chain_com", "wmc_chain_msd", "wmc_trace", "wmc_system_info", "wmc_cell_ids", "wmc_philox",
                   "wmc_set_timing", "wmc_kernel_times"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -115,6 +125,9 @@ def make_params(d: dict) -> Params:
     p.n_layers = int(d.get("n_layers", 15))
     p.retry_cap = int(d.get("retry_cap", 64))
     p.seed = int(d.get("seed", 1))
+    p.accept_rule = ACCEPT[d.get("accept", "metropolis")]
+    p.wavelet_map = WAVELET_MAP[d.get("wavelet_map", "linear")]
+    p.centring = CENTRING[d.get("centring", "anchor")]
     return p
 
 
@@ -220,9 +233,13 @@ class WMC:
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
         self._check(lib().wmc_set_state(self._h, _dp(pos), int(sweep), _stream(None)), "wmc_set_state")
 
-    def observables(self) -> dict:
+    def observables(self, check: bool = True) -> dict:
+        """Counters; with check=False an overflow or wait time-out is reported in the counters
+        (overflows, wait_timeouts) instead of raising."""
         o = Obs()
-        self._check(lib().wmc_observables(self._h, C.byref(o)), "wmc_observables")
+        rc = lib().wmc_observables(self._h, C.byref(o))
+        if check or rc not in (ECAPACITY, ESCHEDULE):
+            self._check(rc, "wmc_observables")
         d = {"sweeps": o.sweeps}
         for name in ("trials", "hits", "attempts", "accepts", "caps", "redraws", "bead_updates"):
             d[name] = np.array(getattr(o, name)[:], dtype=np.int64)
@@ -230,6 +247,8 @@ class WMC:
                      "accepted_total", "rechecks", "overflows", "grid_rebuilds", "wait_timeouts", "fallback_cells",
                      "accepted_bead_updates"):
             d[name] = getattr(o, name)
+        for name in ("pw_shell_attempts", "pw_shell_accepts"):
+            d[name] = np.array(getattr(o, name)[:], dtype=np.int64)
         return d
 
     def tau(self) -> np.ndarray:
@@ -240,6 +259,16 @@ class WMC:
     def chain_rg2(self) -> np.ndarray:
         out = np.empty(self.n_chains)
         self._check(lib().wmc_chain_rg2(self._h, _dp(out)), "wmc_chain_rg2")
+        return out
+
+    def chain_com(self) -> np.ndarray:
+        out = np.empty((self.n_chains, 3))
+        self._check(lib().wmc_chain_com(self._h, _dp(out)), "wmc_chain_com")
+        return out
+
+    def chain_msd(self) -> np.ndarray:
+        out = np.empty(self.n_chains)
+        self._check(lib().wmc_chain_msd(self._h, _dp(out)), "wmc_chain_msd")
         return out
 
     def trace(self, max_records: int = 1 << 22) -> np.ndarray:

@@ -63,5 +63,7 @@ def compare_counters(og, oo):
     for k in ("pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates", "violations",
               "accepted_total", "accepted_bead_updates"):
         assert og[k] == oo[k], (k, og[k], oo[k])
+    for k in ("pw_shell_attempts", "pw_shell_accepts"):
+        np.testing.assert_array_equal(og[k], oo[k], err_msg=k)
     assert og["overflows"] == 0
     assert og.get("wait_timeouts", 0) == 0

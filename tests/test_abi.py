@@ -69,6 +69,7 @@ def test_arena_size_grows_with_problem(L):
     (dict(lambda_min=0.0), -1),
     (dict(bond_type="harmonic", r_int_harmonic=0.0), -1),
     (dict(retry_cap=0), -1),
+    (dict(periodic=0, centring="uniform"), -1),  # uniform centres need a box
 ])
 def test_rejects_bad_parameters(L, bad, expect):
     rc, _ = _arena(L, dict(BASE, **bad), [0, 100], [0, 100])
@@ -79,3 +80,44 @@ def test_rejects_bad_topology(L):
     assert _arena(L, BASE, [0, 100], [0, 50, 90])[0] == -1          # chains do not cover the beads
     assert _arena(L, BASE, [0, 50, 100], [0, 60, 100], box=np.array([20.0, 20.0]))[0] == -1  # crosses systems
     assert _arena(L, dict(BASE, periodic=0), [0, 10, 20], [0, 10, 20])[0] == -1  # infinite: one system
+
+
+def _init_no_arena(L, params, pos, chain_off):
+    """wmc_init with no device arena: every check of the initial state runs on the host before
+    any device work, so a bad state is reported without a GPU."""
+    from paper_1611_09160_amd import wmc
+
+    p = wmc.make_params(params)
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    so = np.array([0, len(pos)], dtype=np.int64)
+    co = np.ascontiguousarray(chain_off, dtype=np.int64)
+    h = C.c_void_p()
+    rc = L.wmc_init(C.byref(h), C.byref(p), 1, so.ctypes.data_as(C.POINTER(C.c_int64)), None, None, len(co) - 1,
+                    co.ctypes.data_as(C.POINTER(C.c_int64)), pos.ctypes.data_as(C.POINTER(C.c_double)), 0, None, 0,
+                    None)
+    msg = L.wmc_last_error(h).decode()
+    L.wmc_free(h)
+    return rc, msg
+
+
+def test_init_rejects_infinite_energy_states(L):
+    rng = np.random.default_rng(0)
+    steps = rng.normal(size=(10, 3))
+    steps = 0.97 * steps / np.linalg.norm(steps, axis=1)[:, None]
+    pos = np.concatenate([np.cumsum(steps[:5], 0) + 3.0, np.cumsum(steps[5:], 0) + 11.0])
+    chain = [0, 5, 10]
+    assert _init_no_arena(L, BASE, pos, chain)[0] == -3          # a valid state: only the arena is missing
+    mono = list(range(11))                                         # ten unbonded beads
+    bad = pos.copy()
+    bad[7] = bad[2]                                                # two beads at one point: WCA diverges
+    rc, msg = _init_no_arena(L, BASE, bad, mono)
+    assert rc == -2 and "same point" in msg
+    bad = pos.copy()
+    bad[2] = [2.5, 3.25, 4.0]
+    bad[7] = [22.5, 3.25, -16.0]                                   # the same point through the box
+    assert _init_no_arena(L, BASE, bad, mono)[0] == -2
+    assert _init_no_arena(L, dict(BASE, wca=0), bad, mono)[0] == -3  # no WCA: finite
+    bad = pos.copy()
+    bad[1] = bad[0] + np.array([1.5, 0.0, 0.0])                    # FENE bond at R0
+    rc, msg = _init_no_arena(L, BASE, bad, chain)
+    assert rc == -2 and "overstretched" in msg
