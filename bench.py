@@ -133,8 +133,28 @@ def run_oracle(cfg, start, sweep0: int, budget_s: float):
     ob = o.observables()
     beads = int(ob["bead_updates"].sum() + ob["pw_bead_updates"])
     return dict(value=beads / dt, unit="bead-updates/s", cores=1, kind="oracle",
-                sample=f"{n} sweeps of the equilibrated workload state, single-threaded FP64 C (gcc -O2)",
+                sample=f"{n} sweeps of the equilibrated workload state, single-threaded FP64 C (gcc -O3)",
                 seconds=round(dt, 2), tau_per_wall_s=float(o.tau().sum()) / dt)
+
+
+def other_workloads(warmup: int, steps: int) -> dict:
+    """Throughput of the paper's other two workload shapes (FP64): the 1024-bead dilute chain in
+    L = 128 with plane waves, and the 64-bead ideal chain in an infinite system (pure wavelets, and
+    with the infinite-system plane waves)."""
+    from paper_1611_09160_amd import workloads as W
+
+    out = {}
+    cases = (("dilute_chain_1024", W.config(2), {}, 50),
+             ("ideal_chain_64", W.config(1), {}, 200),
+             ("ideal_chain_64_w+F", W.config(1), dict(plane_waves=1), 200))
+    for name, cfg, over, equil in cases:
+        cfg = dict(cfg, params=dict(cfg["params"], **over))
+        g, r = run_gpu(cfg, "fp64", equil, warmup, steps)
+        g.close()
+        out[name] = dict(value=round(r["bead_updates_per_s"], 1), unit="bead-updates/s",
+                         tau_per_wall_s=round(r["tau_per_wall_s"], 4), ms_per_step=round(r["ms_per_step"], 3),
+                         beads=int(cfg["sys_offset"][-1]), workload=cfg["name"] + (" + plane waves" if over else ""))
+    return out
 
 
 def copy_bandwidth_gbs(mib: int = 1024, reps: int = 10) -> float:
@@ -163,6 +183,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-others", action="store_true", help="skip the dilute and ideal-chain lines")
     ap.add_argument("--batch-equilibrate", type=int, default=100)
     ap.add_argument("--copy-check", type=int, default=0, metavar="MB",
                     help="only copy a buffer of MB megabytes 4 times (reference for HBM byte counters)")
@@ -176,11 +197,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_check_bytes=a.numel() * 8, copies=4)))
-        return
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is not built.",
               file=sys.stderr)
-        sys.exit(2)
+        return 2
     import numpy as np
     import torch
 
@@ -226,6 +247,7 @@ def main():
         copies["workload"] = "8 independent copies of the 32,768-bead solution (each its own start)"
         split["workload"] = "the 32,768 beads as 8 solutions of 32 x 128 beads, L = 42, same concentration"
         batched = dict(copies=copies, split_32k=split)
+    others = None if args.no_others else other_workloads(args.warmup, args.steps)
     cpu = None
     if not args.no_cpu:
         cpu = run_oracle(cfg, start, sweep0, args.cpu_budget)
@@ -244,7 +266,7 @@ def main():
                    tau_per_wall_s=round(rmix["tau_per_wall_s"], 4), rechecks=rmix["rechecks"],
                    accepted_bead_updates_per_s=round(rmix["accepted_bead_updates_per_s"], 1),
                    ratio_vs_fp64=round(rmix["bead_updates_per_s"] / r64["bead_updates_per_s"], 3)),
-        batched=batched,
+        batched=batched, other_workloads=others,
         kernel_ms_fp64={k: [round(v[0], 3), v[1]] for k, v in kt.items()},
         checks=dict(overflows=r64["overflows"] + rmix["overflows"], violations=r64["violations"],
                     wait_timeouts=r64["wait_timeouts"] + rmix["wait_timeouts"]),
@@ -253,8 +275,15 @@ def main():
     bad = {k: v for k, v in line["checks"].items() if v}
     if bad:
         print(f"bench.py: the run is invalid: {bad} (every count must be 0)", file=sys.stderr)
-        sys.exit(3)
+        return 3
+    return 0
 
 
 if __name__ == "__main__":
-    main()
+    rc = main() or 0
+    # Every context is closed; end without exit-time destructors. Under rocprofv3 the process
+    # otherwise faults inside exit() after the profiler has finalised and written its files,
+    # but only once libwmc's code object is loaded (a copy-only run exits cleanly).
+    sys.stdout.flush()
+    sys.stderr.flush()
+    os._exit(rc)

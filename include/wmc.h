@@ -151,6 +151,20 @@ int wmc_arena_bytes(const wmc_params* p, int32_t n_systems, const int64_t* sys_b
                     const double* sys_box_L, const double* sys_lambda_max, int64_t n_chains,
                     const int64_t* chain_offset, int64_t trace_capacity, size_t* out_bytes);
 
+/* The launch plan wmc_init would make for this problem if cell_blocks and pw_blocks workgroups of
+ * its cell-group and plane-wave kernels could be co-resident, with launches capped at
+ * cell_launch_max / pw_launch_max workgroups. Host only: no device is touched. Every index the
+ * kernels derive from the plan (block maps, cooperative group tables, per-workgroup result slots,
+ * barrier words, list slices, global list slots, cell flags) is checked; report (caller-owned,
+ * report_bytes) receives "ok" or the first violation, then a summary. Returns 0, WMC_EINVAL for a
+ * violation or bad arguments. (An inspection of the schedule the paper leaves to the
+ * implementation, Sec. VII's parallel execution of non-overlapping moves.) */
+int wmc_launch_plan(const wmc_params* p, int32_t n_systems, const int64_t* sys_bead_offset,
+                    const double* sys_box_L, const double* sys_lambda_max, int64_t n_chains,
+                    const int64_t* chain_offset, const double* pos_xyz, int32_t cell_blocks,
+                    int32_t pw_blocks, int32_t cell_launch_max, int32_t pw_launch_max, char* report,
+                    size_t report_bytes);
+
 /* Set up the problem of Sec. II: N_b-bead chains with FENE (Eq. "FENE potential") or harmonic
  * bonds and WCA pairs (Eq. "WCA potential") in periodic boxes or an infinite system. Validates
  * the parameters, builds the per-system schedule tables (levels of Eq. "PDF for lambda", P_F of

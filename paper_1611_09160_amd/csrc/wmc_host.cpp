@@ -575,6 +575,11 @@ extern "C" int wmc_arena_bytes(const wmc_params* p, int32_t n_systems, const int
     return 0;
 }
 
+extern "C" int wmc_launch_plan(const wmc_params* p, int32_t nsys, const int64_t* so, const double* sL,
+                               const double* sl, int64_t n_chains, const int64_t* co, const double* pos,
+                               int32_t cell_blocks, int32_t pw_blocks, int32_t cell_launch_max,
+                               int32_t pw_launch_max, char* report, size_t report_bytes);
+
 // Group sizes of the cooperative launches, from each system's bead count: a cell group gets one
 // workgroup per CELL_GROUP_BEADS beads (at most CELL_GROUP_MAX, and enough that a workgroup's
 // slice of the reach list fits its LDS list), a plane-wave group one per PW_GROUP_BEADS (at most
@@ -638,11 +643,10 @@ static int map_groups(const std::vector<int>& G, int cap, std::vector<int32_t>& 
     return (int)map.size();
 }
 
-static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
+static void build_groups(wmc_ctx* c, int64_t capacity_ints, int ccap, int pcap) {
     c->coop_host.clear();
     auto& H = c->coop_host;
     std::vector<int32_t> tiles;
-    const int ccap = c->P.periodic ? std::min(cell_coop_blocks(), CELL_LAUNCH_MAX) : 0;
     for (int l = 0; l < WMC_MAX_LEVELS; ++l)
         for (int col = 0; col < 8; ++col) {
             c->cwg_n[l][col] = 0;
@@ -711,7 +715,7 @@ static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
         std::vector<int64_t> Ns(c->nsys);
         for (int s = 0; s < c->nsys; ++s) Ns[s] = c->sys[s].N;
         std::vector<int> G(c->nsys);
-        if (size_groups(G, Ns, PW_GROUP_BEADS, PW_GROUP_MAX, std::min(pw_coop_blocks(), PW_LAUNCH_MAX), 0)) {
+        if (size_groups(G, Ns, PW_GROUP_BEADS, PW_GROUP_MAX, pcap, 0)) {
             int first = 0;
             c->pgrp_off = (int64_t)H.size();
             for (int s = 0; s < c->nsys; ++s) {
@@ -719,7 +723,7 @@ static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
                 first += G[s];
             }
             std::vector<int32_t> wmap;
-            const int nwg = map_groups(G, std::min(pw_coop_blocks(), PW_LAUNCH_MAX), wmap);
+            const int nwg = map_groups(G, pcap, wmap);
             c->pwg_off = (int64_t)H.size();
             H.insert(H.end(), wmap.begin(), wmap.end());
             c->pwg_n = nwg;
@@ -733,6 +737,252 @@ static void build_groups(wmc_ctx* c, int64_t capacity_ints) {
         }
         c->pwg_n = 0;
     }
+}
+
+// Launch plan of a context (host only): per periodic LDS-tile level the kernel variant raised until
+// the densest windows fit its lists, the block maps of every (level, colour), and the cooperative
+// groups of the global-list cells and of the plane waves for launches of at most ccap / pcap
+// co-resident workgroups.
+static void plan_launches(wmc_ctx* c, const wmc_params* p, const double* pos, const Plan& pl, int ccap, int pcap) {
+    const int nsys = c->nsys;
+    // capacities from the actual clustering: a dilute chain puts most of its beads into one
+    // cell's reach, far above the uniform-density estimate the plan used. A tile that does not
+    // fit LDS falls back to the global path, whose reach and member lists live in LDS too and
+    // must not overflow. Per periodic LDS-tile level the beads are binned at a quarter of the
+    // cell side; the largest periodic box window as wide as a cell's reach (cell + 2 lambda_hi)
+    // and as wide as a wavelet (2 lambda_hi) bound those lists for any shifted cell and any
+    // centre, and the variant is raised until both fit with a 12.5% margin.
+    if (p->periodic) {
+        const int caps[3] = {1024, 4096, 8192}, capm[3] = {256, 1024, 4096};  // global-path lists per variant
+        for (int s = 0; s < nsys; ++s) {
+            const SysDesc& d = c->sys[s];
+            for (int l = 0; l < d.n_levels; ++l) {
+                LevelDesc& L = c->lev[d.lvl_off + l];
+                if (L.use_global || L.n < 4) continue;
+                const int m = 4 * L.n;
+                const double inv_bin = 4.0 * L.invh;
+                std::vector<int32_t> cnt((size_t)m * m * m, 0);
+                for (int64_t i = d.b0; i < d.b1; ++i) {
+                    int q[3];
+                    for (int ax = 0; ax < 3; ++ax) {
+                        double v = pos[3 * i + ax];
+                        v -= d.L * floor(v * d.invL);
+                        q[ax] = std::min(m - 1, std::max(0, (int)(v * inv_bin)));
+                    }
+                    ++cnt[q[0] + (size_t)m * (q[1] + (size_t)m * q[2])];
+                }
+                // largest count over periodic windows of w bins per axis (separable sliding sums)
+                auto window_max = [&](int w) {
+                    w = std::max(1, std::min(m, w));
+                    std::vector<int32_t> a = cnt, b((size_t)m * m * m);
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const size_t stride = ax == 0 ? 1 : (ax == 1 ? (size_t)m : (size_t)m * m);
+                        for (int u = 0; u < m; ++u)
+                            for (int v = 0; v < m; ++v) {
+                                const size_t base = ax == 0 ? (size_t)m * (u + (size_t)m * v)
+                                                  : (ax == 1 ? (size_t)u + (size_t)m * m * v : (size_t)u + (size_t)m * v);
+                                int64_t run = 0;
+                                for (int k = 0; k < w; ++k) run += a[base + stride * (size_t)(k % m)];
+                                for (int k = 0; k < m; ++k) {
+                                    b[base + stride * (size_t)k] = (int32_t)run;
+                                    run += a[base + stride * (size_t)((k + w) % m)] - a[base + stride * (size_t)k];
+                                }
+                            }
+                        std::swap(a, b);
+                    }
+                    int64_t worst = 0;
+                    for (int32_t v : a) worst = std::max<int64_t>(worst, v);
+                    return worst + worst / 8;
+                };
+                const int64_t need_s = window_max((int)ceil((L.h + 2.0 * L.hi) * inv_bin) + 1);
+                const int64_t need_m = window_max((int)ceil(2.0 * L.hi * inv_bin) + 1);
+                while (L.variant < V1024 && (need_s > caps[L.variant] || need_m > capm[L.variant])) L.variant += 1;
+            }
+        }
+    }
+    // block maps
+    c->max_levels = 0;
+    for (auto& s : c->sys) c->max_levels = std::max(c->max_levels, (int)s.n_levels);
+    c->bmap_host.clear();
+    for (int l = 0; l < WMC_MAX_LEVELS; ++l) {
+        c->phase_variant[l] = V64;
+        for (int col = 0; col < 8; ++col) {
+            c->bmap_off[l][col] = (int64_t)c->bmap_host.size() / 2;
+            int32_t cnt = 0;
+            for (int s = 0; s < nsys && p->periodic; ++s) {
+                if (l >= c->sys[s].n_levels) continue;
+                const LevelDesc& L = c->lev[c->sys[s].lvl_off + l];
+                c->phase_variant[l] = std::max(c->phase_variant[l], L.variant);
+                int64_t ncol = L.n >= 2 ? (int64_t)(L.n / 2) * (L.n / 2) * (L.n / 2) : (col == 0 ? 1 : 0);
+                for (int64_t k = 0; k < ncol; ++k) {
+                    c->bmap_host.push_back(s);
+                    c->bmap_host.push_back((int32_t)k);
+                    ++cnt;
+                }
+            }
+            c->bmap_n[l][col] = cnt;
+        }
+        if (!p->periodic && l < c->max_levels) c->phase_variant[l] = c->lev[l].variant;
+    }
+    build_groups(c, pl.coop_ints, ccap, pcap);
+}
+
+// Every index the kernels derive from a launch plan, checked on the host: block-map entries, the
+// cooperative group tables (workgroup ranges, per-workgroup result slots, barrier words, list
+// slices), the workgroup -> (group, rank) maps, global list slots and cell flags. Returns an empty
+// string when all hold, else the first violation.
+static std::string check_plan(const wmc_ctx* c, const Plan& pl, int ccap, int pcap) {
+    char buf[256];
+    auto bad = [&](const char* what, long a, long b, long d) {
+        snprintf(buf, sizeof(buf), "%s (%ld, %ld, %ld)", what, a, b, d);
+        return std::string(buf);
+    };
+    const auto& H = c->coop_host;
+    if ((int64_t)H.size() > pl.coop_ints) return bad("group table exceeds its arena", (long)H.size(), (long)pl.coop_ints, 0);
+    if ((int64_t)c->bmap_host.size() > 3 * 2 * std::max<int64_t>(pl.bmap, 1)) return bad("block map exceeds its arena", (long)c->bmap_host.size(), (long)pl.bmap, 0);
+    auto ncol_of = [&](const LevelDesc& L, int col) -> int64_t {
+        return L.n >= 2 ? (int64_t)(L.n / 2) * (L.n / 2) * (L.n / 2) : (col == 0 ? 1 : 0);
+    };
+    // group table at goff with ng groups and the map at woff with nwg entries
+    auto check_groups = [&](int64_t goff, int ng, int64_t woff, int nwg, int gmax, int cap, int64_t slice_cap,
+                            const char* kind) -> std::string {
+        if (nwg > cap) return bad(kind, nwg, cap, -1);
+        if (ng > COOP_SLOTS - 1) return bad("more groups than barrier words", ng, COOP_SLOTS - 1, 0);
+        int first = 0;
+        std::vector<int> size(ng);
+        for (int g = 0; g < ng; ++g) {
+            const int32_t* e = &H[goff + 4 * g];
+            if (e[0] < 0 || e[0] >= c->nsys) return bad("group system out of range", g, e[0], c->nsys);
+            if (e[2] != first) return bad("group slots not consecutive", g, e[2], first);
+            if (e[3] < 1 || e[3] > gmax) return bad("group size out of range", g, e[3], gmax);
+            if (slice_cap > 0 && (c->sys[e[0]].N + e[3] - 1) / e[3] > slice_cap)
+                return bad("list slice exceeds the workgroup's list", g, c->sys[e[0]].N, e[3]);
+            first += e[3];
+            size[g] = e[3];
+        }
+        if (first > cap || first > COOP_SLOTS) return bad("group slots exceed the launch", first, cap, COOP_SLOTS);
+        std::vector<std::vector<int>> seen(ng);
+        for (int g = 0; g < ng; ++g) seen[g].assign(size[g], 0);
+        for (int w = 0; w < nwg; ++w) {
+            const int32_t e = H[woff + w];
+            if (e < 0) continue;
+            const int g = e & 0xFFFF, r = e >> 16;
+            if (g >= ng || r >= size[g]) return bad("map entry names no group rank", w, g, r);
+            if (seen[g][r]++) return bad("group rank mapped twice", w, g, r);
+        }
+        for (int g = 0; g < ng; ++g)
+            for (int r = 0; r < size[g]; ++r)
+                if (!seen[g][r]) return bad("group rank without a workgroup", g, r, nwg);
+        return std::string();
+    };
+    for (int l = 0; l < WMC_MAX_LEVELS; ++l) {
+        for (int col = 0; col < 8; ++col) {
+            for (int kind = 0; kind < 2; ++kind) {
+                const int64_t off = kind ? c->glob_off[l][col] : c->tile_off[l][col];
+                const int32_t n = kind ? c->glob_n[l][col] : c->tile_n[l][col];
+                for (int32_t e = 0; e < n; ++e) {
+                    const int32_t sy = c->bmap_host[2 * (off + e)], loc = c->bmap_host[2 * (off + e) + 1];
+                    if (sy < 0 || sy >= c->nsys || l >= c->sys[sy].n_levels) return bad("block map system", l, col, sy);
+                    const LevelDesc& L = c->lev[c->sys[sy].lvl_off + l];
+                    if (loc < 0 || loc >= ncol_of(L, col)) return bad("block map cell", l, col, loc);
+                    if (kind == 0 && (L.use_global || L.n < 4)) return bad("tile cell on a level without tiles", l, sy, L.n);
+                    if (kind == 1 && !L.use_global) return bad("global-list cell on a tile level", l, sy, L.n);
+                    if (kind == 1 && (L.slot_base + loc >= pl.slots || pl.slot_len < c->sys[sy].N))
+                        return bad("global list slot out of range", l, sy, loc);
+                    if (L.variant > c->phase_variant[l]) return bad("level variant above its launch's", l, sy, L.variant);
+                }
+            }
+            if (c->cwg_n[l][col] > 0) {
+                const std::string e = check_groups(c->cgrp_off[l][col], c->glob_n[l][col], c->cwg_off[l][col],
+                                                   c->cwg_n[l][col], CELL_GROUP_MAX, ccap, COOP_LIST_CAP, "cell launch above cap");
+                if (!e.empty()) return e + " level " + std::to_string(l) + " colour " + std::to_string(col);
+                for (int32_t g = 0; g < c->glob_n[l][col]; ++g) {
+                    const int32_t* ge = &H[c->cgrp_off[l][col] + 4 * g];
+                    if (ge[0] != c->bmap_host[2 * (c->glob_off[l][col] + g)] || ge[1] != c->bmap_host[2 * (c->glob_off[l][col] + g) + 1])
+                        return bad("group does not match its block-map cell", l, col, g);
+                }
+            }
+        }
+        if (c->cmerge[l]) {
+            int c0 = -1;
+            for (int col = 0; col < 8; ++col) {
+                if (c->glob_n[l][col] <= 0) continue;
+                if (c->cwg_n[l][col] <= 0) return bad("merged colour without a group launch", l, col, 0);
+                if (c0 < 0) { c0 = col; continue; }
+                if (c->glob_n[l][col] != c->glob_n[l][c0] || c->cwg_n[l][col] != c->cwg_n[l][c0]) return bad("merged colours differ", l, col, c0);
+                for (int32_t g = 0; g < c->glob_n[l][col]; ++g)
+                    for (int q : {0, 2, 3})
+                        if (H[c->cgrp_off[l][col] + 4 * g + q] != H[c->cgrp_off[l][c0] + 4 * g + q]) return bad("merged group differs", l, col, g);
+            }
+        }
+    }
+    if (c->pwg_n > 0) {
+        const std::string e = check_groups(c->pgrp_off, c->nsys, c->pwg_off, c->pwg_n, PW_GROUP_MAX, pcap, 0, "plane-wave launch above cap");
+        if (!e.empty()) return e + " (plane waves)";
+    }
+    for (int s = 0; s < c->nsys; ++s)
+        for (int l = 0; l < c->sys[s].n_levels; ++l) {
+            const LevelDesc& L = c->lev[c->sys[s].lvl_off + l];
+            const int64_t n = std::max(L.n, 1);
+            if (c->P.periodic && L.flag_base + n * n * n > std::max<int64_t>(pl.flags, 1)) return bad("cell flags out of range", s, l, L.flag_base);
+        }
+    return std::string();
+}
+
+extern "C" int wmc_launch_plan(const wmc_params* p, int32_t nsys, const int64_t* so, const double* sL,
+                               const double* sl, int64_t n_chains, const int64_t* co, const double* pos,
+                               int32_t cell_blocks, int32_t pw_blocks, int32_t cell_launch_max,
+                               int32_t pw_launch_max, char* report, size_t report_bytes) {
+    wmc_ctx c;
+    auto put = [&](const std::string& m) {
+        if (report && report_bytes) {
+            strncpy(report, m.c_str(), report_bytes - 1);
+            report[report_bytes - 1] = 0;
+        }
+    };
+    int rc = validate(&c, p, nsys, so, sL, sl, n_chains, co);
+    if (rc) {
+        put(c.err);
+        return rc;
+    }
+    if (!pos || cell_blocks < 0 || pw_blocks < 0) {
+        put("null positions or negative limits");
+        return WMC_EINVAL;
+    }
+    c.p = *p;
+    c.nsys = nsys;
+    c.N = so[nsys];
+    c.n_chains = n_chains;
+    memset(&c.P, 0, sizeof(c.P));
+    c.P.periodic = p->periodic;
+    c.P.plane_waves = p->plane_waves;
+    Plan pl;
+    std::vector<PWTables> pool;
+    std::vector<int> pidx;
+    rc = plan_systems(&c, p, nsys, so, sL, sl, n_chains, 0, pl, &c.sys, &c.lev, &pool, &pidx);
+    if (rc) {
+        put(c.err);
+        return rc;
+    }
+    const int ccap = p->periodic ? std::min(cell_blocks, cell_launch_max) : 0;
+    const int pcap = std::min(pw_blocks, pw_launch_max);
+    plan_launches(&c, p, pos, pl, ccap, pcap);
+    const std::string err = check_plan(&c, pl, ccap, pcap);
+    int groups = 0, cell_launches = 0, widest = 0;
+    for (int l = 0; l < WMC_MAX_LEVELS; ++l)
+        for (int col = 0; col < 8; ++col)
+            if (c.cwg_n[l][col] > 0) {
+                ++cell_launches;
+                groups += c.glob_n[l][col];
+                widest = std::max(widest, (int)c.cwg_n[l][col]);
+            }
+    char buf[512];
+    snprintf(buf, sizeof(buf),
+             "%s; systems %d beads %lld arena %zu bytes; cell-group launches %d (groups %d, widest %d workgroups); "
+             "plane-wave group launch %d workgroups",
+             err.empty() ? "ok" : err.c_str(), nsys, (long long)c.N, pl.bytes, cell_launches, groups, widest, c.pwg_n);
+    put(buf);
+    return err.empty() ? 0 : WMC_EINVAL;
 }
 
 extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const int64_t* so, const double* sL,
@@ -886,86 +1136,8 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
         std::copy(pool[k].cdf.begin(), pool[k].cdf.end(), cube.begin() + k * pool[k].cdf.size());
         std::copy(pool[k].shell.begin(), pool[k].shell.end(), shell.begin() + k * 4097);
     }
-    // capacities from the actual clustering: a dilute chain puts most of its beads into one
-    // cell's reach, far above the uniform-density estimate the plan used. A tile that does not
-    // fit LDS falls back to the global path, whose reach and member lists live in LDS too and
-    // must not overflow. Per periodic LDS-tile level the beads are binned at a quarter of the
-    // cell side; the largest periodic box window as wide as a cell's reach (cell + 2 lambda_hi)
-    // and as wide as a wavelet (2 lambda_hi) bound those lists for any shifted cell and any
-    // centre, and the variant is raised until both fit with a 12.5% margin.
-    if (p->periodic) {
-        const int caps[3] = {1024, 4096, 8192}, capm[3] = {256, 1024, 4096};  // global-path lists per variant
-        for (int s = 0; s < nsys; ++s) {
-            const SysDesc& d = c->sys[s];
-            for (int l = 0; l < d.n_levels; ++l) {
-                LevelDesc& L = c->lev[d.lvl_off + l];
-                if (L.use_global || L.n < 4) continue;
-                const int m = 4 * L.n;
-                const double inv_bin = 4.0 * L.invh;
-                std::vector<int32_t> cnt((size_t)m * m * m, 0);
-                for (int64_t i = d.b0; i < d.b1; ++i) {
-                    int q[3];
-                    for (int ax = 0; ax < 3; ++ax) {
-                        double v = pos[3 * i + ax];
-                        v -= d.L * floor(v * d.invL);
-                        q[ax] = std::min(m - 1, std::max(0, (int)(v * inv_bin)));
-                    }
-                    ++cnt[q[0] + (size_t)m * (q[1] + (size_t)m * q[2])];
-                }
-                // largest count over periodic windows of w bins per axis (separable sliding sums)
-                auto window_max = [&](int w) {
-                    w = std::max(1, std::min(m, w));
-                    std::vector<int32_t> a = cnt, b((size_t)m * m * m);
-                    for (int ax = 0; ax < 3; ++ax) {
-                        const size_t stride = ax == 0 ? 1 : (ax == 1 ? (size_t)m : (size_t)m * m);
-                        for (int u = 0; u < m; ++u)
-                            for (int v = 0; v < m; ++v) {
-                                const size_t base = ax == 0 ? (size_t)m * (u + (size_t)m * v)
-                                                  : (ax == 1 ? (size_t)u + (size_t)m * m * v : (size_t)u + (size_t)m * v);
-                                int64_t run = 0;
-                                for (int k = 0; k < w; ++k) run += a[base + stride * (size_t)(k % m)];
-                                for (int k = 0; k < m; ++k) {
-                                    b[base + stride * (size_t)k] = (int32_t)run;
-                                    run += a[base + stride * (size_t)((k + w) % m)] - a[base + stride * (size_t)k];
-                                }
-                            }
-                        std::swap(a, b);
-                    }
-                    int64_t worst = 0;
-                    for (int32_t v : a) worst = std::max<int64_t>(worst, v);
-                    return worst + worst / 8;
-                };
-                const int64_t need_s = window_max((int)ceil((L.h + 2.0 * L.hi) * inv_bin) + 1);
-                const int64_t need_m = window_max((int)ceil(2.0 * L.hi * inv_bin) + 1);
-                while (L.variant < V1024 && (need_s > caps[L.variant] || need_m > capm[L.variant])) L.variant += 1;
-            }
-        }
-    }
-    // block maps
-    c->max_levels = 0;
-    for (auto& s : c->sys) c->max_levels = std::max(c->max_levels, (int)s.n_levels);
-    c->bmap_host.clear();
-    for (int l = 0; l < WMC_MAX_LEVELS; ++l) {
-        c->phase_variant[l] = V64;
-        for (int col = 0; col < 8; ++col) {
-            c->bmap_off[l][col] = (int64_t)c->bmap_host.size() / 2;
-            int32_t cnt = 0;
-            for (int s = 0; s < nsys && p->periodic; ++s) {
-                if (l >= c->sys[s].n_levels) continue;
-                const LevelDesc& L = c->lev[c->sys[s].lvl_off + l];
-                c->phase_variant[l] = std::max(c->phase_variant[l], L.variant);
-                int64_t ncol = L.n >= 2 ? (int64_t)(L.n / 2) * (L.n / 2) * (L.n / 2) : (col == 0 ? 1 : 0);
-                for (int64_t k = 0; k < ncol; ++k) {
-                    c->bmap_host.push_back(s);
-                    c->bmap_host.push_back((int32_t)k);
-                    ++cnt;
-                }
-            }
-            c->bmap_n[l][col] = cnt;
-        }
-        if (!p->periodic && l < c->max_levels) c->phase_variant[l] = c->lev[l].variant;
-    }
-    build_groups(c, pl.coop_ints);
+    plan_launches(c, p, pos, pl, p->periodic ? std::min(cell_coop_blocks(), CELL_LAUNCH_MAX) : 0,
+                  std::min(pw_coop_blocks(), PW_LAUNCH_MAX));
     HIPCHK(c, hipMemsetAsync(base, 0, pl.bytes - 256, st));
     HIPCHK(c, hipMemcpyAsync(D.x, soa.data(), 3 * N * 8, hipMemcpyHostToDevice, st));
     HIPCHK(c, hipMemcpyAsync(D.bond_next, bond.data(), N, hipMemcpyHostToDevice, st));

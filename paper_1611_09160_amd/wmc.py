@@ -75,6 +75,8 @@ def lib():
         L.wmc_arena_bytes.argtypes = [C.POINTER(Params), i32, lp, dp, dp, i64, lp, i64, C.POINTER(C.c_size_t)]
         L.wmc_init.argtypes = [C.POINTER(vp), C.POINTER(Params), i32, lp, dp, dp, i64, lp, dp, i64, vp, C.c_size_t, vp]
         L.wmc_init_static.argtypes = [C.POINTER(vp), C.POINTER(Params), i32, lp, dp, dp, i64, lp, dp, i64, vp]
+        L.wmc_launch_plan.argtypes = [C.POINTER(Params), i32, lp, dp, dp, i64, lp, dp, i32, i32, i32, i32, C.c_char_p,
+                                      C.c_size_t]
         L.wmc_sweep.argtypes = [vp, i64, vp]
         L.wmc_positions.argtypes = [vp, dp, i32, vp]
         L.wmc_set_state.argtypes = [vp, dp, i64, vp]
@@ -93,7 +95,7 @@ def lib():
         L.wmc_last_error.argtypes = [vp]
         L.wmc_last_error.restype = C.c_char_p
         L.wmc_free.argtypes = [vp]
-        for f in ("wmc_arena_bytes", "wmc_init", "wmc_init_static", "wmc_sweep", "wmc_positions", "wmc_set_state", "wmc_observables",
+        for f in ("wmc_arena_bytes", "wmc_launch_plan", "wmc_init", "wmc_init_static", "wmc_sweep", "wmc_positions", "wmc_set_state", "wmc_observables",
                   "wmc_system_tau", "wmc_chain_rg2", "wmc_chain_com", "wmc_chain_msd", "wmc_trace", "wmc_system_info", "wmc_cell_ids", "wmc_philox",
                   "wmc_set_timing", "wmc_kernel_times"):
             getattr(L, f).restype = C.c_int
@@ -302,6 +304,23 @@ class WMC:
         self._check(lib().wmc_cell_ids(self._h, system, int(sweep), level, out.ctypes.data_as(C.POINTER(C.c_int32))),
                     "wmc_cell_ids")
         return out
+
+
+def launch_plan(cfg: dict, cell_blocks: int, pw_blocks: int, cell_launch_max: int, pw_launch_max: int):
+    """Host-only check of the launch plan of a workload for given co-residency limits
+    (wmc_launch_plan): returns (return code, report)."""
+    p = make_params(cfg["params"])
+    so = np.ascontiguousarray(cfg["sys_offset"], dtype=np.int64)
+    co = np.ascontiguousarray(cfg["chain_offset"], dtype=np.int64)
+    pos = np.ascontiguousarray(cfg["pos"], dtype=np.float64).reshape(-1, 3)
+    bl = cfg.get("sys_box_L")
+    lm = cfg.get("sys_lambda_max")
+    bl = None if bl is None else np.ascontiguousarray(bl, dtype=np.float64)
+    lm = None if lm is None else np.ascontiguousarray(lm, dtype=np.float64)
+    buf = C.create_string_buffer(1024)
+    rc = lib().wmc_launch_plan(C.byref(p), len(so) - 1, _lp(so), _dp(bl), _dp(lm), len(co) - 1, _lp(co), _dp(pos),
+                               int(cell_blocks), int(pw_blocks), int(cell_launch_max), int(pw_launch_max), buf, 1024)
+    return rc, buf.value.decode()
 
 
 def philox(ctr, key, n: int = 1) -> np.ndarray:
