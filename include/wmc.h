@@ -89,7 +89,9 @@ typedef struct {
                                 infinite system k from P(k) ~ k^2 I(k lambda_max) (Eq. "PDF of k")
                                 with P_F = (lambda_min/lambda_max)^3 (Eq. "P(Fourier) infinite") */
     int32_t wavelets;        /* 1: wavelet moves (0 only for plane-wave-only checks) */
-    int32_t precision;       /* WMC_FP64, or WMC_MIXED: FP32 energy terms with FP64 recheck */
+    int32_t precision;       /* WMC_FP64, or WMC_MIXED: FP32 tile offsets, displacements,
+                                distances and energy terms, FP64 positions, an FP64 recheck of
+                                every decision within the FP32 error bound */
     double box_L;            /* box side, used when sys_box_L is NULL */
     double lambda_min;       /* smallest wavelet radius; sets a = lambda_min / lambda_a */
     double lambda_max;       /* largest wavelet radius (<= L/2), used when sys_lambda_max is NULL */
@@ -108,7 +110,9 @@ typedef struct {
     int32_t accept_rule;     /* WMC_ACCEPT_* */
     int32_t wavelet_map;     /* WMC_MAP_* */
     int32_t centring;        /* WMC_CENTRE_* (UNIFORM needs a periodic box) */
-    int32_t pad;
+    int32_t mixed_verify;    /* WMC_MIXED, 1: also evaluate every FP32-tile test in FP64 and
+                                count those whose FP32 error exceeds the recheck margin (the
+                                decisions are unchanged; slower, for validation) */
 } wmc_params;
 
 /* Counters summed over systems (wmc_observables). */
@@ -137,6 +141,10 @@ typedef struct {
      * floor(|l|) of the lattice index l, infinite floor(|k| lambda_max), capped at 15 */
     int64_t pw_shell_attempts[WMC_K_SHELLS];
     int64_t pw_shell_accepts[WMC_K_SHELLS];
+    int64_t member_rechecks;              /* WMC_MIXED: FP32 support tests re-evaluated in FP64 */
+    int64_t margin_checks;                /* mixed_verify: tests evaluated in both precisions */
+    int64_t margin_fails;                 /* ... whose |dU32 - dU64| exceeded the margin (must be 0) */
+    double margin_max_ratio;              /* ... largest |dU32 - dU64| / margin seen */
 } wmc_obs;
 
 /* One trace record per Metropolis test (kind 0 wavelet, 2 plane wave) and per cell phase

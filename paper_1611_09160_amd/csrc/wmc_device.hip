@@ -16,6 +16,7 @@
 #include <math.h>
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 #include "wmc_internal.h"
 
 namespace wmc {
@@ -197,6 +198,41 @@ __device__ __forceinline__ float u_pair_fs(const DevParams& P, double r2, float&
         return INFINITY;
     }
     const float s2 = (float)P.sigma2 / r2f, s6 = s2 * s2 * s2, e4 = 4.0f * (float)P.eps;
+    sens = e4 * (6.0f * s6 * s6 + 3.0f * s6);
+    return e4 * (s6 * s6 - s6 + 0.25f);
+}
+
+// The same terms from an FP32 r2 (FP32 tile). sens bounds |r2 dU/dr2| and |U| of the term (for
+// WCA 6 s^12 + 3 s^6 >= |s^12 - s^6 + 1/4| inside the cut-off; for FENE r2/(R0^2 - r2) R0^2/2 >=
+// -ln(1 - r2/R0^2) R0^2/2 times x ln x/(x - 1) <= 1), so that one margin covers both the error
+// of r2 and the rounding of the term.
+__device__ __forceinline__ float u_bond_f32(const DevParams& P, float r2, float& sens) {
+    if (P.bond_type == WMC_BOND_FENE) {
+        const float R02 = (float)P.R02, x = 1.0f - r2 / R02;
+        if (!(x > 0.0f)) {
+            sens = INFINITY;
+            return INFINITY;
+        }
+        sens = 0.5f * (float)P.k_bond * r2 / x;
+        return -0.5f * (float)P.k_bond * R02 * logf(x);
+    }
+    if (P.bond_type == WMC_BOND_HARMONIC) {
+        sens = 0.5f * (float)P.k_bond * r2;
+        return sens;
+    }
+    sens = 0.0f;
+    return 0.0f;
+}
+__device__ __forceinline__ float u_pair_f32(const DevParams& P, float r2, float rc2f, float& sens) {
+    if (r2 >= rc2f) {
+        sens = 0.0f;
+        return 0.0f;
+    }
+    if (r2 <= 0.0f) {
+        sens = INFINITY;
+        return INFINITY;
+    }
+    const float s2 = (float)P.sigma2 / r2, s6 = s2 * s2 * s2, e4 = 4.0f * (float)P.eps;
     sens = e4 * (6.0f * s6 * s6 + 3.0f * s6);
     return e4 * (s6 * s6 - s6 + 0.25f);
 }
@@ -1186,9 +1222,11 @@ constexpr int32_t ID_MASK = 0x3FFFFFFF;
 constexpr int32_t ID_NEXT = 0x40000000;  // bonded to bead id + 1
 constexpr uint32_t ID_PREV = 0x80000000u;  // bonded to bead id - 1
 
-template <int W, int CAPH, int CAPM, int NCD>
+// T = double: absolute FP64 positions (FP64 contexts). T = float (mixed precision): FP32 offsets from
+// the tile's centre, minimg(r - c) rounded once; the FP64 positions stay in HBM.
+template <int W, int CAPH, int CAPM, int NCD, class T = double>
 struct TileShared {
-    double x[CAPH], y[CAPH], z[CAPH];
+    T x[CAPH], y[CAPH], z[CAPH];
     int32_t id[CAPH];
     int16_t kc[CAPH];           // tile cell list: slots by tile cell, ascending within a cell
     // member index of a moved slot (-1: not moved); with no trial positions kept (CAPM == 0)
@@ -1200,8 +1238,9 @@ struct TileShared {
     // entries, so that the index build can update them as packed pairs
     alignas(4) int16_t cst[(NCD * NCD * NCD + 2) & ~1];
     int16_t M[CAPH];                   // member slots of the current test
-    // trial positions of the first CAPM members (later ones are recomputed when needed)
-    double MX[CAPM > 0 ? CAPM : 1], MY[CAPM > 0 ? CAPM : 1], MZ[CAPM > 0 ? CAPM : 1];
+    // trial positions (T = float: FP32 displacements) of the first CAPM members (later ones are
+    // recomputed when needed)
+    T MX[CAPM > 0 ? CAPM : 1], MY[CAPM > 0 ? CAPM : 1], MZ[CAPM > 0 ? CAPM : 1];
     double red[W / 64 > 0 ? W / 64 : 1];
     int redi[W / 64 > 0 ? W / 64 : 1];
     int count;
@@ -1211,26 +1250,26 @@ struct TileShared {
     uint32_t pub_next;
 };
 
-template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD>
+template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, class T = double>
 union PhaseLDS {
     PhaseShared<W, CAPS, CAPM> g;
-    TileShared<W, CAPH, CAPMT, NCD> t;
+    TileShared<W, CAPH, CAPMT, NCD, T> t;
 };
 
-template <int W, int CAPH, int CAPM, int NCD>
-__device__ __forceinline__ int tile_tag(const TileShared<W, CAPH, CAPM, NCD>& sh, int sl) {
+template <int W, int CAPH, int CAPM, int NCD, class T>
+__device__ __forceinline__ int tile_tag(const TileShared<W, CAPH, CAPM, NCD, T>& sh, int sl) {
     if (CAPM > 0) return sh.tag[sl];
     return ((sh.tagb[sl >> 5] >> (sl & 31)) & 1u) ? 0 : -1;
 }
-template <int W, int CAPH, int CAPM, int NCD>
-__device__ __forceinline__ void tile_tag_set(TileShared<W, CAPH, CAPM, NCD>& sh, int sl, int k) {
+template <int W, int CAPH, int CAPM, int NCD, class T>
+__device__ __forceinline__ void tile_tag_set(TileShared<W, CAPH, CAPM, NCD, T>& sh, int sl, int k) {
     if (CAPM > 0)
         sh.tag[sl] = (int16_t)k;
     else
         atomicOr(&sh.tagb[sl >> 5], 1u << (sl & 31));
 }
-template <int W, int CAPH, int CAPM, int NCD>
-__device__ __forceinline__ void tile_tag_clear(TileShared<W, CAPH, CAPM, NCD>& sh, int sl) {
+template <int W, int CAPH, int CAPM, int NCD, class T>
+__device__ __forceinline__ void tile_tag_clear(TileShared<W, CAPH, CAPM, NCD, T>& sh, int sl) {
     if (CAPM > 0)
         sh.tag[sl] = -1;
     else
@@ -1254,6 +1293,8 @@ __device__ __forceinline__ int tile_clamp(const TileGeo& tg, double u) {
 __device__ __forceinline__ double tile_u(const Grid& g, const TileGeo& tg, double v, int a) {
     return minimg(g, v - tg.c[a]) + tg.He;
 }
+// tile coordinate of a stored position: absolute FP64, or an FP32 offset from the centre
+__device__ __forceinline__ double tile_u(const Grid&, const TileGeo& tg, float v, int) { return (double)v + tg.He; }
 
 // trial position of member k (tile slot sl)
 template <int W, int CAPH, int CAPM, int NCD>
@@ -1270,6 +1311,58 @@ __device__ __forceinline__ void member_new(const TileShared<W, CAPH, CAPM, NCD>&
         ny = sh.y[sl] + w1;
         nz = sh.z[sl] + w2;
     }
+}
+
+// The wavelet of the current test on an FP32 tile: centre as an FP32 offset from the tile centre,
+// FP32 polarisation, radius and amplitude.
+struct WaveDesc32 {
+    float b[3], p[3], lam, invlam, A;
+    int rot;
+};
+
+// FP32 displacement of the bead at tile offset (x, y, z): the two maps of wavelet_disp, with
+// x_r = (r - b)/lambda from offsets (no minimum image: a tile is shorter than half the box)
+__device__ __forceinline__ void wavelet_disp32(const WaveDesc32& wv, float x, float y, float z, float& w0, float& w1,
+                                               float& w2) {
+    const float xr0 = (x - wv.b[0]) * wv.invlam, xr1 = (y - wv.b[1]) * wv.invlam, xr2 = (z - wv.b[2]) * wv.invlam;
+    const float rr = sqrtf((xr0 * xr0 + xr1 * xr1) + xr2 * xr2);
+    if (wv.rot) {
+        const float a = rr < 1.0f ? (wv.A * wv.invlam) * (1.0f - rr) : 0.0f;
+        const float sa = sinf(a), hs = sinf(0.5f * a), omc = 2.0f * hs * hs;
+        const float pd = (wv.p[0] * xr0 + wv.p[1] * xr1) + wv.p[2] * xr2;
+        w0 = wv.lam * (sa * (wv.p[1] * xr2 - wv.p[2] * xr1) + omc * (wv.p[0] * pd - xr0));
+        w1 = wv.lam * (sa * (wv.p[2] * xr0 - wv.p[0] * xr2) + omc * (wv.p[1] * pd - xr1));
+        w2 = wv.lam * (sa * (wv.p[0] * xr1 - wv.p[1] * xr0) + omc * (wv.p[2] * pd - xr2));
+        return;
+    }
+    const float f = rr < 1.0f ? wv.A * (1.0f - rr) : 0.0f;
+    w0 = f * (wv.p[1] * xr2 - wv.p[2] * xr1);
+    w1 = f * (wv.p[2] * xr0 - wv.p[0] * xr2);
+    w2 = f * (wv.p[0] * xr1 - wv.p[1] * xr0);
+}
+
+// FP32 displacement of member k (tile slot sl): kept in MX/MY/MZ for the first CAPM members
+template <int W, int CAPH, int CAPM, int NCD>
+__device__ __forceinline__ void member_w32(const TileShared<W, CAPH, CAPM, NCD, float>& sh, const WaveDesc32& wv, int k,
+                                           int sl, float& w0, float& w1, float& w2) {
+    if (CAPM > 0 && k < CAPM) {
+        w0 = sh.MX[k];
+        w1 = sh.MY[k];
+        w2 = sh.MZ[k];
+    } else {
+        wavelet_disp32(wv, sh.x[sl], sh.y[sl], sh.z[sl], w0, w1, w2);
+    }
+}
+
+// FP32 squared distance of two tile offsets; wrap applies the minimum image (needed only once a
+// tile with its drift spans more than the box minus the cut-off)
+__device__ __forceinline__ float r2_f32(float dx, float dy, float dz, bool wrap, float Lf, float invLf) {
+    if (wrap) {
+        dx -= Lf * rintf(dx * invLf);
+        dy -= Lf * rintf(dy * invLf);
+        dz -= Lf * rintf(dz * invLf);
+    }
+    return (dx * dx + dy * dy) + dz * dz;
 }
 
 // exchanges at distance J inside one thread's 8 consecutive entries v[0..8) (first index i0),
@@ -1360,8 +1453,8 @@ __device__ void bitonic_sort(int32_t* a, int np2) {
 }
 
 // tile cell of slot i
-template <int W, int CAPH, int CAPM, int NCD>
-__device__ __forceinline__ int tile_key(const TileShared<W, CAPH, CAPM, NCD>& sh, int i, const Grid& g,
+template <int W, int CAPH, int CAPM, int NCD, class T>
+__device__ __forceinline__ int tile_key(const TileShared<W, CAPH, CAPM, NCD, T>& sh, int i, const Grid& g,
                                         const TileGeo& tg) {
     const int cx = tile_clamp(tg, tile_u(g, tg, sh.x[i], 0));
     const int cy = tile_clamp(tg, tile_u(g, tg, sh.y[i], 1));
@@ -1374,8 +1467,8 @@ __device__ __forceinline__ int tile_key(const TileShared<W, CAPH, CAPM, NCD>& sh
 // scatter that takes positions down from each end (leaving each cell's start), and an
 // insertion sort of every cell's few entries by slot. The result is the list sorted by
 // (cell, slot), whatever order the atomics took.
-template <int W, int CAPH, int CAPM, int NCD>
-__device__ void tile_index(TileShared<W, CAPH, CAPM, NCD>& sh, int nH, const Grid& g, const TileGeo& tg) {
+template <int W, int CAPH, int CAPM, int NCD, class T>
+__device__ void tile_index(TileShared<W, CAPH, CAPM, NCD, T>& sh, int nH, const Grid& g, const TileGeo& tg) {
     const int tid = threadIdx.x;
     const int NC = tg.nc * tg.nc * tg.nc;
     uint32_t* cw = reinterpret_cast<uint32_t*>(sh.cst);
@@ -1422,8 +1515,8 @@ __device__ void tile_index(TileShared<W, CAPH, CAPM, NCD>& sh, int nH, const Gri
 }
 
 // slot of bead j in the sorted tile, or -1
-template <int W, int CAPH, int CAPM, int NCD>
-__device__ __forceinline__ int tile_find(const TileShared<W, CAPH, CAPM, NCD>& sh, int nH, int32_t j) {
+template <int W, int CAPH, int CAPM, int NCD, class T>
+__device__ __forceinline__ int tile_find(const TileShared<W, CAPH, CAPM, NCD, T>& sh, int nH, int32_t j) {
     int lo = 0, hi = nH - 1;
     while (lo <= hi) {
         int mid = (lo + hi) >> 1;
@@ -1441,11 +1534,39 @@ __device__ __forceinline__ int tile_find(const TileShared<W, CAPH, CAPM, NCD>& s
 // drift since the list was built. One work item is a (member, y-z row of cells) pair whose
 // x range is contiguous in the list.
 // mode 0: FP64; mode 1: FP32 terms (acc) with their sensitivity (sens).
-template <int W, int CAPH, int CAPM, int NCD>
+// On an FP32 tile (T = float, WV = WaveDesc32) this is the FP64 recheck: the same bonds and pairs
+// (found from the FP32 tile), evaluated from the FP64 positions in HBM plus the FP32 displacements
+// that an accept would apply.
+template <int W, int CAPH, int CAPM, int NCD, class T = double, class WV = WaveDesc>
 __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
-                        const TileShared<W, CAPH, CAPM, NCD>& sh, const Grid& g, const TileGeo& tg,
-                        const WaveDesc& wv, double R,
+                        const TileShared<W, CAPH, CAPM, NCD, T>& sh, const Grid& g, const TileGeo& tg,
+                        const WV& wv, double R,
                         int nH, int n, int mode, double& acc, double& sens, unsigned long long& viol) {
+    constexpr bool F32 = std::is_same<T, float>::value;
+    auto cur = [&](int sl, double& x, double& y, double& z) {
+        if constexpr (F32) {
+            const int32_t j = sh.id[sl] & ID_MASK;
+            x = D.x[j];
+            y = D.y[j];
+            z = D.z[j];
+        } else {
+            x = sh.x[sl];
+            y = sh.y[sl];
+            z = sh.z[sl];
+        }
+    };
+    auto trial = [&](int k, int sl, double& x, double& y, double& z) {
+        if constexpr (F32) {
+            cur(sl, x, y, z);
+            float w0, w1, w2;
+            member_w32(sh, wv, k, sl, w0, w1, w2);
+            x += (double)w0;
+            y += (double)w1;
+            z += (double)w2;
+        } else {
+            member_new(sh, g, wv, k, sl, x, y, z);
+        }
+    };
     const int tid = threadIdx.x;
     const double L = s.L, invL = s.invL;
     const int NR = min(tg.nc, (int)floor(2.0 * R * tg.invf) + 2);
@@ -1462,9 +1583,9 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
             const int sl = sh.M[k];
             const int32_t raw = sh.id[sl];
             const int32_t j = raw & ID_MASK;
-            const double jx = sh.x[sl], jy = sh.y[sl], jz = sh.z[sl];
-            double kx, ky, kz;
-            member_new(sh, g, wv, k, sl, kx, ky, kz);
+            double jx, jy, jz, kx, ky, kz;
+            cur(sl, jx, jy, jz);
+            trial(k, sl, kx, ky, kz);
             for (int e = 0; e < 2; ++e) {
                 bool bonded = e == 0 ? (raw & ID_NEXT) != 0 : ((uint32_t)raw & ID_PREV) != 0;
                 if (!bonded) continue;
@@ -1475,13 +1596,11 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                 if (ps >= 0) {
                     const int tm = tile_tag(sh, ps);
                     if (tm >= 0 && ps < sl) continue;
-                    mx = sh.x[ps];
-                    my = sh.y[ps];
-                    mz = sh.z[ps];
+                    cur(ps, mx, my, mz);
                     nx = mx;
                     ny = my;
                     nz = mz;
-                    if (tm >= 0) member_new(sh, g, wv, tm, ps, nx, ny, nz);
+                    if (tm >= 0) trial(tm, ps, nx, ny, nz);
                 } else {
                     // partner beyond the halo: only a bond longer than r_int can do this
                     mx = nx = D.x[m];
@@ -1506,24 +1625,26 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
             const int k = it / per, q = it - k * per;
             const int qy = q % NR, qz = q / NR;
             const int sl = sh.M[k];
-            const double jx = sh.x[sl], jy = sh.y[sl], jz = sh.z[sl];
-            const double uy = tile_u(g, tg, jy, 1), uz = tile_u(g, tg, jz, 2);
+            double jx, jy, jz;
+            cur(sl, jx, jy, jz);
+            const double uy = tile_u(g, tg, sh.y[sl], 1), uz = tile_u(g, tg, sh.z[sl], 2);
             const int cy = tile_clamp(tg, uy - R) + qy, cz = tile_clamp(tg, uz - R) + qz;
             if (cy > tile_clamp(tg, uy + R) || cz > tile_clamp(tg, uz + R)) continue;
-            const double ux = tile_u(g, tg, jx, 0);
+            const double ux = tile_u(g, tg, sh.x[sl], 0);
             const int row = tg.nc * (cy + tg.nc * cz);
             const int p0 = sh.cst[row + tile_clamp(tg, ux - R)], p1 = sh.cst[row + tile_clamp(tg, ux + R) + 1];
             double kx, ky, kz;
-            member_new(sh, g, wv, k, sl, kx, ky, kz);
+            trial(k, sl, kx, ky, kz);
             for (int pp = p0; pp < p1; ++pp) {
                 const int m = sh.kc[pp];
                 if (m == sl) continue;
                 const int tm = tile_tag(sh, m);
                 if (tm >= 0 && m < sl) continue;
-                const double mx = sh.x[m], my = sh.y[m], mz = sh.z[m];
+                double mx, my, mz;
+                cur(m, mx, my, mz);
                 double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
                 double nx = mx, ny = my, nz = mz;
-                if (tm >= 0) member_new(sh, g, wv, tm, m, nx, ny, nz);
+                if (tm >= 0) trial(tm, m, nx, ny, nz);
                 double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
                 if (r2o < P.rc2 || r2n < P.rc2) {
                     if (mode) {
@@ -1539,11 +1660,120 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
     }
 }
 
+// Energy change of the current test on an FP32 tile: the bonds and pairs of tile_dU, with FP32
+// distances between tile offsets and FP32 terms; each term's difference is summed in FP64 (acc).
+// s1 and s2 sum every counted term's sensitivity and sensitivity / r for the recheck margin; a
+// pair that FP32 places just outside the cut-off (r2 < rc2g) adds the sensitivity at the cut-off.
+template <int W, int CAPH, int CAPM, int NCD>
+__device__ void tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared<W, CAPH, CAPM, NCD, float>& sh,
+                          const Grid& g, const TileGeo& tg, const WaveDesc32& wv, double R, int nH, int n, bool wrap,
+                          float Lf, float invLf, float rc2f, float rc2g, double& acc, float& s1, float& s2,
+                          unsigned long long& viol) {
+    const int tid = threadIdx.x;
+    const float rint2 = (float)(P.r_int * P.r_int);
+    const int NR = min(tg.nc, (int)floor(2.0 * R * tg.invf) + 2);
+    const int per = NR * NR;
+    const int items = n * per;
+    const bool split = W == 256 && P.bond_type != WMC_BOND_NONE && P.wca && items <= W - 64;
+    const int b0 = split ? tid - (W - 64) : tid, bstride = split ? 64 : W;
+    const int p0 = split ? (tid < W - 64 ? tid : items) : tid, pstride = split ? W - 64 : W;
+    if (P.bond_type != WMC_BOND_NONE) {
+        for (int k = b0 < 0 ? n : b0; k < n; k += bstride) {
+            const int sl = sh.M[k];
+            const int32_t raw = sh.id[sl];
+            const int32_t j = raw & ID_MASK;
+            const float jx = sh.x[sl], jy = sh.y[sl], jz = sh.z[sl];
+            float w0, w1, w2;
+            member_w32(sh, wv, k, sl, w0, w1, w2);
+            const float kx = jx + w0, ky = jy + w1, kz = jz + w2;
+            for (int e = 0; e < 2; ++e) {
+                bool bonded = e == 0 ? (raw & ID_NEXT) != 0 : ((uint32_t)raw & ID_PREV) != 0;
+                if (!bonded) continue;
+                const int32_t m = e == 0 ? j + 1 : j - 1;
+                int ps = e == 0 ? sl + 1 : sl - 1;
+                if (ps < 0 || ps >= nH || (sh.id[ps] & ID_MASK) != m) ps = tile_find(sh, nH, m);
+                float mx, my, mz, nx, ny, nz;
+                if (ps >= 0) {
+                    const int tm = tile_tag(sh, ps);
+                    if (tm >= 0 && ps < sl) continue;
+                    mx = nx = sh.x[ps];
+                    my = ny = sh.y[ps];
+                    mz = nz = sh.z[ps];
+                    if (tm >= 0) {
+                        float v0, v1, v2;
+                        member_w32(sh, wv, tm, ps, v0, v1, v2);
+                        nx += v0;
+                        ny += v1;
+                        nz += v2;
+                    }
+                } else {
+                    // partner beyond the halo: only a bond longer than r_int can do this
+                    mx = nx = (float)minimg(g, D.x[m] - tg.c[0]);
+                    my = ny = (float)minimg(g, D.y[m] - tg.c[1]);
+                    mz = nz = (float)minimg(g, D.z[m] - tg.c[2]);
+                }
+                const float r2o = r2_f32(jx - mx, jy - my, jz - mz, wrap, Lf, invLf);
+                const float r2n = r2_f32(kx - nx, ky - ny, kz - nz, wrap, Lf, invLf);
+                if (r2o > rint2) ++viol;
+                float sn, so;
+                acc += (double)(u_bond_f32(P, r2n, sn) - u_bond_f32(P, r2o, so));
+                s1 += sn + so;
+                s2 += sn * rsqrtf(r2n) + so * rsqrtf(r2o);
+            }
+        }
+    }
+    if (P.wca) {
+        const float sc = 12.0f * (float)P.eps;  // sensitivity at the cut-off, 4 eps (6/4 + 3/2)
+        for (int it = p0; it < items; it += pstride) {
+            const int k = it / per, q = it - k * per;
+            const int qy = q % NR, qz = q / NR;
+            const int sl = sh.M[k];
+            const float jx = sh.x[sl], jy = sh.y[sl], jz = sh.z[sl];
+            const double uy = tile_u(g, tg, jy, 1), uz = tile_u(g, tg, jz, 2);
+            const int cy = tile_clamp(tg, uy - R) + qy, cz = tile_clamp(tg, uz - R) + qz;
+            if (cy > tile_clamp(tg, uy + R) || cz > tile_clamp(tg, uz + R)) continue;
+            const double ux = tile_u(g, tg, jx, 0);
+            const int row = tg.nc * (cy + tg.nc * cz);
+            const int q0 = sh.cst[row + tile_clamp(tg, ux - R)], q1 = sh.cst[row + tile_clamp(tg, ux + R) + 1];
+            float w0, w1, w2;
+            member_w32(sh, wv, k, sl, w0, w1, w2);
+            const float kx = jx + w0, ky = jy + w1, kz = jz + w2;
+            for (int pp = q0; pp < q1; ++pp) {
+                const int m = sh.kc[pp];
+                if (m == sl) continue;
+                const int tm = tile_tag(sh, m);
+                if (tm >= 0 && m < sl) continue;
+                const float mx = sh.x[m], my = sh.y[m], mz = sh.z[m];
+                const float r2o = r2_f32(jx - mx, jy - my, jz - mz, wrap, Lf, invLf);
+                float nx = mx, ny = my, nz = mz;
+                if (tm >= 0) {
+                    float v0, v1, v2;
+                    member_w32(sh, wv, tm, m, v0, v1, v2);
+                    nx += v0;
+                    ny += v1;
+                    nz += v2;
+                }
+                const float r2n = r2_f32(kx - nx, ky - ny, kz - nz, wrap, Lf, invLf);
+                const float m2 = fminf(r2o, r2n);
+                if (m2 < rc2f) {
+                    float sn, so;
+                    acc += (double)(u_pair_f32(P, r2n, rc2f, sn) - u_pair_f32(P, r2o, rc2f, so));
+                    s1 += sn + so;
+                    s2 += sn * rsqrtf(r2n) + so * rsqrtf(r2o);
+                } else if (m2 < rc2g) {
+                    s1 += sc;
+                    s2 += sc * rsqrtf(m2);
+                }
+            }
+        }
+    }
+}
+
 // returns false (before any move) when the halo does not fit; the caller then uses the
 // global path for this cell. Dg bounds the drift, since the neighbour grid was built, of every bead
 // the cell can meet; the largest drift of the beads the cell moves is returned in dl_out.
-template <int W, int CAPH, int CAPM, int NCD, bool MIXED, bool VAR>
-__device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShared<W, CAPH, CAPM, NCD>& sh, int sys,
+template <int W, int CAPH, int CAPM, int NCD, bool MIXED, bool VAR, class T>
+__device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShared<W, CAPH, CAPM, NCD, T>& sh, int sys,
                                   int level, int colour, int64_t local, int64_t sweep, const Grid& g,
                                   const double Dg, double& dl_out) {
     const SysDesc& s = D.sys[sys];
@@ -1557,6 +1787,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     const double rh = lv.hi + lv.r_int, rh2 = rh * rh;
     const double L = s.L, invL = s.invL;
     dl_out = 0.0;
+    // FP32 tile (mixed precision): offsets from the tile centre, the FP64 positions in HBM
+    constexpr bool F32 = std::is_same<T, float>::value;
 
     // tile cell list geometry; relative tile coordinates identify pairs only while the tile
     // (plus a cut-off and a margin for moves) is shorter than the box
@@ -1586,7 +1818,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
         const int nseg = cn[1] * cn[2] * (wrapx ? 2 : 1);
         int32_t* segB = reinterpret_cast<int32_t*>(sh.x);  // first index entry of each range
         int32_t* segP = reinterpret_cast<int32_t*>(sh.y);  // exclusive prefix of the range lengths
-        if (nseg + 1 <= 2 * CAPH) {
+        if (nseg + 1 <= (int)(sizeof(T) / 4) * CAPH) {
             for (int q = tid; q < nseg; q += W) {
                 const int r = wrapx ? (q >> 1) : q, part = wrapx ? (q & 1) : 0;
                 const int fy = (f0[1] + r % cn[1]) % s.nf, fz = (f0[2] + r / cn[1]) % s.nf;
@@ -1660,9 +1892,15 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
         if (i < nH) {
             int32_t j = sh.id[i];
             double x = D.x[j], y = D.y[j], z = D.z[j];
-            sh.x[i] = x;
-            sh.y[i] = y;
-            sh.z[i] = z;
+            if constexpr (F32) {
+                sh.x[i] = (float)minimg(g, x - tg.c[0]);
+                sh.y[i] = (float)minimg(g, y - tg.c[1]);
+                sh.z[i] = (float)minimg(g, z - tg.c[2]);
+            } else {
+                sh.x[i] = x;
+                sh.y[i] = y;
+                sh.z[i] = z;
+            }
             if (CAPM > 0) sh.tag[i] = -1;
             int32_t fl = j;
             if (j + 1 < s.b1 && D.bond_next[j]) fl |= ID_NEXT;
@@ -1677,7 +1915,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     }
     __syncthreads();
     tile_index<W, CAPH, CAPM, NCD>(sh, nH, g, tg);
-    double E = 0.0;  // bound on any tile bead's displacement since the cell list was built
+    double E = 0.0;     // bound on any tile bead's displacement since the cell list was built
+    double Etot = 0.0;  // ... since the tile was loaded (bounds the FP32 offsets with He)
 
     // ---- 3. trials and chains (as the global path, on LDS)
     const bool uni = VAR && P.centring == WMC_CENTRE_UNIFORM;
@@ -1693,6 +1932,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
         if (tid == 0) atomicAdd(&D.cnt[CNT_VIOL], 1ull);
     }
     unsigned long long c_hits = 0, c_att = 0, c_acc = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0;
+    unsigned long long c_mre = 0;  // FP32 support tests rechecked in FP64
     double d_local = 0.0;
     constexpr bool mixed = MIXED;
     // trials are drawn W at a time (one per lane); the draws (lambda, anchor, ball vector, stream
@@ -1700,10 +1940,19 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     // hits and only its hit test, which reads the anchor's current position, is repeated (a uniform
     // centre is drawn whole and kept in the ball vector's place)
     auto slot_of = [&](int64_t i) -> int32_t { return (int32_t)sh.S[i]; };
+    // FP64 position of a tile slot (centres decide cells, so they are drawn in FP64: from LDS, or
+    // from HBM for an FP32 tile)
     auto slot_pos = [&](int32_t sl, double& px, double& py, double& pz) {
-        px = sh.x[sl];
-        py = sh.y[sl];
-        pz = sh.z[sl];
+        if constexpr (F32) {
+            const int32_t j = sh.id[sl] & ID_MASK;
+            px = D.x[j];
+            py = D.y[j];
+            pz = D.z[j];
+        } else {
+            px = sh.x[sl];
+            py = sh.y[sl];
+            pz = sh.z[sl];
+        }
     };
     for (int64_t t0 = 0; t0 < K; t0 += W) {
         const int64_t t = t0 + tid;
@@ -1735,9 +1984,11 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 by = vy_t;
                 bz = vz_t;
             } else {
-                bx = sh.x[as_t] + lam_t * vx_t;
-                by = sh.y[as_t] + lam_t * vy_t;
-                bz = sh.z[as_t] + lam_t * vz_t;
+                double ax, ay, az;
+                slot_pos(as_t, ax, ay, az);
+                bx = ax + lam_t * vx_t;
+                by = ay + lam_t * vy_t;
+                bz = az + lam_t * vz_t;
             }
             hit = cell_of_point(g, bx, by, bz) == cell;
         }
@@ -1767,6 +2018,35 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             double px, py, pz;
             direction(cs, px, py, pz);
             const double u_acc = cs.oc();
+            // support test: FP64, or (FP32 tile) FP32 offsets with an FP64 recheck from HBM of every
+            // bead within the FP32 error bound of the sphere: the offsets carry at most eps He', the
+            // difference and sum their own rounding, so |d2_32 - d2| <= eps (7 lam He' + 6.5 lam^2)
+            // near |d| = lam (eps = 2^-24, He' = tile half-width plus drift); tolm is 16 times that
+            float bf0 = 0.0f, bf1 = 0.0f, bf2 = 0.0f, lam2f = 0.0f, tolm = 0.0f;
+            if constexpr (F32) {
+                bf0 = (float)minimg(g, b[0] - tg.c[0]);
+                bf1 = (float)minimg(g, b[1] - tg.c[1]);
+                bf2 = (float)minimg(g, b[2] - tg.c[2]);
+                lam2f = (float)lam2;
+                tolm = (float)(0x1p-20 * (lam * (tg.He + Etot) + 2.0 * lam2));
+            }
+            auto in_ball = [&](int sl) -> bool {
+                if constexpr (F32) {
+                    if (sl == as) return true;
+                    const float dx = sh.x[sl] - bf0, dy = sh.y[sl] - bf1, dz = sh.z[sl] - bf2;
+                    const float d2 = (dx * dx + dy * dy) + dz * dz;
+                    if (fabsf(d2 - lam2f) > tolm) return d2 <= lam2f;
+                    ++c_mre;
+                    const int32_t j = sh.id[sl] & ID_MASK;
+                    const double ex = minimg(g, D.x[j] - b[0]), ey = minimg(g, D.y[j] - b[1]),
+                                 ez = minimg(g, D.z[j] - b[2]);
+                    return ((ex * ex + ey * ey) + ez * ez) <= lam2;
+                } else {
+                    const double dx = minimg(g, sh.x[sl] - b[0]), dy = minimg(g, sh.y[sl] - b[1]),
+                                 dz = minimg(g, sh.z[sl] - b[2]);
+                    return ((dx * dx + dy * dy) + dz * dz) <= lam2 || sl == as;
+                }
+            };
             __syncthreads();
             int n = 0;
             if (W >= 256 && nS > W && nS <= 32 * W) {
@@ -1776,12 +2056,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 uint32_t mask = 0;
                 for (int u = 0; u < q; ++u) {
                     const int i = i0 + u;
-                    if (i < nS) {
-                        const int sl = sh.S[i];
-                        const double dx = minimg(g, sh.x[sl] - b[0]), dy = minimg(g, sh.y[sl] - b[1]),
-                                     dz = minimg(g, sh.z[sl] - b[2]);
-                        if (((dx * dx + dy * dy) + dz * dz) <= lam2 || sl == as) mask |= 1u << u;
-                    }
+                    if (i < nS && in_ball(sh.S[i])) mask |= 1u << u;
                 }
                 int before;
                 n = block_scan_count<W>(__popc(mask), before, sh.redi);
@@ -1794,10 +2069,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                     int sl = 0;
                     if (i < nS) {
                         sl = sh.S[i];
-                        double dx = minimg(g, sh.x[sl] - b[0]), dy = minimg(g, sh.y[sl] - b[1]),
-                               dz = minimg(g, sh.z[sl] - b[2]);
-                        double d2 = (dx * dx + dy * dy) + dz * dz;
-                        f = d2 <= lam2 || sl == as;
+                        f = in_ball(sl);
                     }
                     int before;
                     int tot = block_scan_flag<W>(f, before, sh.redi);
@@ -1816,33 +2088,102 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             wv.lam = lam;
             wv.A = wavelet_amp<VAR>(P, s, lam, n);
             wv.rot = VAR && P.wavelet_map == WMC_MAP_ROTATION;
+            WaveDesc32 wv32;
             double dmax_l = 0.0;
-            for (int k = tid; k < n; k += W) {
-                const int sl = sh.M[k];
-                double w0, w1, w2;
-                wavelet_disp(g, wv, sh.x[sl], sh.y[sl], sh.z[sl], w0, w1, w2);
-                if (CAPM > 0 && k < CAPM) {
-                    sh.MX[k] = sh.x[sl] + w0;
-                    sh.MY[k] = sh.y[sl] + w1;
-                    sh.MZ[k] = sh.z[sl] + w2;
+            if constexpr (F32) {
+                wv32.b[0] = bf0;
+                wv32.b[1] = bf1;
+                wv32.b[2] = bf2;
+                wv32.p[0] = (float)px;
+                wv32.p[1] = (float)py;
+                wv32.p[2] = (float)pz;
+                wv32.lam = (float)lam;
+                wv32.invlam = (float)(1.0 / lam);
+                wv32.A = (float)wv.A;
+                wv32.rot = wv.rot;
+                for (int k = tid; k < n; k += W) {
+                    const int sl = sh.M[k];
+                    float w0, w1, w2;
+                    wavelet_disp32(wv32, sh.x[sl], sh.y[sl], sh.z[sl], w0, w1, w2);
+                    if (CAPM > 0 && k < CAPM) {
+                        sh.MX[k] = w0;
+                        sh.MY[k] = w1;
+                        sh.MZ[k] = w2;
+                    }
+                    tile_tag_set(sh, sl, k);
+                    dmax_l = fmax(dmax_l, (double)sqrtf((w0 * w0 + w1 * w1) + w2 * w2));
                 }
-                tile_tag_set(sh, sl, k);
-                dmax_l = fmax(dmax_l, sqrt((w0 * w0 + w1 * w1) + w2 * w2));
+            } else {
+                for (int k = tid; k < n; k += W) {
+                    const int sl = sh.M[k];
+                    double w0, w1, w2;
+                    wavelet_disp(g, wv, sh.x[sl], sh.y[sl], sh.z[sl], w0, w1, w2);
+                    if (CAPM > 0 && k < CAPM) {
+                        sh.MX[k] = sh.x[sl] + w0;
+                        sh.MY[k] = sh.y[sl] + w1;
+                        sh.MZ[k] = sh.z[sl] + w2;
+                    }
+                    tile_tag_set(sh, sl, k);
+                    dmax_l = fmax(dmax_l, sqrt((w0 * w0 + w1 * w1) + w2 * w2));
+                }
             }
-            const double dmax = block_max<W>(dmax_l, sh.red);  // barrier: trial positions and tags visible
+            // barrier: trial positions and tags visible (an FP32 length is raised by 2^-20, more
+            // than its rounding)
+            const double dmax = block_max<W>(dmax_l, sh.red) * (F32 ? 1.0 + 0x1p-20 : 1.0);
             const double Rq = P.rc + 2.0 * dmax + E + 1e-9 * L;
             double acc = 0.0, sens = 0.0;
-            tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, mixed ? 1 : 0, acc, sens, c_viol);
             const double thr = accept_threshold<VAR>(P, u_acc);
-            double dU = block_sum<W>(acc, sh.red);
-            if (mixed) {
-                double bound = 64.0 * 0x1.0p-23 * block_sum<W>(sens, sh.red) + 1e-12;
-                if (!(isfinite(dU) && fabs(dU - thr) > bound)) {
+            double dU;
+            if constexpr (F32) {
+                // margin: a coordinate of magnitude <= Hq carries <= 4 eps Hq (offset, displacement
+                // and sum roundings), so a term's r2 is off by <= eps r2 (28 Hq/r + 6.5) and the term
+                // by <= eps sens (28 Hq/r + 24); the margin doubles both coefficients
+                const double Hq = tg.He + Etot + dmax;
+                const bool wrap = g.periodic && 2.0 * Hq + P.rc >= L;
+                const double Hm = wrap ? fmax(Hq, L) : Hq;
+                const float rc2g = (float)(P.rc2 * (1.0 + 0x1p-18 * (28.0 * Hm / fmax(P.rc, 1e-3) + 8.0)));
+                float s1 = 0.0f, s2 = 0.0f;
+                tile_dU32<W, CAPH, CAPM, NCD>(P, D, sh, g, tg, wv32, Rq, nH, n, wrap, (float)L, (float)invL,
+                                              (float)P.rc2, rc2g, acc, s1, s2, c_viol);
+                dU = block_sum<W>(acc, sh.red);
+                const double S1 = block_sum<W>((double)s1, sh.red), S2 = block_sum<W>((double)s2, sh.red);
+                const double m = 0x1.0p-23 * (64.0 * S1 + 32.0 * Hm * S2) + 1e-12;
+                const bool near = !(isfinite(dU) && fabs(dU - thr) > m);
+                if (near || P.mixed_verify) {
                     double a64 = 0.0, s64 = 0.0;
                     unsigned long long v64 = 0;
-                    tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, 0, a64, s64, v64);
-                    dU = block_sum<W>(a64, sh.red);
-                    if (tid == 0) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
+                    tile_dU<W, CAPH, CAPM, NCD, float, WaveDesc32>(P, D, s, sh, g, tg, wv32, Rq, nH, n, 0, a64, s64,
+                                                                    v64);
+                    const double d64 = block_sum<W>(a64, sh.red);
+                    if (tid == 0) {
+                        if (near) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
+                        if (P.mixed_verify) {
+                            atomicAdd(&D.cnt[CNT_MARGIN_CHECK], 1ull);
+                            bool fail = !near && !isfinite(d64);
+                            if (isfinite(dU) && isfinite(d64)) {
+                                const double ratio = fabs(dU - d64) / m;
+                                fail = fail || ratio > 1.0;
+                                if (ratio == ratio)
+                                    atomicMax(&D.cnt[CNT_MARGIN_RATIO],
+                                              (unsigned long long)__float_as_uint((float)ratio));
+                            }
+                            if (fail) atomicAdd(&D.cnt[CNT_MARGIN_FAIL], 1ull);
+                        }
+                    }
+                    if (near) dU = d64;
+                }
+            } else {
+                tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, mixed ? 1 : 0, acc, sens, c_viol);
+                dU = block_sum<W>(acc, sh.red);
+                if (mixed) {
+                    double bound = 64.0 * 0x1.0p-23 * block_sum<W>(sens, sh.red) + 1e-12;
+                    if (!(isfinite(dU) && fabs(dU - thr) > bound)) {
+                        double a64 = 0.0, s64 = 0.0;
+                        unsigned long long v64 = 0;
+                        tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, 0, a64, s64, v64);
+                        dU = block_sum<W>(a64, sh.red);
+                        if (tid == 0) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
+                    }
                 }
             }
             const bool accept = dU <= thr;
@@ -1856,10 +2197,22 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 if (accept) {
                     const int32_t j = sh.id[sl] & ID_MASK;
                     double nx, ny, nz;
-                    member_new(sh, g, wv, k, sl, nx, ny, nz);
-                    sh.x[sl] = nx;
-                    sh.y[sl] = ny;
-                    sh.z[sl] = nz;
+                    if constexpr (F32) {
+                        // FP64 position plus the FP32 displacement; the tile keeps its rounded offset
+                        float w0, w1, w2;
+                        member_w32(sh, wv32, k, sl, w0, w1, w2);
+                        nx = D.x[j] + (double)w0;
+                        ny = D.y[j] + (double)w1;
+                        nz = D.z[j] + (double)w2;
+                        sh.x[sl] = (float)minimg(g, nx - tg.c[0]);
+                        sh.y[sl] = (float)minimg(g, ny - tg.c[1]);
+                        sh.z[sl] = (float)minimg(g, nz - tg.c[2]);
+                    } else {
+                        member_new(sh, g, wv, k, sl, nx, ny, nz);
+                        sh.x[sl] = nx;
+                        sh.y[sl] = ny;
+                        sh.z[sl] = nz;
+                    }
                     D.x[j] = nx;
                     D.y[j] = ny;
                     D.z[j] = nz;
@@ -1873,6 +2226,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 ++c_acc;
                 if (tid == 0) atomicAdd(&D.cnt[CNT_ACC_BEADS], (unsigned long long)n);
                 E += dmax;
+                Etot += dmax;
                 if (E > 0.5 * tg.f) {
                     tile_index<W, CAPH, CAPM, NCD>(sh, nH, g, tg);
                     E = 0.0;
@@ -1928,6 +2282,10 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     }
     d_local = block_max<W>(d_local, sh.red);
     unsigned long long viol_all = (unsigned long long)block_sum<W>((double)c_viol, sh.red);
+    if constexpr (F32) {
+        const unsigned long long mre = (unsigned long long)block_sum<W>((double)c_mre, sh.red);
+        if (tid == 0 && mre) atomicAdd(&D.cnt[CNT_MEMBER_RECHECK], mre);
+    }
     if (tid == 0) {
         unsigned long long* C = D.cnt + CNT_LEVEL + level * 8;
         atomicAdd(&C[0], (unsigned long long)K);
@@ -1953,7 +2311,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
 template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, bool MIXED, bool VAR>
 __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, int colour, int64_t sweep,
                                              const int32_t* bmap, int nblocks) {
-    __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD> sh;
+    __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD, typename std::conditional<MIXED, float, double>::type> sh;
     if (P.periodic) {
         const int sys = bmap[2 * blockIdx.x], local = bmap[2 * blockIdx.x + 1];
         const SysDesc& s = D.sys[sys];
@@ -2035,7 +2393,7 @@ constexpr unsigned FLOW_SPIN_LIMIT = 1u << 24;
 template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, bool MIXED, bool VAR>
 __global__ __launch_bounds__(W, (W == 64 || MIXED) ? 2 : 1) void k_level_flow(DevParams P, DevPtrs D, int level, int64_t sweep,
                                                      const int32_t* items, FlowArgs fa) {
-    __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD> sh;
+    __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD, typename std::conditional<MIXED, float, double>::type> sh;
     __shared__ int s_idx;
     __shared__ int s_timeout;
     __shared__ double s_dg[27];

@@ -298,6 +298,7 @@ static int validate(wmc_ctx* c, const wmc_params* p, int32_t nsys, const int64_t
     if (p->wavelet_map < 0 || p->wavelet_map > 1) return fail("bad wavelet_map");
     if (p->centring < 0 || p->centring > 1) return fail("bad centring");
     if (p->centring == WMC_CENTRE_UNIFORM && !p->periodic) return fail("uniform centres need a periodic box");
+    if (p->mixed_verify < 0 || p->mixed_verify > 1) return fail("mixed_verify must be 0 or 1");
     if (!p->periodic && nsys != 1) return fail("an infinite system runs as a single system");
     if (so[0] != 0) return fail("sys_bead_offset[0] must be 0");
     for (int s = 0; s < nsys; ++s) {
@@ -1058,6 +1059,7 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     P.plane_waves = p->plane_waves;
     P.wavelets = p->wavelets;
     P.accept_rule = p->accept_rule;
+    P.mixed_verify = p->mixed_verify;
     P.wavelet_map = p->wavelet_map;
     P.centring = p->centring;
     P.precision = p->precision;
@@ -1442,6 +1444,15 @@ extern "C" int wmc_observables(wmc_ctx* c, wmc_obs* o) {
     for (int k = 0; k < WMC_K_SHELLS; ++k) {
         o->pw_shell_attempts[k] = cnt[CNT_SHELL + 2 * k];
         o->pw_shell_accepts[k] = cnt[CNT_SHELL + 2 * k + 1];
+    }
+    o->member_rechecks = cnt[CNT_MEMBER_RECHECK];
+    o->margin_checks = cnt[CNT_MARGIN_CHECK];
+    o->margin_fails = cnt[CNT_MARGIN_FAIL];
+    {
+        float r;
+        const uint32_t bits = (uint32_t)cnt[CNT_MARGIN_RATIO];
+        memcpy(&r, &bits, 4);
+        o->margin_max_ratio = r;
     }
     if (o->overflows > 0) {
         c->err = "a cell list overflowed its capacity: the sweeps since wmc_init are not valid samples";

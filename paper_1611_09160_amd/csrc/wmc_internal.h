@@ -26,7 +26,11 @@ constexpr int CNT_FLOWWAIT = 141;   // dependency waits that hit their spin limi
 constexpr int CNT_ACC_BEADS = 143;  // beads displaced by accepted moves, wavelet and plane wave
 constexpr int CNT_FALLBACK = 142;   // LDS-tile cells whose halo did not fit: run on the global-list path
 constexpr int CNT_SHELL = 144;      // [2 * shell + accepted]: plane-wave tests per |k| shell
-constexpr int CNT_TOTAL = 176;
+constexpr int CNT_MEMBER_RECHECK = 176;  // FP32-tile support tests re-evaluated in FP64
+constexpr int CNT_MARGIN_CHECK = 177;    // mixed_verify: tests evaluated in both precisions
+constexpr int CNT_MARGIN_FAIL = 178;     // ... whose FP32 error exceeded the recheck margin
+constexpr int CNT_MARGIN_RATIO = 179;    // ... largest error / margin, as FP32 bits (atomic max)
+constexpr int CNT_TOTAL = 184;
 
 // Cooperative launches: groups of co-resident workgroups, each group on one (system, cell) of a
 // colour phase or on one system's plane waves. A group owns workgroups [first, first + size)
@@ -99,7 +103,7 @@ struct LevelDesc {
 struct DevParams {
     int32_t periodic, plane_waves, wavelets, precision;
     int32_t bond_type, wca, retry_cap, n_layers;
-    int32_t accept_rule, wavelet_map, centring, pad1;
+    int32_t accept_rule, wavelet_map, centring, mixed_verify;
     double A0, kT, k_bond, R0, R02, sigma2, eps, rc2, rc, r_int;
     uint32_t seed_lo, seed_hi;
     int32_t nsys, pad;

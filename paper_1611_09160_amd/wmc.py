@@ -36,7 +36,7 @@ class Params(C.Structure):
         ("r_int_harmonic", C.c_double),
         ("n_layers", C.c_int32), ("retry_cap", C.c_int32),
         ("seed", C.c_uint64),
-        ("accept_rule", C.c_int32), ("wavelet_map", C.c_int32), ("centring", C.c_int32), ("pad", C.c_int32),
+        ("accept_rule", C.c_int32), ("wavelet_map", C.c_int32), ("centring", C.c_int32), ("mixed_verify", C.c_int32),
     ]
 
 
@@ -48,7 +48,9 @@ class Obs(C.Structure):
         "pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates",
         "violations", "accepted_total", "rechecks", "overflows", "grid_rebuilds", "wait_timeouts",
         "fallback_cells", "accepted_bead_updates")] + [
-        ("pw_shell_attempts", C.c_int64 * K_SHELLS), ("pw_shell_accepts", C.c_int64 * K_SHELLS)]
+        ("pw_shell_attempts", C.c_int64 * K_SHELLS), ("pw_shell_accepts", C.c_int64 * K_SHELLS),
+        ("member_rechecks", C.c_int64), ("margin_checks", C.c_int64), ("margin_fails", C.c_int64),
+        ("margin_max_ratio", C.c_double)]
 
 
 class TraceRec(C.Structure):
@@ -130,6 +132,7 @@ def make_params(d: dict) -> Params:
     p.accept_rule = ACCEPT[d.get("accept", "metropolis")]
     p.wavelet_map = WAVELET_MAP[d.get("wavelet_map", "linear")]
     p.centring = CENTRING[d.get("centring", "anchor")]
+    p.mixed_verify = int(d.get("mixed_verify", 0))
     return p
 
 
@@ -247,7 +250,8 @@ class WMC:
             d[name] = np.array(getattr(o, name)[:], dtype=np.int64)
         for name in ("pw_chains", "pw_attempts", "pw_accepts", "pw_k0", "pw_caps", "pw_bead_updates", "violations",
                      "accepted_total", "rechecks", "overflows", "grid_rebuilds", "wait_timeouts", "fallback_cells",
-                     "accepted_bead_updates"):
+                     "accepted_bead_updates", "member_rechecks", "margin_checks", "margin_fails",
+                     "margin_max_ratio"):
             d[name] = getattr(o, name)
         for name in ("pw_shell_attempts", "pw_shell_accepts"):
             d[name] = np.array(getattr(o, name)[:], dtype=np.int64)

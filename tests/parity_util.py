@@ -4,6 +4,21 @@ import numpy as np
 
 KEY = ("kind", "system", "sweep", "level", "cell", "trial", "retry")
 
+# Mixed precision against the FP64 oracle. Decisions must be identical (a decision within the FP32
+# error bound is re-evaluated in FP64). The reported dU of a test that was not re-evaluated is the
+# FP32 sum: its terms come from FP32 tile offsets (absolute error ~eps times the tile half-width,
+# so a WCA term near contact is off by up to ~1e-3). Positions carry the FP32 displacements: per
+# accepted move about eps (He/lambda) A of error, summed over the moves of one sweep.
+MIXED_DU_TOL = dict(dU_rtol=1e-3, dU_atol=1e-3, dU_atol_member=2e-3)
+MIXED_POS_RTOL = 1e-6
+
+
+def tolerances(precision):
+    """(trace tolerance kwargs, position rtol) of a parity comparison at this precision."""
+    if precision == "mixed":
+        return MIXED_DU_TOL, MIXED_POS_RTOL
+    return {}, 1e-10
+
 
 def build_pair(cfg, trace=1_000_000, precision="fp64", **over):
     from oracle import oracle as O

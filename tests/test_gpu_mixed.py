@@ -1,0 +1,78 @@
+"""Mixed precision against FP64 over long runs on the GPU: the two precisions start from the same
+state and drift apart through FP32 displacement rounding, so agreement is statistical. The mean
+squared radius of gyration (Sec. VI.A, Eq. "Radius of gyration"), the chain centre-of-mass
+diffusion coefficient (Sec. VI.B) and the one-sweep displacement covariance of bead pairs at
+separation r (the two-tracer covariance of Sec. III) must agree within their statistical errors.
+The numbers are printed as the error report of mixed precision against FP64."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+R_EDGES = np.array([0.8, 1.5, 2.5, 4.0, 6.0])
+
+
+def _run(cfg, precision, blocks, per_block, pair_sweeps):
+    from scipy.spatial import cKDTree
+
+    from paper_1611_09160_amd import wmc
+
+    g = wmc.WMC(dict(cfg["params"], precision=precision), cfg["sys_offset"], cfg["chain_offset"], cfg["pos"],
+                trace_capacity=0)
+    L = cfg["params"]["box_L"]
+    rg = []
+    for _ in range(blocks):
+        g.sweep(per_block)
+        rg.append(g.chain_rg2().mean())
+    tau = float(g.tau()[0])
+    msd = g.chain_msd()
+    # displacement covariance of bead pairs (different beads, any chain) by their separation at the
+    # start of each sweep
+    per_sweep = []  # each sweep's mean covariance per bin: the sweeps are the independent samples
+    before = g.positions()
+    for _ in range(pair_sweeps):
+        g.sweep(1)
+        after = g.positions()
+        d = after - before
+        tree = cKDTree(np.mod(before, L), boxsize=L)
+        pairs = tree.query_pairs(R_EDGES[-1], output_type="ndarray")
+        sep = before[pairs[:, 0]] - before[pairs[:, 1]]
+        sep -= L * np.round(sep / L)
+        r = np.sqrt((sep ** 2).sum(1))
+        dd = (d[pairs[:, 0]] * d[pairs[:, 1]]).sum(1)
+        b = np.digitize(r, R_EDGES) - 1
+        ok = (b >= 0) & (b < len(R_EDGES) - 1)
+        per_sweep.append(np.bincount(b[ok], dd[ok], len(R_EDGES) - 1) / np.bincount(b[ok], None, len(R_EDGES) - 1))
+        before = after
+    ob = g.observables()
+    g.close()
+    ps = np.array(per_sweep)
+    return dict(rg=np.array(rg), tau=tau, msd=msd, cov=ps.mean(0), cov_se=ps.std(0, ddof=1) / np.sqrt(len(ps)),
+                rechecks=ob["rechecks"], member_rechecks=ob["member_rechecks"], attempts=int(ob["attempts"].sum()))
+
+
+def test_mixed_long_run_statistics():
+    from paper_1611_09160_amd import workloads as W
+
+    cfg = W.config(3, scale=0.25)  # 64 chains x 128 beads, the semi-dilute density
+    res = {p: _run(cfg, p, blocks=30, per_block=10, pair_sweeps=40) for p in ("fp64", "mixed")}
+    f, m = res["fp64"], res["mixed"]
+    # R_g^2: after a 5-block burn-in, standard error of each run from the means of 5 batches of 5
+    # blocks (50 sweeps each: consecutive blocks are correlated)
+    rf, rm = f["rg"][5:].reshape(5, 5).mean(1), m["rg"][5:].reshape(5, 5).mean(1)
+    se = np.hypot(rf.std(ddof=1), rm.std(ddof=1)) / np.sqrt(len(rf))
+    print(f"R_g^2: fp64 {rf.mean():.5f} mixed {rm.mean():.5f} (difference {rm.mean() - rf.mean():+.2e}, "
+          f"standard error {se:.2e})")
+    assert abs(rm.mean() - rf.mean()) <= 4.0 * se + 1e-9
+    # chain centre-of-mass diffusion: D = <dr^2>/(6 tau) over the chains
+    Df, Dm = f["msd"].mean() / (6 * f["tau"]), m["msd"].mean() / (6 * m["tau"])
+    seD = np.hypot(f["msd"].std(ddof=1) / f["tau"], m["msd"].std(ddof=1) / m["tau"]) / np.sqrt(len(f["msd"])) / 6
+    print(f"D_cm: fp64 {Df:.5e} mixed {Dm:.5e} (difference {Dm - Df:+.2e}, standard error {seD:.2e})")
+    assert abs(Dm - Df) <= 4.0 * seD + 1e-15
+    # two-tracer displacement covariance per separation bin
+    for i in range(len(R_EDGES) - 1):
+        s = np.hypot(f["cov_se"][i], m["cov_se"][i])
+        print(f"cov r in [{R_EDGES[i]}, {R_EDGES[i + 1]}): fp64 {f['cov'][i]:.4e} mixed {m['cov'][i]:.4e} "
+              f"(standard error {s:.1e})")
+        assert abs(m["cov"][i] - f["cov"][i]) <= 5.0 * s
+    print(f"mixed: {m['attempts']} tests, {m['rechecks']} decision rechecks, {m['member_rechecks']} support rechecks")
