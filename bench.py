@@ -12,8 +12,9 @@ A step is one sweep. Prints one JSON line:
   roofline      the dominant kernel class, timed with HIP events on the library's stream, beside
                 the bandwidth of a plain 1 GiB device copy measured in the same run
   cpu_baseline  the FP64 oracle on the host, on a bounded sample of sweeps of the same state
-  mixed         the same system in mixed precision (FP32 energy terms, FP64 recheck near the
-                threshold), from the FP64 run's final state
+  mixed         the same system in mixed precision (FP32 LDS tiles: offsets, displacements,
+                distances and energy terms; FP64 positions; FP64 recheck near the threshold),
+                from the FP64 run's final state
   batched       mixed precision on many systems at once: 8 independent copies of the solution,
                 and the 32,768 beads as 8 smaller solutions of the same chains and concentration;
                 ratio_vs_fp64 compares with the single-system FP64 value
@@ -268,6 +269,7 @@ def main():
                    ratio_vs_fp64=round(rmix["bead_updates_per_s"] / r64["bead_updates_per_s"], 3)),
         batched=batched, other_workloads=others,
         kernel_ms_fp64={k: [round(v[0], 3), v[1]] for k, v in kt.items()},
+        kernel_ms_mixed={k: [round(v[0], 3), v[1]] for k, v in rmix["kernel_ms"].items()},
         checks=dict(overflows=r64["overflows"] + rmix["overflows"], violations=r64["violations"],
                     wait_timeouts=r64["wait_timeouts"] + rmix["wait_timeouts"]),
     )

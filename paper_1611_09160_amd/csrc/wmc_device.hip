@@ -427,6 +427,32 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     for (int i = 0; i < W / 64; ++i) t += red[i];
     return t;
 }
+// three sums in one exchange (red holds 3 W/64 entries)
+template <int W>
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* red) {
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+        c += __shfl_xor(c, o);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        red[3 * wv] = a;
+        red[3 * wv + 1] = b;
+        red[3 * wv + 2] = c;
+    }
+    __syncthreads();
+    double ta = 0.0, tb = 0.0, tc = 0.0;
+    for (int i = 0; i < W / 64; ++i) {
+        ta += red[3 * i];
+        tb += red[3 * i + 1];
+        tc += red[3 * i + 2];
+    }
+    a = ta;
+    b = tb;
+    c = tc;
+}
 template <int W>
 __device__ __forceinline__ double block_max(double v, double* red) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
@@ -1242,9 +1268,11 @@ struct TileShared {
     // recomputed when needed)
     T MX[CAPM > 0 ? CAPM : 1], MY[CAPM > 0 ? CAPM : 1], MZ[CAPM > 0 ? CAPM : 1];
     double red[W / 64 > 0 ? W / 64 : 1];
+    double red3[3 * (W / 64 > 0 ? W / 64 : 1)];
     int redi[W / 64 > 0 ? W / 64 : 1];
     int count;
-    double pub_b[3];
+    double pub_b[3];  // the centre; on an FP32 tile with anchored centres the ball vector V
+    float pub_bf[3];  // FP32 tile: the centre's offset from the tile centre
     double pub_lam;
     int32_t pub_a;
     uint32_t pub_next;
@@ -1541,7 +1569,8 @@ template <int W, int CAPH, int CAPM, int NCD, class T = double, class WV = WaveD
 __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                         const TileShared<W, CAPH, CAPM, NCD, T>& sh, const Grid& g, const TileGeo& tg,
                         const WV& wv, double R,
-                        int nH, int n, int mode, double& acc, double& sens, unsigned long long& viol) {
+                        int nH, int n, int mode, double& acc, double& sens, unsigned long long& viol,
+                        float rc2g = 0.0f) {
     constexpr bool F32 = std::is_same<T, float>::value;
     auto cur = [&](int sl, double& x, double& y, double& z) {
         if constexpr (F32) {
@@ -1635,11 +1664,28 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
             const int p0 = sh.cst[row + tile_clamp(tg, ux - R)], p1 = sh.cst[row + tile_clamp(tg, ux + R) + 1];
             double kx, ky, kz;
             trial(k, sl, kx, ky, kz);
+            float mw0 = 0.0f, mw1 = 0.0f, mw2 = 0.0f;
+            if constexpr (F32) member_w32(sh, wv, k, sl, mw0, mw1, mw2);
             for (int pp = p0; pp < p1; ++pp) {
                 const int m = sh.kc[pp];
                 if (m == sl) continue;
                 const int tm = tile_tag(sh, m);
                 if (tm >= 0 && m < sl) continue;
+                if constexpr (F32) {
+                    // FP32 tile: only pairs that FP32 places within the widened cut-off can be within
+                    // the cut-off in FP64 (rc2g exceeds the FP32 error of r2), so only those are read
+                    // from HBM
+                    // (a pair whose offsets differ by half the box or more is always read)
+                    float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+                    if (tm >= 0) member_w32(sh, wv, tm, m, v0, v1, v2);
+                    const float ex = sh.x[sl] - sh.x[m], ey = sh.y[sl] - sh.y[m], ez = sh.z[sl] - sh.z[m];
+                    const float ro = (ex * ex + ey * ey) + ez * ez;
+                    const float fx = ex + (mw0 - v0), fy = ey + (mw1 - v1), fz = ez + (mw2 - v2);
+                    const float rn = (fx * fx + fy * fy) + fz * fz;
+                    if (fminf(ro, rn) >= rc2g &&
+                        (!g.periodic || 2.0f * (fabsf(ex) + fabsf(ey) + fabsf(ez)) < (float)L))
+                        continue;
+                }
                 double mx, my, mz;
                 cur(m, mx, my, mz);
                 double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
@@ -1954,6 +2000,23 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             pz = sh.z[sl];
         }
     };
+    // FP32 tile, anchored centre b = r_a + lam V: its offset f from the tile centre (= the cell's
+    // centre) is o_a + lam V in FP32, within eps (2 He' + lam) of the exact offset; the cell test
+    // |f| < h/2 per axis is exact unless f lies within 16 times that of a face, where the FP64 test
+    // runs on the anchor's position from HBM
+    const float hh = (float)g.half;
+    auto hit_f32 = [&](int a, double lm, double vx, double vy, double vz, float& f0, float& f1, float& f2) -> bool {
+        f0 = sh.x[a] + (float)(lm * vx);
+        f1 = sh.y[a] + (float)(lm * vy);
+        f2 = sh.z[a] + (float)(lm * vz);
+        const float m = fmaxf(fabsf(f0), fmaxf(fabsf(f1), fabsf(f2)));
+        const float tb = (float)(0x1p-20 * (tg.He + Etot + lm));
+        if (m < hh - tb) return true;
+        if (m > hh + tb) return false;
+        double ax, ay, az;
+        slot_pos(a, ax, ay, az);
+        return cell_of_point(g, ax + lm * vx, ay + lm * vy, az + lm * vz) == cell;
+    };
     for (int64_t t0 = 0; t0 < K; t0 += W) {
         const int64_t t = t0 + tid;
         const bool drawn = t < K && (nS > 0 || uni);
@@ -1978,19 +2041,31 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
       for (int from = 0;;) {
         bool hit = false;
         double bx = 0.0, by = 0.0, bz = 0.0;
+        float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
         if (drawn && tid >= from) {
             if (uni) {
                 bx = vx_t;
                 by = vy_t;
                 bz = vz_t;
+                hit = cell_of_point(g, bx, by, bz) == cell;
+                if (F32) {
+                    f0 = (float)minimg(g, bx - tg.c[0]);
+                    f1 = (float)minimg(g, by - tg.c[1]);
+                    f2 = (float)minimg(g, bz - tg.c[2]);
+                }
+            } else if (F32) {
+                bx = vx_t;
+                by = vy_t;
+                bz = vz_t;
+                hit = hit_f32(as_t, lam_t, vx_t, vy_t, vz_t, f0, f1, f2);
             } else {
                 double ax, ay, az;
                 slot_pos(as_t, ax, ay, az);
                 bx = ax + lam_t * vx_t;
                 by = ay + lam_t * vy_t;
                 bz = az + lam_t * vz_t;
+                hit = cell_of_point(g, bx, by, bz) == cell;
             }
-            hit = cell_of_point(g, bx, by, bz) == cell;
         }
         int first = block_min_int<W>(hit ? tid : 0x7FFFFFFF, sh.redi);
         if (first == 0x7FFFFFFF) break;
@@ -2000,13 +2075,23 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             sh.pub_b[0] = bx;
             sh.pub_b[1] = by;
             sh.pub_b[2] = bz;
+            sh.pub_bf[0] = f0;
+            sh.pub_bf[1] = f1;
+            sh.pub_bf[2] = f2;
             sh.pub_next = next_t;
         }
         __syncthreads();
         const int64_t tc = t0 + first;
         double lam = sh.pub_lam;
         int as = sh.pub_a;
-        double b[3] = {sh.pub_b[0], sh.pub_b[1], sh.pub_b[2]};
+        // the chain's centre: kept in registers on an FP64 tile; an FP32 tile reads it from LDS
+        // where needed (pub_b, pub_bf hold it until the chain's next redraw)
+        double b[3] = {0.0, 0.0, 0.0};
+        if constexpr (!F32) {
+            b[0] = sh.pub_b[0];
+            b[1] = sh.pub_b[1];
+            b[2] = sh.pub_b[2];
+        }
         uint32_t nxt = sh.pub_next;
         int jtry = 0;
         ++c_hits;
@@ -2024,9 +2109,9 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             // near |d| = lam (eps = 2^-24, He' = tile half-width plus drift); tolm is 16 times that
             float bf0 = 0.0f, bf1 = 0.0f, bf2 = 0.0f, lam2f = 0.0f, tolm = 0.0f;
             if constexpr (F32) {
-                bf0 = (float)minimg(g, b[0] - tg.c[0]);
-                bf1 = (float)minimg(g, b[1] - tg.c[1]);
-                bf2 = (float)minimg(g, b[2] - tg.c[2]);
+                bf0 = sh.pub_bf[0];
+                bf1 = sh.pub_bf[1];
+                bf2 = sh.pub_bf[2];
                 lam2f = (float)lam2;
                 tolm = (float)(0x1p-20 * (lam * (tg.He + Etot) + 2.0 * lam2));
             }
@@ -2037,9 +2122,18 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                     const float d2 = (dx * dx + dy * dy) + dz * dz;
                     if (fabsf(d2 - lam2f) > tolm) return d2 <= lam2f;
                     ++c_mre;
+                    // the FP64 centre (pub_b holds V for an anchored centre)
+                    double cb[3] = {sh.pub_b[0], sh.pub_b[1], sh.pub_b[2]};
+                    if (!uni) {
+                        double ax, ay, az;
+                        slot_pos(as, ax, ay, az);
+                        cb[0] = ax + lam * cb[0];
+                        cb[1] = ay + lam * cb[1];
+                        cb[2] = az + lam * cb[2];
+                    }
                     const int32_t j = sh.id[sl] & ID_MASK;
-                    const double ex = minimg(g, D.x[j] - b[0]), ey = minimg(g, D.y[j] - b[1]),
-                                 ez = minimg(g, D.z[j] - b[2]);
+                    const double ex = minimg(g, D.x[j] - cb[0]), ey = minimg(g, D.y[j] - cb[1]),
+                                 ez = minimg(g, D.z[j] - cb[2]);
                     return ((ex * ex + ey * ey) + ez * ez) <= lam2;
                 } else {
                     const double dx = minimg(g, sh.x[sl] - b[0]), dy = minimg(g, sh.y[sl] - b[1]),
@@ -2135,25 +2229,35 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             const double thr = accept_threshold<VAR>(P, u_acc);
             double dU;
             if constexpr (F32) {
-                // margin: a coordinate of magnitude <= Hq carries <= 4 eps Hq (offset, displacement
-                // and sum roundings), so a term's r2 is off by <= eps r2 (28 Hq/r + 6.5) and the term
-                // by <= eps sens (28 Hq/r + 24); the margin doubles both coefficients
+                // error of the FP32 sum (eps = 2^-24; every offset magnitude <= Hq). Worst case: an
+                // offset carries <= eps Hq, the centre's <= 3 eps Hq, so x_r is off by <= 5 eps Hq/lambda
+                // per axis and a displacement (A <= A0 lambda) by <= 19 A0 eps Hq; a trial coordinate
+                // by <= eps Hq (2.5 + 19 A0), a distance component by twice that, r2 by <= 2 eps r2
+                // (Hq (8.7 + 66 A0)/r + 1.5), and a term by <= 2 eps sens (Hq (8.7 + 66 A0)/r + 6)
+                // with its own FP32 evaluation. rc2g widens the cut-off by 8 times that r2 bound, so
+                // no pair within the FP64 cut-off is missed. The margin itself,
+                // 2^-23 (16 S1 + 8 Hq S2) with S1 = sum of sens and S2 = sum of sens/r, is smaller
+                // than the worst case (which has all roundings aligned, and ignores that a pair's
+                // offset roundings enter its old and new distance alike): its sufficiency is what the
+                // mixed_verify mode measures (every |dU32 - dU64| against it).
                 const double Hq = tg.He + Etot + dmax;
                 const bool wrap = g.periodic && 2.0 * Hq + P.rc >= L;
                 const double Hm = wrap ? fmax(Hq, L) : Hq;
-                const float rc2g = (float)(P.rc2 * (1.0 + 0x1p-18 * (28.0 * Hm / fmax(P.rc, 1e-3) + 8.0)));
+                const double K2 = 9.0 + 66.0 * P.A0;
+                const float rc2g = (float)(P.rc2 * (1.0 + 0x1p-20 * (K2 * Hm / fmax(P.rc, 1e-3) + 2.0)));
                 float s1 = 0.0f, s2 = 0.0f;
                 tile_dU32<W, CAPH, CAPM, NCD>(P, D, sh, g, tg, wv32, Rq, nH, n, wrap, (float)L, (float)invL,
                                               (float)P.rc2, rc2g, acc, s1, s2, c_viol);
-                dU = block_sum<W>(acc, sh.red);
-                const double S1 = block_sum<W>((double)s1, sh.red), S2 = block_sum<W>((double)s2, sh.red);
-                const double m = 0x1.0p-23 * (64.0 * S1 + 32.0 * Hm * S2) + 1e-12;
+                double S1 = (double)s1, S2 = (double)s2;
+                dU = acc;
+                block_sum3<W>(dU, S1, S2, sh.red3);
+                const double m = 0x1.0p-23 * (16.0 * S1 + 8.0 * Hm * S2) + 1e-12;
                 const bool near = !(isfinite(dU) && fabs(dU - thr) > m);
                 if (near || P.mixed_verify) {
                     double a64 = 0.0, s64 = 0.0;
                     unsigned long long v64 = 0;
                     tile_dU<W, CAPH, CAPM, NCD, float, WaveDesc32>(P, D, s, sh, g, tg, wv32, Rq, nH, n, 0, a64, s64,
-                                                                    v64);
+                                                                    v64, rc2g);
                     const double d64 = block_sum<W>(a64, sh.red);
                     if (tid == 0) {
                         if (near) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
@@ -2244,11 +2348,24 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 int jj = j0 + tid;
                 bool h2 = false;
                 double ex = 0, ey = 0, ez = 0;
+                float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
                 int a2 = 0;
                 Stream rs;
                 if (tid < len && jj < 4096) {
                     rs.init(P, sys, sweep, level, key, tc, r, jj);
-                    h2 = draw_trial_centre<VAR>(P, rs, g, ic, cell, lam, nS, slot_of, slot_pos, a2, ex, ey, ez);
+                    if (F32 && !uni) {
+                        // the draws of draw_trial_centre (anchor, then ball vector), FP32 cell test
+                        a2 = slot_of(rs.index(nS));
+                        ball(rs, ex, ey, ez);
+                        h2 = hit_f32(a2, lam, ex, ey, ez, g0, g1, g2);
+                    } else {
+                        h2 = draw_trial_centre<VAR>(P, rs, g, ic, cell, lam, nS, slot_of, slot_pos, a2, ex, ey, ez);
+                        if (F32) {
+                            g0 = (float)minimg(g, ex - tg.c[0]);
+                            g1 = (float)minimg(g, ey - tg.c[1]);
+                            g2 = (float)minimg(g, ez - tg.c[2]);
+                        }
+                    }
                 }
                 int fj = block_min_int<W>(h2 ? jj : 0x7FFFFFFF, sh.redi);
                 if (fj != 0x7FFFFFFF) {
@@ -2257,6 +2374,9 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                         sh.pub_b[0] = ex;
                         sh.pub_b[1] = ey;
                         sh.pub_b[2] = ez;
+                        sh.pub_bf[0] = g0;
+                        sh.pub_bf[1] = g1;
+                        sh.pub_bf[2] = g2;
                         sh.pub_next = rs.next;
                     }
                     found = fj;
@@ -2270,9 +2390,11 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             }
             c_redraw += (unsigned long long)found;
             as = sh.pub_a;
-            b[0] = sh.pub_b[0];
-            b[1] = sh.pub_b[1];
-            b[2] = sh.pub_b[2];
+            if constexpr (!F32) {
+                b[0] = sh.pub_b[0];
+                b[1] = sh.pub_b[1];
+                b[2] = sh.pub_b[2];
+            }
             nxt = sh.pub_next;
             jtry = found;
             __syncthreads();
