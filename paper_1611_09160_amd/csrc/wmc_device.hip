@@ -165,44 +165,7 @@ __device__ __forceinline__ double accept_threshold(const DevParams& P, double u)
     return -P.kT * log(u);
 }
 
-// FP32 term and its sensitivity together (mixed precision). The cut-off and the FENE limit are
-// applied to the FP64 r2, exactly as in the FP64 terms; the term is then evaluated in FP32. The
-// sensitivity only scales the recheck margin (64 ulp of it, about ten times the rounding it
-// covers), so FP32 suffices; a bond pushed to R0 by rounding gives an infinite term, which
-// forces the recheck.
-__device__ __forceinline__ float u_bond_fs(const DevParams& P, double r2, float& sens) {
-    if (P.bond_type == WMC_BOND_FENE) {
-        const float x = 1.0f - (float)r2 / (float)P.R02;
-        if (r2 >= P.R02 || x <= 0.0f) {
-            sens = INFINITY;
-            return INFINITY;
-        }
-        sens = 0.5f * (float)P.k_bond * (float)r2 / x;
-        return -0.5f * (float)P.k_bond * (float)P.R02 * logf(x);
-    }
-    if (P.bond_type == WMC_BOND_HARMONIC) {
-        sens = 0.5f * (float)P.k_bond * (float)r2;
-        return sens;
-    }
-    sens = 0.0f;
-    return 0.0f;
-}
-__device__ __forceinline__ float u_pair_fs(const DevParams& P, double r2, float& sens) {
-    if (r2 >= P.rc2) {
-        sens = 0.0f;
-        return 0.0f;
-    }
-    const float r2f = (float)r2;
-    if (r2f <= 0.0f) {
-        sens = INFINITY;
-        return INFINITY;
-    }
-    const float s2 = (float)P.sigma2 / r2f, s6 = s2 * s2 * s2, e4 = 4.0f * (float)P.eps;
-    sens = e4 * (6.0f * s6 * s6 + 3.0f * s6);
-    return e4 * (s6 * s6 - s6 + 0.25f);
-}
-
-// The same terms from an FP32 r2 (FP32 tile). sens bounds |r2 dU/dr2| and |U| of the term (for
+// FP32 terms from an FP32 r2 (FP32 tile, mixed precision) with their sensitivity: sens bounds |r2 dU/dr2| and |U| of the term (for
 // WCA 6 s^12 + 3 s^6 >= |s^12 - s^6 + 1/4| inside the cut-off; for FENE r2/(R0^2 - r2) R0^2/2 >=
 // -ln(1 - r2/R0^2) R0^2/2 times x ln x/(x - 1) <= 1), so that one margin covers both the error
 // of r2 and the rounding of the term.
@@ -232,7 +195,8 @@ __device__ __forceinline__ float u_pair_f32(const DevParams& P, float r2, float 
         sens = INFINITY;
         return INFINITY;
     }
-    const float s2 = (float)P.sigma2 / r2, s6 = s2 * s2 * s2, e4 = 4.0f * (float)P.eps;
+    // the hardware reciprocal (1 ulp): its error is one more rounding within the margin's S1 share
+    const float s2 = (float)P.sigma2 * __builtin_amdgcn_rcpf(r2), s6 = s2 * s2 * s2, e4 = 4.0f * (float)P.eps;
     sens = e4 * (6.0f * s6 * s6 + 3.0f * s6);
     return e4 * (s6 * s6 - s6 + 0.25f);
 }
@@ -785,10 +749,9 @@ __device__ __forceinline__ void cell_coords(const DevParams& P, const LevelDesc&
 // displacements and the drift since the build. One work item is a (member, y-z row of grid
 // cells) pair; its x range is one or two contiguous runs of the grid's bead list.
 // Work items are dealt to threads t0, t0 + stride, ... (one workgroup, or a whole grid).
-// mode 0: FP64; mode 1: FP32 terms (acc) with their sensitivity (sens).
 __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, const int32_t* Ml, const double* MXl,
-                        const double* MYl, const double* MZl, int n, double R, int mode, int t0, int stride,
-                        double& acc, double& sens, unsigned long long& viol) {
+                        const double* MYl, const double* MZl, int n, double R, int t0, int stride,
+                        double& acc, unsigned long long& viol) {
     const double L = s.L, invL = s.invL;
     auto term = [&](int32_t j, double jx, double jy, double jz, double kx, double ky, double kz, int32_t m) {
         if (m == j) return;
@@ -798,15 +761,7 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
         const double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my, nz = km >= 0 ? MZl[km] : mz;
         const double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
         const double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
-        if (r2o < P.rc2 || r2n < P.rc2) {
-            if (mode) {
-                float sn, so;
-                acc += (double)(u_pair_fs(P, r2n, sn) - u_pair_fs(P, r2o, so));
-                sens += (double)sn + (double)so;
-            } else {
-                acc += u_pair(P, r2n) - u_pair(P, r2o);
-            }
-        }
+        if (r2o < P.rc2 || r2n < P.rc2) acc += u_pair(P, r2n) - u_pair(P, r2o);
     };
     if (P.bond_type != WMC_BOND_NONE) {
         for (int k = t0; k < n; k += stride) {
@@ -826,13 +781,7 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
                 const double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
                 const double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
                 if (r2o > P.r_int * P.r_int) ++viol;
-                if (mode) {
-                    float sn, so;
-                    acc += (double)(u_bond_fs(P, r2n, sn) - u_bond_fs(P, r2o, so));
-                    sens += (double)sn + (double)so;
-                } else {
-                    acc += u_bond_delta(P, r2n, r2o);
-                }
+                acc += u_bond_delta(P, r2n, r2o);
             }
         }
     }
@@ -881,7 +830,7 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
 
 // Dg bounds the drift, since the neighbour grid was built, of every bead this cell can meet; the
 // largest drift of the beads the cell moves is returned in dl_out.
-template <int W, int CAPS, int CAPM, bool MIXED, bool VAR>
+template <int W, int CAPS, int CAPM, bool VAR>
 __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& D,
                                                        PhaseShared<W, CAPS, CAPM>& sh, int sys,
                              int level, int colour, int64_t local, int64_t sweep, const Grid& g,
@@ -1007,7 +956,6 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
     unsigned long long c_hits = 0, c_att = 0, c_acc = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0;
     double d_local = 0.0;  // max drift of beads moved in this phase
 
-    constexpr bool mixed = MIXED;
     const double L = s.L, invL = s.invL;
     const double lam_hi = lv.hi;
 
@@ -1130,21 +1078,9 @@ __device__ __forceinline__ void process_cell(const DevParams& P, const DevPtrs& 
             double dU;
             const double thr = accept_threshold<VAR>(P, u_acc);
             {
-                double acc = 0.0, sens = 0.0;
-                glob_dU(P, D, s, Ml, MXl, MYl, MZl, n, Rq, mixed ? 1 : 0, tid, W, acc, sens, c_viol);
+                double acc = 0.0;
+                glob_dU(P, D, s, Ml, MXl, MYl, MZl, n, Rq, tid, W, acc, c_viol);
                 dU = block_sum<W>(acc, sh.red);
-                if (mixed) {
-                    // FP32 terms summed in FP64; each FP32 term is within ~4 ulp of r2 and of the
-                    // energy: re-evaluate in FP64 when the decision is within the bound
-                    const double bound = 64.0 * 0x1.0p-23 * block_sum<W>(sens, sh.red) + 1e-12;
-                    if (!(isfinite(dU) && fabs(dU - thr) > bound)) {
-                        double a64 = 0.0, s64 = 0.0;
-                        unsigned long long v64 = 0;
-                        glob_dU(P, D, s, Ml, MXl, MYl, MZl, n, Rq, 0, tid, W, a64, s64, v64);
-                        dU = block_sum<W>(a64, sh.red);
-                        if (tid == 0) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
-                    }
-                }
             }
             const bool accept = dU <= thr;
             if (tid == 0) trace_push(D, 0, sys, sweep, level, key, tc, r, n, accept ? 1 : 0, a, dU, thr);
@@ -1561,16 +1497,14 @@ __device__ __forceinline__ int tile_find(const TileShared<W, CAPH, CAPM, NCD, T>
 // axis) of a member's current position, R covering the cut-off, both displacements and the
 // drift since the list was built. One work item is a (member, y-z row of cells) pair whose
 // x range is contiguous in the list.
-// mode 0: FP64; mode 1: FP32 terms (acc) with their sensitivity (sens).
-// On an FP32 tile (T = float, WV = WaveDesc32) this is the FP64 recheck: the same bonds and pairs
+// FP64 terms. On an FP32 tile (T = float, WV = WaveDesc32) this is the FP64 recheck: the same bonds and pairs
 // (found from the FP32 tile), evaluated from the FP64 positions in HBM plus the FP32 displacements
 // that an accept would apply.
 template <int W, int CAPH, int CAPM, int NCD, class T = double, class WV = WaveDesc>
 __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                         const TileShared<W, CAPH, CAPM, NCD, T>& sh, const Grid& g, const TileGeo& tg,
                         const WV& wv, double R,
-                        int nH, int n, int mode, double& acc, double& sens, unsigned long long& viol,
-                        float rc2g = 0.0f) {
+                        int nH, int n, double& acc, unsigned long long& viol, float rc2g = 0.0f) {
     constexpr bool F32 = std::is_same<T, float>::value;
     auto cur = [&](int sl, double& x, double& y, double& z) {
         if constexpr (F32) {
@@ -1606,7 +1540,11 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
     // 512-thread tile the pair items need every lane)
     const bool split = W == 256 && P.bond_type != WMC_BOND_NONE && P.wca && items <= W - 64;
     const int b0 = split ? tid - (W - 64) : tid, bstride = split ? 64 : W;
-    const int p0 = split ? (tid < W - 64 ? tid : items) : tid, pstride = split ? W - 64 : W;
+    const int p0 = split ? (tid < W - 64 ? tid : 0x3FFFFFFF) : tid, pstride = split ? W - 64 : W;
+    // lanes per pair item: when the items leave lanes idle, G lanes share an item's row of beads
+    // (each takes every G-th), so a lane walks fewer pairs in sequence
+    int G = 1;
+    while (G < 8 && items * 2 * G <= pstride) G <<= 1;
     if (P.bond_type != WMC_BOND_NONE) {
         for (int k = b0 < 0 ? n : b0; k < n; k += bstride) {
             const int sl = sh.M[k];
@@ -1639,18 +1577,13 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                 double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
                 double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
                 if (r2o > P.r_int * P.r_int) ++viol;
-                if (mode) {
-                    float sn, so;
-                    acc += (double)(u_bond_fs(P, r2n, sn) - u_bond_fs(P, r2o, so));
-                    sens += (double)sn + (double)so;
-                } else {
-                    acc += u_bond_delta(P, r2n, r2o);
-                }
+                acc += u_bond_delta(P, r2n, r2o);
             }
         }
     }
     if (P.wca) {
-        for (int it = p0; it < items; it += pstride) {
+        for (int ig = p0; ig < items * G; ig += pstride) {
+            const int it = ig / G, sub = ig - it * G;
             const int k = it / per, q = it - k * per;
             const int qy = q % NR, qz = q / NR;
             const int sl = sh.M[k];
@@ -1666,7 +1599,7 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
             trial(k, sl, kx, ky, kz);
             float mw0 = 0.0f, mw1 = 0.0f, mw2 = 0.0f;
             if constexpr (F32) member_w32(sh, wv, k, sl, mw0, mw1, mw2);
-            for (int pp = p0; pp < p1; ++pp) {
+            for (int pp = p0 + sub; pp < p1; pp += G) {
                 const int m = sh.kc[pp];
                 if (m == sl) continue;
                 const int tm = tile_tag(sh, m);
@@ -1692,15 +1625,7 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                 double nx = mx, ny = my, nz = mz;
                 if (tm >= 0) trial(tm, m, nx, ny, nz);
                 double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
-                if (r2o < P.rc2 || r2n < P.rc2) {
-                    if (mode) {
-                        float sn, so;
-                        acc += (double)(u_pair_fs(P, r2n, sn) - u_pair_fs(P, r2o, so));
-                        sens += (double)sn + (double)so;
-                    } else {
-                        acc += u_pair(P, r2n) - u_pair(P, r2o);
-                    }
-                }
+                if (r2o < P.rc2 || r2n < P.rc2) acc += u_pair(P, r2n) - u_pair(P, r2o);
             }
         }
     }
@@ -1715,6 +1640,8 @@ __device__ void tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared
                           const Grid& g, const TileGeo& tg, const WaveDesc32& wv, double R, int nH, int n, bool wrap,
                           float Lf, float invLf, float rc2f, float rc2g, double& acc, float& s1, float& s2,
                           unsigned long long& viol) {
+    // the margin sums need only a few correct digits: hardware reciprocal square root (1 ulp)
+    auto rsq = [](float v) { return __builtin_amdgcn_rsqf(v); };
     const int tid = threadIdx.x;
     const float rint2 = (float)(P.r_int * P.r_int);
     const int NR = min(tg.nc, (int)floor(2.0 * R * tg.invf) + 2);
@@ -1722,7 +1649,11 @@ __device__ void tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared
     const int items = n * per;
     const bool split = W == 256 && P.bond_type != WMC_BOND_NONE && P.wca && items <= W - 64;
     const int b0 = split ? tid - (W - 64) : tid, bstride = split ? 64 : W;
-    const int p0 = split ? (tid < W - 64 ? tid : items) : tid, pstride = split ? W - 64 : W;
+    const int p0 = split ? (tid < W - 64 ? tid : 0x3FFFFFFF) : tid, pstride = split ? W - 64 : W;
+    // lanes per pair item: when the items leave lanes idle, G lanes share an item's row of beads
+    // (each takes every G-th), so a lane walks fewer pairs in sequence
+    int G = 1;
+    while (G < 8 && items * 2 * G <= pstride) G <<= 1;
     if (P.bond_type != WMC_BOND_NONE) {
         for (int k = b0 < 0 ? n : b0; k < n; k += bstride) {
             const int sl = sh.M[k];
@@ -1764,13 +1695,14 @@ __device__ void tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared
                 float sn, so;
                 acc += (double)(u_bond_f32(P, r2n, sn) - u_bond_f32(P, r2o, so));
                 s1 += sn + so;
-                s2 += sn * rsqrtf(r2n) + so * rsqrtf(r2o);
+                s2 += sn * rsq(r2n) + so * rsq(r2o);
             }
         }
     }
     if (P.wca) {
         const float sc = 12.0f * (float)P.eps;  // sensitivity at the cut-off, 4 eps (6/4 + 3/2)
-        for (int it = p0; it < items; it += pstride) {
+        for (int ig = p0; ig < items * G; ig += pstride) {
+            const int it = ig / G, sub = ig - it * G;
             const int k = it / per, q = it - k * per;
             const int qy = q % NR, qz = q / NR;
             const int sl = sh.M[k];
@@ -1784,7 +1716,7 @@ __device__ void tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared
             float w0, w1, w2;
             member_w32(sh, wv, k, sl, w0, w1, w2);
             const float kx = jx + w0, ky = jy + w1, kz = jz + w2;
-            for (int pp = q0; pp < q1; ++pp) {
+            for (int pp = q0 + sub; pp < q1; pp += G) {
                 const int m = sh.kc[pp];
                 if (m == sl) continue;
                 const int tm = tile_tag(sh, m);
@@ -1805,10 +1737,10 @@ __device__ void tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared
                     float sn, so;
                     acc += (double)(u_pair_f32(P, r2n, rc2f, sn) - u_pair_f32(P, r2o, rc2f, so));
                     s1 += sn + so;
-                    s2 += sn * rsqrtf(r2n) + so * rsqrtf(r2o);
+                    s2 += sn * rsq(r2n) + so * rsq(r2o);
                 } else if (m2 < rc2g) {
                     s1 += sc;
-                    s2 += sc * rsqrtf(m2);
+                    s2 += sc * rsq(m2);
                 }
             }
         }
@@ -1980,7 +1912,6 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     unsigned long long c_hits = 0, c_att = 0, c_acc = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0;
     unsigned long long c_mre = 0;  // FP32 support tests rechecked in FP64
     double d_local = 0.0;
-    constexpr bool mixed = MIXED;
     // trials are drawn W at a time (one per lane); the draws (lambda, anchor, ball vector, stream
     // position) do not depend on positions, so a lane keeps its trial across the chains of earlier
     // hits and only its hit test, which reads the anchor's current position, is repeated (a uniform
@@ -2225,7 +2156,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             // than its rounding)
             const double dmax = block_max<W>(dmax_l, sh.red) * (F32 ? 1.0 + 0x1p-20 : 1.0);
             const double Rq = P.rc + 2.0 * dmax + E + 1e-9 * L;
-            double acc = 0.0, sens = 0.0;
+            double acc = 0.0;
             const double thr = accept_threshold<VAR>(P, u_acc);
             double dU;
             if constexpr (F32) {
@@ -2254,10 +2185,10 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 const double m = 0x1.0p-23 * (16.0 * S1 + 8.0 * Hm * S2) + 1e-12;
                 const bool near = !(isfinite(dU) && fabs(dU - thr) > m);
                 if (near || P.mixed_verify) {
-                    double a64 = 0.0, s64 = 0.0;
+                    double a64 = 0.0;
                     unsigned long long v64 = 0;
-                    tile_dU<W, CAPH, CAPM, NCD, float, WaveDesc32>(P, D, s, sh, g, tg, wv32, Rq, nH, n, 0, a64, s64,
-                                                                    v64, rc2g);
+                    tile_dU<W, CAPH, CAPM, NCD, float, WaveDesc32>(P, D, s, sh, g, tg, wv32, Rq, nH, n, a64, v64,
+                                                                    rc2g);
                     const double d64 = block_sum<W>(a64, sh.red);
                     if (tid == 0) {
                         if (near) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
@@ -2277,18 +2208,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                     if (near) dU = d64;
                 }
             } else {
-                tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, mixed ? 1 : 0, acc, sens, c_viol);
+                tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, acc, c_viol);
                 dU = block_sum<W>(acc, sh.red);
-                if (mixed) {
-                    double bound = 64.0 * 0x1.0p-23 * block_sum<W>(sens, sh.red) + 1e-12;
-                    if (!(isfinite(dU) && fabs(dU - thr) > bound)) {
-                        double a64 = 0.0, s64 = 0.0;
-                        unsigned long long v64 = 0;
-                        tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, 0, a64, s64, v64);
-                        dU = block_sum<W>(a64, sh.red);
-                        if (tid == 0) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
-                    }
-                }
             }
             const bool accept = dU <= thr;
             if (tid == 0)
@@ -2449,7 +2370,9 @@ __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, 
         if (lv.use_global || !process_cell_tile<W, CAPH, CAPMT, NCD, MIXED, VAR>(P, D, sh.t, sys, level, colour, local, sweep, g,
                                                                             Dg, dl)) {
             __syncthreads();
-            process_cell<W, CAPS, CAPM, MIXED, VAR>(P, D, sh.g, sys, level, colour, local, sweep, g, Dg, dl);
+            // global-list cells compute in FP64 in both precisions (their time is not arithmetic: FP32
+            // terms with the recheck margin measured slower there)
+            process_cell<W, CAPS, CAPM, VAR>(P, D, sh.g, sys, level, colour, local, sweep, g, Dg, dl);
         }
         if (threadIdx.x == 0 && dl > 0.0) atomic_max_double(&D.drift_col[8 * sys + colour], dl);
     } else {
@@ -2464,7 +2387,7 @@ __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, 
         int64_t cells = mx * my * mz;
         double dl = 0.0;
         for (int64_t local = blockIdx.x; local < cells; local += gridDim.x)
-            process_cell<W, CAPS, CAPM, MIXED, VAR>(P, D, sh.g, 0, level, colour, local, sweep, g, 0.0, dl);
+            process_cell<W, CAPS, CAPM, VAR>(P, D, sh.g, 0, level, colour, local, sweep, g, 0.0, dl);
     }
 }
 
@@ -2513,7 +2436,7 @@ void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, 
 constexpr unsigned FLOW_SPIN_LIMIT = 1u << 24;
 
 template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, bool MIXED, bool VAR>
-__global__ __launch_bounds__(W, (W == 64 || MIXED) ? 2 : 1) void k_level_flow(DevParams P, DevPtrs D, int level, int64_t sweep,
+__global__ __launch_bounds__(W, W == 64 ? 2 : 1) void k_level_flow(DevParams P, DevPtrs D, int level, int64_t sweep,
                                                      const int32_t* items, FlowArgs fa) {
     __shared__ PhaseLDS<W, CAPS, CAPM, CAPH, CAPMT, NCD, typename std::conditional<MIXED, float, double>::type> sh;
     __shared__ int s_idx;
@@ -2575,7 +2498,7 @@ __global__ __launch_bounds__(W, (W == 64 || MIXED) ? 2 : 1) void k_level_flow(De
         // frame and the registers saved around it, for every cell)
         __syncthreads();
         if (tid == 0) atomicAdd(&D.cnt[CNT_FALLBACK], 1ull);
-        process_cell<W, CAPS, CAPM, MIXED, VAR>(P, D, sh.g, sys, level, colour, local, sweep, g, Dg, dl);
+        process_cell<W, CAPS, CAPM, VAR>(P, D, sh.g, sys, level, colour, local, sweep, g, Dg, dl);
     }
     // publish: every wave's stores complete, then this cell's drift and one release of the epoch
     __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -2669,7 +2592,7 @@ __device__ __forceinline__ double coop_max(const double* part, int G, CoopShared
 
 // one cell of colour `colour` for the group `grp` (index gi); gen is the group's barrier
 // generation and Dg its system's drift bound, both carried from colour to colour
-template <bool MIXED, bool VAR>
+template <bool VAR>
 __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
                           const CoopGroup grp, int gi, int rank, CoopShared& sh, unsigned& gen, double& Dg) {
     const int sys = grp.sys;
@@ -2695,8 +2618,6 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
     int32_t* ccnt = D.coop_i + grp.first;
     double* c_dmax = D.coop_d + grp.first;
     double* c_acc = D.coop_d + COOP_SLOTS + grp.first;
-    double* c_sens = D.coop_d + 2 * COOP_SLOTS + grp.first;
-    double* c_a64 = D.coop_d + 3 * COOP_SLOTS + grp.first;
     double* c_dl = D.coop_d + 4 * COOP_SLOTS + grp.first;
 
     // ---- 1. reach list, bead order
@@ -2734,10 +2655,8 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
         if (ms.co() < mu - (double)K) K += 1;
     }
     if (K > 0xFFFFF) K = 0xFFFFF;
-    unsigned long long c_hits = 0, c_att = 0, c_acc_n = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0,
-                       c_rechk = 0;
+    unsigned long long c_hits = 0, c_att = 0, c_acc_n = 0, c_caps = 0, c_redraw = 0, c_beads = 0, c_viol = 0;
     double dloc = 0.0;  // largest drift of beads moved in this phase (same in every workgroup)
-    constexpr bool mixed = MIXED;
     const int qS = (nS + G - 1) / G;
     const int slo = wg * qS, shi = min(nS, slo + qS);
 
@@ -2844,29 +2763,12 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
             const double thr = accept_threshold<VAR>(P, u_acc);
             double dU;
             {
-                double acc = 0.0, sens = 0.0;
-                glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, mixed ? 1 : 0, gt, gstride, acc, sens, c_viol);
+                double acc = 0.0;
+                glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, gt, gstride, acc, c_viol);
                 const double pa = block_sum<CW>(acc, sh.red);
-                const double ps = mixed ? block_sum<CW>(sens, sh.red) : 0.0;
-                if (tid == 0) {
-                    c_acc[wg] = pa;
-                    c_sens[wg] = ps;
-                }
+                if (tid == 0) c_acc[wg] = pa;
                 group_barrier(bar, G, gen);  // 3: partial sums
                 dU = coop_sum(c_acc, G, sh);
-                if (mixed) {
-                    const double bound = 64.0 * 0x1.0p-23 * coop_sum(c_sens, G, sh) + 1e-12;
-                    if (!(isfinite(dU) && fabs(dU - thr) > bound)) {
-                        double a64 = 0.0, s64 = 0.0;
-                        unsigned long long v64 = 0;
-                        glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, 0, gt, gstride, a64, s64, v64);
-                        const double p64 = block_sum<CW>(a64, sh.red);
-                        if (tid == 0) c_a64[wg] = p64;
-                        group_barrier(bar, G, gen);
-                        dU = coop_sum(c_a64, G, sh);
-                        ++c_rechk;
-                    }
-                }
             }
             const bool accept = dU <= thr;
             if (wg == 0 && tid == 0) trace_push(D, 0, sys, sweep, level, key, tc, r, n, accept ? 1 : 0, a, dU, thr);
@@ -2956,7 +2858,6 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
         atomicAdd(&C[5], c_redraw);
         atomicAdd(&C[6], c_beads);
         if (viol_tot) atomicAdd(&D.cnt[CNT_VIOL], viol_tot);
-        if (c_rechk) atomicAdd(&D.cnt[CNT_RECHECK], c_rechk);
         if (c_acc_n) {
             atomicAdd(&D.cnt[CNT_ACCEPTED], c_acc_n);
             atomicAdd(&D.sys_acc[sys], c_acc_n);
@@ -2968,7 +2869,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
     Dg = fmax(Dg, dloc);
 }
 
-template <bool MIXED, bool VAR>
+template <bool VAR>
 __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int level, CoopColours cc, int64_t sweep,
                                                   const CoopGroup* groups, const int32_t* wg_group) {
     __shared__ CoopShared sh;
@@ -2980,7 +2881,7 @@ __global__ __launch_bounds__(CW) void k_cell_coop(DevParams P, DevPtrs D, int le
     double Dg = __longlong_as_double((long long)D.drift[sys]);
     for (int i = 0; i < cc.n; ++i) {
         const CoopGroup* gt = (const CoopGroup*)((const int32_t*)groups + cc.goff[i]);
-        coop_cell<MIXED, VAR>(P, D, level, cc.col[i], sweep, gt[gi], gi, rank, sh, gen, Dg);
+        coop_cell<VAR>(P, D, level, cc.col[i], sweep, gt[gi], gi, rank, sh, gen, Dg);
     }
 }
 
@@ -2989,19 +2890,15 @@ int cell_coop_blocks() {
     if (nb < 0) {
         int dev = 0, per_cu = 0;
         hipDeviceProp_t prop;
-        int per_cu64 = 0;
-        // the smallest occupancy of the instances (precision, variants), so any launch is co-resident
-        int per_v = 0, per_v64 = 0;
+        // the smaller occupancy of the two instances (variants), so any launch is co-resident
+        int per_v = 0;
         if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cell_coop<true, false>, CW, 0) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, k_cell_coop<false, false>, CW, 0) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_v, k_cell_coop<true, true>, CW, 0) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_v64, k_cell_coop<false, true>, CW, 0) != hipSuccess ||
-            std::min(std::min(per_cu, per_cu64), std::min(per_v, per_v64)) < 1)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cell_coop<false>, CW, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_v, k_cell_coop<true>, CW, 0) != hipSuccess ||
+            std::min(per_cu, per_v) < 1)
             nb = 0;
         else
-            nb = std::min(std::min(std::min(per_cu, per_cu64), std::min(per_v, per_v64)) * prop.multiProcessorCount,
-                          COOP_SLOTS);
+            nb = std::min(std::min(per_cu, per_v) * prop.multiProcessorCount, COOP_SLOTS);
     }
     return nb;
 }
@@ -3018,8 +2915,8 @@ bool launch_cell_coop(const DevParams& P, const DevPtrs& D, int level, const Coo
     const int32_t* wp = wg_group;
     void* args[] = {&Pc, &Dc, &lv, &ccc, &sw, &gp, &wp};
     const bool v = uses_variants(P);
-    const void* k = P.precision == WMC_MIXED ? (v ? (const void*)k_cell_coop<true, true> : (const void*)k_cell_coop<true, false>)
-                                             : (v ? (const void*)k_cell_coop<false, true> : (const void*)k_cell_coop<false, false>);
+    // cell groups compute in FP64 in both precisions, as the global-list cells
+    const void* k = v ? (const void*)k_cell_coop<true> : (const void*)k_cell_coop<false>;
     return hipLaunchCooperativeKernel(k, dim3(nwg), dim3(CW), args, 0, st) == hipSuccess;
 }
 
