@@ -4,7 +4,9 @@ Workload: semi-dilute periodic solution, 256 chains x 128 beads (32,768 beads), 
 box L = 84 (c/c* ~ 1), wavelet levels lambda = 1 .. L/4 in octave bands plus plane waves,
 A0 = 0.5, synthetic self-avoiding random-walk start, 200 equilibration sweeps.
 
-A step is one sweep. Prints one JSON line:
+A step is one sweep. Before the timed sweeps every run tunes its launches from its equilibrated
+state (wmc_tune, which restores that state; `--tune 0` keeps the plan's launches) and reports the
+choices in `tuning`. Prints one JSON line:
   value         bead-updates/s of the timed sweeps (beads displaced per Metropolis test,
                 wavelet and plane wave, accepted or not, summed; inputs resident in HBM)
   tau_per_wall_s  physical time (units of tau) advanced per wall-clock second
@@ -69,7 +71,7 @@ def algorithmic_bytes_per_sweep(cls: str, N: int, n_fine: int, pw_attempts_per_s
     return 0.0
 
 
-def run_gpu(cfg, precision: str, equilibrate: int, warmup: int, steps: int, start=None):
+def run_gpu(cfg, precision: str, equilibrate: int, warmup: int, steps: int, start=None, tune: int = 0):
     import numpy as np
     import torch
 
@@ -79,6 +81,8 @@ def run_gpu(cfg, precision: str, equilibrate: int, warmup: int, steps: int, star
                 cfg["pos"] if start is None else start)
     if start is None:
         g.sweep(equilibrate)
+    # launch tuning from the equilibrated state (the tuner restores that state), outside the timing
+    tuned = g.tune(tune) if tune > 0 else None
     g.sweep(warmup)
     torch.cuda.synchronize()
     o0 = g.observables()
@@ -102,18 +106,24 @@ def run_gpu(cfg, precision: str, equilibrate: int, warmup: int, steps: int, star
                     zip(o1["accepts"] - o0["accepts"], o1["attempts"] - o0["attempts"]) if b > 0],
         pw_attempts=int(o1["pw_attempts"] - o0["pw_attempts"]), overflows=int(o1["overflows"]),
         violations=int(o1["violations"]), wait_timeouts=int(o1["wait_timeouts"]), rechecks=int(o1["rechecks"] - o0["rechecks"]), kernel_ms=kt,
+        tuning=None if tuned is None else {
+            "levels": [(f"tile:{lv['pass']}/{lv['variant']}" + (f"/{lv['width']}" if lv["width"] else "")
+                        if "tile" in lv["cells"] else "") + (" " if lv["cells"] == "tile+global" else "") +
+                       (("global:" + ("groups" if lv["groups"] == "on" else "cells") + f"/{lv['variant']}")
+                        if "global" in lv["cells"] else "") for lv in tuned["levels"]],
+            "plane_wave_groups": tuned["plane_wave_groups"], "trial_sweeps": tuned["trial_sweeps"]},
     )
     return g, res
 
 
-def run_batched(cfg, precision: str, equilibrate: int, warmup: int, steps: int) -> dict:
+def run_batched(cfg, precision: str, equilibrate: int, warmup: int, steps: int, tune: int = 0) -> dict:
     """Many independent systems advanced together (one launch per level and colour serves all)."""
-    g, r = run_gpu(cfg, precision, equilibrate, warmup, steps)
+    g, r = run_gpu(cfg, precision, equilibrate, warmup, steps, tune=tune)
     nsys = len(cfg["sys_offset"]) - 1
     out = dict(value=round(r["bead_updates_per_s"], 1), unit="bead-updates/s", ms_per_step=round(r["ms_per_step"], 3),
                accepted_bead_updates_per_s=round(r["accepted_bead_updates_per_s"], 1), systems=nsys, beads=int(cfg["sys_offset"][-1]), precision=precision,
                tau_per_wall_s_per_system=round(r["tau_per_wall_s"] / nsys, 4),
-               tau_per_wall_s_total=round(r["tau_per_wall_s"], 4), overflows=r["overflows"],
+               tau_per_wall_s_total=round(r["tau_per_wall_s"], 4), overflows=r["overflows"], tuning=r["tuning"],
                kernel_ms={k: [round(v[0], 3), v[1]] for k, v in r["kernel_ms"].items()})
     g.close()
     return out
@@ -187,6 +197,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-others", action="store_true", help="skip the dilute and ideal-chain lines")
     ap.add_argument("--batch-equilibrate", type=int, default=100)
+    ap.add_argument("--tune", type=int, default=3, metavar="K",
+                    help="launch tuning before the timed sweeps, K trial sweeps per choice (0: the plan's launches)")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MB",
                     help="only copy a buffer of MB megabytes 4 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -218,10 +230,10 @@ def main():
 
     cfg = W.config(3)
     N = int(cfg["sys_offset"][-1])
-    g64, r64 = run_gpu(cfg, "fp64", args.equilibrate, args.warmup, args.steps)
+    g64, r64 = run_gpu(cfg, "fp64", args.equilibrate, args.warmup, args.steps, tune=args.tune)
     start = g64.positions()
     sweep0 = args.equilibrate + args.warmup + args.steps
-    gm, rmix = run_gpu(cfg, "mixed", 0, args.warmup, args.steps, start=start)
+    gm, rmix = run_gpu(cfg, "mixed", 0, args.warmup, args.steps, start=start, tune=args.tune)
     # roofline of the dominant kernel class of the FP64 run (a level's LDS-tile cells run as one
     # launch per sweep; its global-list cells, if any, as one launch per colour)
     kt = r64["kernel_ms"]
@@ -247,8 +259,9 @@ def main():
     gm.close()
     batched = None
     if not args.no_batched:
-        copies = run_batched(W.replicas(3, 8), "mixed", args.batch_equilibrate, args.warmup, args.steps)
-        split = run_batched(W.batch_semidilute(8, 32), "mixed", args.batch_equilibrate, args.warmup, args.steps)
+        copies = run_batched(W.replicas(3, 8), "mixed", args.batch_equilibrate, args.warmup, args.steps, args.tune)
+        split = run_batched(W.batch_semidilute(8, 32), "mixed", args.batch_equilibrate, args.warmup, args.steps,
+                            args.tune)
         ref = r64["bead_updates_per_s"]
         copies["ratio_vs_fp64"] = round(copies["value"] / ref, 3)
         split["ratio_vs_fp64"] = round(split["value"] / ref, 3)
@@ -270,7 +283,9 @@ def main():
         tau_per_wall_s=round(r64["tau_per_wall_s"], 4), sweeps_per_s=round(r64["sweeps_per_s"], 2),
         accepted_bead_updates_per_s=round(r64["accepted_bead_updates_per_s"], 1),
         acceptance_per_level=r64["acceptance"], roofline=roof, cpu_baseline=cpu,
+        tuning=r64["tuning"],
         mixed=dict(value=round(rmix["bead_updates_per_s"], 1), ms_per_step=round(rmix["ms_per_step"], 3),
+                   tuning=rmix["tuning"],
                    tau_per_wall_s=round(rmix["tau_per_wall_s"], 4), rechecks=rmix["rechecks"],
                    accepted_bead_updates_per_s=round(rmix["accepted_bead_updates_per_s"], 1),
                    ratio_vs_fp64=round(rmix["bead_updates_per_s"] / r64["bead_updates_per_s"], 3)),

@@ -270,6 +270,28 @@ int wmc_philox(const uint32_t ctr[4], const uint32_t key[2], int64_t n, uint32_t
 int wmc_set_timing(wmc_ctx* c, int32_t enable);
 int wmc_kernel_times(wmc_ctx* c, double* ms_out, int64_t* launches_out);
 
+/* Launch tuning (an implementation choice the paper leaves open: how the concurrent moves of
+ * Sec. VII are scheduled on the device; results stay those of the method). Per level, LDS-tile
+ * cells run as one dependency-ordered pass ("flow") or one launch per colour ("colours"), with a
+ * kernel variant at least the planned one ("V64" < "V256" < "V1024": tile capacity and threads per
+ * cell) and, for V64 passes, 64 or 256 threads per cell; global-list cells run as cooperative cell
+ * groups ("groups": "on") or one workgroup per cell ("off"); plane waves likewise.
+ *
+ * wmc_tune: from the current state, times trial_sweeps sweeps (after one untimed sweep) for each
+ * candidate choice of every level at once, keeps the fastest per level, and restores the state
+ * (positions, sweep counter, counters, trace) exactly as it was. It allocates a device copy of the
+ * context's arena while it runs (freed before it returns). json_out (caller-owned, json_bytes)
+ * receives the chosen settings with their times as
+ *   {"trial_sweeps": k, "levels": [{"level": 0, "cells": "tile", "pass": "flow", "variant": "V64",
+ *    "width": 256, "groups": "on", "ms_per_sweep": t}, ...], "plane_wave_groups": "on", ...}
+ * ("cells": which kinds of cell the level has, "tile", "global" or "tile+global"; informative).
+ * Periodic systems with wavelet moves only; WMC_EINVAL otherwise or when json_out is too small.
+ * wmc_set_tuning: applies such a JSON text (fields may be omitted: the plan's choice; unknown
+ * values: WMC_EINVAL, nothing applied). wmc_get_tuning: the settings in force, same format. */
+int wmc_tune(wmc_ctx* c, int32_t trial_sweeps, char* json_out, size_t json_bytes);
+int wmc_set_tuning(wmc_ctx* c, const char* json);
+int wmc_get_tuning(wmc_ctx* c, char* json_out, size_t json_bytes);
+
 const char* wmc_last_error(const wmc_ctx* c);
 void wmc_free(wmc_ctx* c);
 

@@ -2512,12 +2512,12 @@ __global__ __launch_bounds__(W, W == 64 ? 2 : 1) void k_level_flow(DevParams P, 
 
 template <bool M, bool V>
 static void launch_level_flow_t(int variant, const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
-                       const int32_t* items, const FlowArgs& fa, hipStream_t st) {
+                       const int32_t* items, const FlowArgs& fa, int width64, hipStream_t st) {
     if (fa.nitems <= 0) return;
     // the smallest tile: a few thousand cells (one large system) finish sooner with four waves
     // per cell, since the pass is its longest chain of cells; many more cells (a batch) fill the
-    // GPU better with one wave per cell
-    if (variant == V64 && fa.nitems <= 4096)
+    // GPU better with one wave per cell (width64 overrides the rule)
+    if (variant == V64 && (width64 == 256 || (width64 == 0 && fa.nitems <= 4096)))
         hipLaunchKernelGGL((k_level_flow<256, 1024, 256, 512, 32, 8, M, V>), dim3(fa.nitems), dim3(256), 0, st, P, D,
                            level, sweep, items, fa);
     else if (variant == V64)
@@ -2532,14 +2532,14 @@ static void launch_level_flow_t(int variant, const DevParams& P, const DevPtrs& 
 }
 
 void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
-                       const int32_t* items, const FlowArgs& fa, hipStream_t st) {
+                       const int32_t* items, const FlowArgs& fa, int width64, hipStream_t st) {
     const bool v = uses_variants(P);
     if (P.precision == WMC_MIXED) {
-        if (v) launch_level_flow_t<true, true>(variant, P, D, level, sweep, items, fa, st);
-        else launch_level_flow_t<true, false>(variant, P, D, level, sweep, items, fa, st);
+        if (v) launch_level_flow_t<true, true>(variant, P, D, level, sweep, items, fa, width64, st);
+        else launch_level_flow_t<true, false>(variant, P, D, level, sweep, items, fa, width64, st);
     } else {
-        if (v) launch_level_flow_t<false, true>(variant, P, D, level, sweep, items, fa, st);
-        else launch_level_flow_t<false, false>(variant, P, D, level, sweep, items, fa, st);
+        if (v) launch_level_flow_t<false, true>(variant, P, D, level, sweep, items, fa, width64, st);
+        else launch_level_flow_t<false, false>(variant, P, D, level, sweep, items, fa, width64, st);
     }
 }
 

@@ -15,6 +15,9 @@
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
+#include <cctype>
+#include <cstdio>
+#include <cstdlib>
 
 #include <algorithm>
 #include <array>
@@ -48,6 +51,15 @@ struct wmc_ctx {
     int32_t glob_n[WMC_MAX_LEVELS][8];
     unsigned long long flow_handed[WMC_MAX_LEVELS] = {0};  // cells handed out per level so far
     int32_t flow_epoch = 0;
+    // launch choices (wmc_tune / wmc_set_tuning), 0 = the plan's: tile levels run one
+    // dependency-ordered pass (1) or one launch per colour (2), with a kernel variant of at least
+    // the plan's (variant + 1) and, for the smallest, 64 or 256 threads per cell; global-list
+    // levels use their cell groups (1) or one workgroup per cell (2); plane waves likewise
+    int tune_pass[WMC_MAX_LEVELS] = {0};
+    int tune_variant[WMC_MAX_LEVELS] = {0};
+    int tune_width[WMC_MAX_LEVELS] = {0};
+    int tune_groups[WMC_MAX_LEVELS] = {0};
+    int tune_pw = 0;
     int32_t* bmap_dev;
     // cooperative groups (int32 table: CoopGroup records, then the workgroup -> group map)
     std::vector<int32_t> coop_host;
@@ -68,6 +80,7 @@ struct wmc_ctx {
     int64_t t_n[WMC_TIMING_CLASSES] = {0};
     char* arena;
     size_t arena_bytes;
+    size_t arena_used = 0;  // bytes from `arena` (256-B aligned) the context's sub-arrays occupy
     int static_dev = -1;  // device whose library-held arena this context uses (wmc_init_static), else -1
     std::string err;
 };
@@ -1051,6 +1064,7 @@ extern "C" int wmc_init(wmc_ctx** out, const wmc_params* p, int32_t nsys, const 
     char* base = (char*)(((uintptr_t)arena + 255) & ~(uintptr_t)255);
     c->arena = base;
     c->arena_bytes = arena_bytes;
+    c->arena_used = pl.bytes - 256;
     hipStream_t st = (hipStream_t)stream;
     // device parameters
     DevParams& P = c->P;
@@ -1283,18 +1297,29 @@ extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
                     fa.nitems += c->tile_n[l][col];
                     fa.colour_end[col] = fa.nitems;
                 }
-                if (fa.nitems > 0) {
+                const int tv = c->tune_variant[l] > 0 ? std::max(c->phase_variant[l], c->tune_variant[l] - 1)
+                                                      : c->phase_variant[l];
+                if (fa.nitems > 0 && c->tune_pass[l] == 2) {
+                    // one launch per colour: the colour phases in order
+                    for (int col = 0; col < 8; ++col) {
+                        if (c->tile_n[l][col] <= 0) continue;
+                        Timed t(c, 1 + l, st);
+                        launch_phase(tv, c->P, c->D, l, col, sw, c->bmap_dev + 2 * c->tile_off[l][col],
+                                     c->tile_n[l][col], st);
+                    }
+                } else if (fa.nitems > 0) {
                     Timed t(c, 1 + l, st);
                     fa.epoch = ++c->flow_epoch;
                     fa.qbase = c->flow_handed[l];
                     c->flow_handed[l] += (unsigned long long)fa.nitems;
-                    launch_level_flow(c->phase_variant[l], c->P, c->D, l, sw, c->bmap_dev + 2 * c->tile_off[l][0], fa,
-                                      st);
+                    launch_level_flow(tv, c->P, c->D, l, sw, c->bmap_dev + 2 * c->tile_off[l][0], fa,
+                                      c->tune_width[l], st);
                 }
                 // global-list cells colour by colour: cooperative groups, else one workgroup each;
                 // every colour in one group launch when their groups agree
                 bool merged = false;
-                if (c->cmerge[l]) {
+                const bool groups = c->tune_groups[l] != 2;
+                if (c->cmerge[l] && groups) {
                     CoopColours cc;
                     cc.n = 0;
                     int c0 = -1;
@@ -1316,7 +1341,7 @@ extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
                     cc.n = 1;
                     cc.col[0] = col;
                     cc.goff[0] = 0;
-                    if (c->cwg_n[l][col] > 0 &&
+                    if (c->cwg_n[l][col] > 0 && groups &&
                         launch_cell_coop(c->P, c->D, l, cc, sw, (const CoopGroup*)(c->coop_dev + c->cgrp_off[l][col]),
                                          c->coop_dev + c->cwg_off[l][col], c->cwg_n[l][col], st))
                         continue;
@@ -1343,7 +1368,7 @@ extern "C" int wmc_sweep(wmc_ctx* c, int64_t n_sweeps, void* stream) {
             Timed t(c, 17, st);
             // groups of workgroups per system when they fit one cooperative launch, otherwise one
             // workgroup per system
-            if (!(c->pwg_n > 0 && launch_pw_coop(c->P, c->D, sw, (const CoopGroup*)(c->coop_dev + c->pgrp_off),
+            if (!(c->pwg_n > 0 && c->tune_pw != 2 && launch_pw_coop(c->P, c->D, sw, (const CoopGroup*)(c->coop_dev + c->pgrp_off),
                                                  c->coop_dev + c->pwg_off, c->pwg_n, st)))
                 launch_pw(c->P, c->D, sw, c->nsys, st);
         }
@@ -1371,6 +1396,246 @@ extern "C" int wmc_kernel_times(wmc_ctx* c, double* ms_out, int64_t* n_out) {
     for (int i = 0; i < WMC_TIMING_CLASSES; ++i) {
         if (ms_out) ms_out[i] = c->t_ms[i];
         if (n_out) n_out[i] = c->t_n[i];
+    }
+    return 0;
+}
+
+// ------------------------------------------------------------------- launch tuning
+namespace {
+const char* kVariantName[3] = {"V64", "V256", "V1024"};
+
+// the current launch choices as JSON (times per level appended when given)
+std::string tuning_json(const wmc_ctx* c, const std::vector<double>* level_ms, double pw_ms, int trial_sweeps) {
+    std::string s = "{\"trial_sweeps\": " + std::to_string(trial_sweeps) + ", \"levels\": [";
+    for (int l = 0; l < c->max_levels; ++l) {
+        const int v = c->tune_variant[l] > 0 ? std::max(c->phase_variant[l], c->tune_variant[l] - 1) : c->phase_variant[l];
+        int ntile = 0, nglob = 0;
+        for (int col = 0; col < 8; ++col) {
+            ntile += c->tile_n[l][col];
+            nglob += c->glob_n[l][col];
+        }
+        char buf[360];
+        snprintf(buf, sizeof(buf),
+                 "%s{\"level\": %d, \"cells\": \"%s\", \"pass\": \"%s\", \"variant\": \"%s\", \"width\": %d, "
+                 "\"groups\": \"%s\"",
+                 l ? ", " : "", l, ntile && nglob ? "tile+global" : (ntile ? "tile" : "global"),
+                 c->tune_pass[l] == 2 ? "colours" : "flow", kVariantName[v], c->tune_width[l],
+                 c->tune_groups[l] == 2 ? "off" : "on");
+        s += buf;
+        if (level_ms) {
+            snprintf(buf, sizeof(buf), ", \"ms_per_sweep\": %.4f", (*level_ms)[l]);
+            s += buf;
+        }
+        s += "}";
+    }
+    s += std::string("], \"plane_wave_groups\": \"") + (c->tune_pw == 2 ? "off" : "on") + "\"";
+    if (level_ms) {
+        char buf[64];
+        snprintf(buf, sizeof(buf), ", \"plane_wave_ms_per_sweep\": %.4f", pw_ms);
+        s += buf;
+    }
+    return s + "}";
+}
+
+// value of "key" in a flat JSON object text (a string without its quotes, or a number), or ""
+std::string json_field(const std::string& obj, const char* key) {
+    const std::string k = std::string("\"") + key + "\"";
+    size_t p = obj.find(k);
+    if (p == std::string::npos) return "";
+    p = obj.find(':', p + k.size());
+    if (p == std::string::npos) return "";
+    ++p;
+    while (p < obj.size() && (obj[p] == ' ' || obj[p] == '\n' || obj[p] == '\t')) ++p;
+    if (p < obj.size() && obj[p] == '"') {
+        const size_t e = obj.find('"', p + 1);
+        return e == std::string::npos ? "" : obj.substr(p + 1, e - p - 1);
+    }
+    size_t e = p;
+    while (e < obj.size() && (isalnum((unsigned char)obj[e]) || obj[e] == '-' || obj[e] == '.')) ++e;
+    return obj.substr(p, e - p);
+}
+
+struct SavedState {
+    void* snap = nullptr;
+    int64_t sweep;
+    int32_t epoch;
+    unsigned long long handed[WMC_MAX_LEVELS];
+};
+int save_state(wmc_ctx* c, SavedState& s) {
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMalloc(&s.snap, c->arena_used));
+    HIPCHK(c, hipMemcpy(s.snap, c->arena, c->arena_used, hipMemcpyDeviceToDevice));
+    s.sweep = c->sweep;
+    s.epoch = c->flow_epoch;
+    memcpy(s.handed, c->flow_handed, sizeof(s.handed));
+    return 0;
+}
+// the device arena and the host counters that index it, as saved (the flow epoch keeps growing:
+// an epoch value is never reused within a context)
+int restore_state(wmc_ctx* c, const SavedState& s) {
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemcpy(c->arena, s.snap, c->arena_used, hipMemcpyDeviceToDevice));
+    c->sweep = s.sweep;
+    memcpy(c->flow_handed, s.handed, sizeof(s.handed));
+    return 0;
+}
+}  // namespace
+
+extern "C" int wmc_tune(wmc_ctx* c, int32_t trial_sweeps, char* json_out, size_t json_bytes) {
+    if (!c || trial_sweeps < 1 || trial_sweeps > 1000) return WMC_EINVAL;
+    if (!c->P.periodic || !c->p.wavelets) {
+        c->err = "wmc_tune: periodic systems with wavelet moves only";
+        return WMC_EINVAL;
+    }
+    struct Cand {
+        int pass, variant, width, groups;
+    };
+    const int NL = c->max_levels;
+    std::vector<std::vector<Cand>> cand(NL);
+    int K = 1;
+    for (int l = 0; l < NL; ++l) {
+        int ntile = 0, nglob = 0, ngrp = 0;
+        for (int col = 0; col < 8; ++col) {
+            ntile += c->tile_n[l][col];
+            nglob += c->glob_n[l][col];
+            ngrp += c->cwg_n[l][col];
+        }
+        std::vector<Cand> tile, glob;
+        if (ntile > 0) {
+            for (int pass = 1; pass <= 2; ++pass)
+                for (int v = c->phase_variant[l]; v <= V1024; ++v) {
+                    if (v == V64 && pass == 1) {
+                        tile.push_back({pass, v + 1, 64, 0});
+                        tile.push_back({pass, v + 1, 256, 0});
+                    } else {
+                        tile.push_back({pass, v + 1, 0, 0});
+                    }
+                }
+        } else {
+            tile.push_back({0, 0, 0, 0});
+        }
+        glob.push_back({0, 0, 0, 0});
+        if (nglob > 0 && ngrp > 0) glob.push_back({0, 0, 0, 2});
+        for (const Cand& a : tile)
+            for (const Cand& b : glob) cand[l].push_back({a.pass, a.variant, a.width, b.groups});
+        K = std::max(K, (int)cand[l].size());
+    }
+    const int npw = c->pwg_n > 0 ? 2 : 1;
+    K = std::max(K, npw);
+    SavedState st0;
+    int rc = save_state(c, st0);
+    if (rc) return rc;
+    const bool timing0 = c->timing;
+    std::vector<std::vector<double>> ms(NL, std::vector<double>(K, 1e300));
+    std::vector<double> pwms(K, 1e300);
+    for (int k = 0; k < K && rc == 0; ++k) {
+        for (int l = 0; l < NL; ++l) {
+            const Cand& q = cand[l][k % cand[l].size()];
+            c->tune_pass[l] = q.pass;
+            c->tune_variant[l] = q.variant;
+            c->tune_width[l] = q.width;
+            c->tune_groups[l] = q.groups;
+        }
+        c->tune_pw = (k % npw) ? 2 : 0;
+        if ((rc = restore_state(c, st0))) break;
+        // one untimed sweep, then the timed ones, all from the saved state
+        if ((rc = wmc_sweep(c, 1, nullptr))) break;
+        wmc_set_timing(c, 1);
+        if ((rc = wmc_sweep(c, trial_sweeps, nullptr))) break;
+        double t[WMC_TIMING_CLASSES];
+        wmc_kernel_times(c, t, nullptr);
+        for (int l = 0; l < NL; ++l)
+            if (k < (int)cand[l].size()) ms[l][k] = t[1 + l] / trial_sweeps;
+        if (k < npw) pwms[k] = t[17] / trial_sweeps;
+    }
+    if (rc == 0) {
+        std::vector<double> best_ms(NL);
+        for (int l = 0; l < NL; ++l) {
+            int b = 0;
+            for (int k = 1; k < (int)cand[l].size(); ++k)
+                if (ms[l][k] < ms[l][b]) b = k;
+            c->tune_pass[l] = cand[l][b].pass;
+            c->tune_variant[l] = cand[l][b].variant;
+            c->tune_width[l] = cand[l][b].width;
+            c->tune_groups[l] = cand[l][b].groups;
+            best_ms[l] = ms[l][b];
+        }
+        const int bp = (npw > 1 && pwms[1] < pwms[0]) ? 1 : 0;
+        c->tune_pw = bp ? 2 : 0;
+        rc = restore_state(c, st0);
+        const std::string js = tuning_json(c, &best_ms, pwms[bp], trial_sweeps);
+        if (json_out && json_bytes > 0) {
+            strncpy(json_out, js.c_str(), json_bytes - 1);
+            json_out[json_bytes - 1] = '\0';
+            if (js.size() >= json_bytes && rc == 0) {
+                c->err = "wmc_tune: json_out too small";
+                rc = WMC_EINVAL;
+            }
+        }
+    } else {
+        restore_state(c, st0);
+    }
+    (void)hipFree(st0.snap);
+    wmc_set_timing(c, timing0 ? 1 : 0);
+    return rc;
+}
+
+extern "C" int wmc_set_tuning(wmc_ctx* c, const char* json) {
+    if (!c || !json) return WMC_EINVAL;
+    const std::string s(json);
+    int pass[WMC_MAX_LEVELS] = {0}, var[WMC_MAX_LEVELS] = {0}, width[WMC_MAX_LEVELS] = {0}, grp[WMC_MAX_LEVELS] = {0};
+    size_t p = s.find("\"levels\"");
+    if (p == std::string::npos) {
+        c->err = "wmc_set_tuning: no \"levels\" array";
+        return WMC_EINVAL;
+    }
+    const size_t end = s.find(']', p);
+    for (size_t o = s.find('{', p); o != std::string::npos && o < end; o = s.find('{', o + 1)) {
+        const size_t e = s.find('}', o);
+        if (e == std::string::npos) break;
+        const std::string obj = s.substr(o, e - o + 1);
+        const std::string ls = json_field(obj, "level");
+        char* endp = nullptr;
+        const long l = strtol(ls.c_str(), &endp, 10);
+        if (ls.empty() || *endp || l < 0 || l >= WMC_MAX_LEVELS) {
+            c->err = "wmc_set_tuning: bad level in " + obj;
+            return WMC_EINVAL;
+        }
+        const std::string ps = json_field(obj, "pass"), vs = json_field(obj, "variant"),
+                          ws = json_field(obj, "width"), gs = json_field(obj, "groups");
+        pass[l] = ps == "colours" ? 2 : (ps == "flow" || ps.empty() ? 1 : -1);
+        var[l] = vs.empty() ? 0 : (vs == "V64" ? 1 : vs == "V256" ? 2 : vs == "V1024" ? 3 : -1);
+        width[l] = ws.empty() || ws == "0" ? 0 : (ws == "64" ? 64 : ws == "256" ? 256 : -1);
+        grp[l] = gs == "off" ? 2 : (gs == "on" || gs.empty() ? 0 : -1);
+        if (pass[l] < 0 || var[l] < 0 || width[l] < 0 || grp[l] < 0) {
+            c->err = "wmc_set_tuning: bad value in " + obj;
+            return WMC_EINVAL;
+        }
+        if (pass[l] == 1) pass[l] = 0;
+    }
+    const std::string pw = json_field(s, "plane_wave_groups");
+    if (!pw.empty() && pw != "on" && pw != "off") {
+        c->err = "wmc_set_tuning: bad plane_wave_groups";
+        return WMC_EINVAL;
+    }
+    for (int l = 0; l < WMC_MAX_LEVELS; ++l) {
+        c->tune_pass[l] = pass[l];
+        c->tune_variant[l] = var[l];
+        c->tune_width[l] = width[l];
+        c->tune_groups[l] = grp[l];
+    }
+    c->tune_pw = pw == "off" ? 2 : 0;
+    return 0;
+}
+
+extern "C" int wmc_get_tuning(wmc_ctx* c, char* json_out, size_t json_bytes) {
+    if (!c || !json_out || json_bytes == 0) return WMC_EINVAL;
+    const std::string js = tuning_json(c, nullptr, 0.0, 0);
+    strncpy(json_out, js.c_str(), json_bytes - 1);
+    json_out[json_bytes - 1] = '\0';
+    if (js.size() >= json_bytes) {
+        c->err = "wmc_get_tuning: json_out too small";
+        return WMC_EINVAL;
     }
     return 0;
 }

@@ -156,8 +156,9 @@ struct FlowArgs {
     int32_t epoch;           // value a completed cell publishes; never reused within a context
     unsigned long long qbase;  // flow_ctr[level] before this launch
 };
+// width64: threads per cell of the smallest tile variant (0: 256 up to 4,096 cells, else 64)
 void launch_level_flow(int variant, const DevParams& P, const DevPtrs& D, int level, int64_t sweep,
-                       const int32_t* items, const FlowArgs& fa, hipStream_t st);
+                       const int32_t* items, const FlowArgs& fa, int width64, hipStream_t st);
 void launch_pw(const DevParams& P, const DevPtrs& D, int64_t sweep, int nsys, hipStream_t st);
 bool launch_pw_coop(const DevParams& P, const DevPtrs& D, int64_t sweep, const CoopGroup* groups,
                     const int32_t* wg_group, int nwg, hipStream_t st);

@@ -94,12 +94,15 @@ def lib():
                                  C.c_size_t, vp]
         L.wmc_set_timing.argtypes = [vp, i32]
         L.wmc_kernel_times.argtypes = [vp, dp, lp]
+        L.wmc_tune.argtypes = [vp, i32, C.c_char_p, C.c_size_t]
+        L.wmc_set_tuning.argtypes = [vp, C.c_char_p]
+        L.wmc_get_tuning.argtypes = [vp, C.c_char_p, C.c_size_t]
         L.wmc_last_error.argtypes = [vp]
         L.wmc_last_error.restype = C.c_char_p
         L.wmc_free.argtypes = [vp]
         for f in ("wmc_arena_bytes", "wmc_launch_plan", "wmc_init", "wmc_init_static", "wmc_sweep", "wmc_positions", "wmc_set_state", "wmc_observables",
                   "wmc_system_tau", "wmc_chain_rg2", "wmc_chain_com", "wmc_chain_msd", "wmc_trace", "wmc_system_info", "wmc_cell_ids", "wmc_philox",
-                  "wmc_set_timing", "wmc_kernel_times"):
+                  "wmc_set_timing", "wmc_kernel_times", "wmc_tune", "wmc_set_tuning", "wmc_get_tuning"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -301,6 +304,29 @@ class WMC:
         self._check(lib().wmc_kernel_times(self._h, _dp(ms), _lp(n)), "wmc_kernel_times")
         names = ["grid"] + [f"level{l}" for l in range(MAX_LEVELS)] + ["plane_waves"]
         return {names[i]: (float(ms[i]), int(n[i])) for i in range(18) if n[i] > 0}
+
+    def tune(self, trial_sweeps: int = 3) -> dict:
+        """Time each launch choice per level from the current state, keep the fastest, restore the
+        state (wmc_tune); returns the chosen settings with their times."""
+        import json
+
+        buf = C.create_string_buffer(1 << 16)
+        self._check(lib().wmc_tune(self._h, int(trial_sweeps), buf, len(buf)), "wmc_tune")
+        return json.loads(buf.value.decode())
+
+    def set_tuning(self, settings):
+        """Apply launch settings (a dict as tune() returns, or its JSON text)."""
+        import json
+
+        text = settings if isinstance(settings, str) else json.dumps(settings)
+        self._check(lib().wmc_set_tuning(self._h, text.encode()), "wmc_set_tuning")
+
+    def get_tuning(self) -> dict:
+        import json
+
+        buf = C.create_string_buffer(1 << 16)
+        self._check(lib().wmc_get_tuning(self._h, buf, len(buf)), "wmc_get_tuning")
+        return json.loads(buf.value.decode())
 
     def cell_ids(self, system: int, sweep: int, level: int) -> np.ndarray:
         n = int(self.sys_off[system + 1] - self.sys_off[system])
