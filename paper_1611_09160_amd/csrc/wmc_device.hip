@@ -1504,7 +1504,8 @@ template <int W, int CAPH, int CAPM, int NCD, class T = double, class WV = WaveD
 __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                         const TileShared<W, CAPH, CAPM, NCD, T>& sh, const Grid& g, const TileGeo& tg,
                         const WV& wv, double R,
-                        int nH, int n, double& acc, unsigned long long& viol, float rc2g = 0.0f) {
+                        int nH, int n, double& acc, unsigned long long& viol, float rc2g = 0.0f,
+                        double Rp2 = INFINITY) {
     constexpr bool F32 = std::is_same<T, float>::value;
     auto cur = [&](int sl, double& x, double& y, double& z) {
         if constexpr (F32) {
@@ -1622,6 +1623,8 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                 double mx, my, mz;
                 cur(m, mx, my, mz);
                 double r2o = pair_r2(P, invL, L, jx, jy, jz, mx, my, mz);
+                // a pair further apart than r_cut + 2 dmax stays beyond the cut-off after the move
+                if (r2o > Rp2) continue;
                 double nx = mx, ny = my, nz = mz;
                 if (tm >= 0) trial(tm, m, nx, ny, nz);
                 double r2n = pair_r2(P, invL, L, kx, ky, kz, nx, ny, nz);
@@ -1638,8 +1641,8 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
 template <int W, int CAPH, int CAPM, int NCD>
 __device__ void tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared<W, CAPH, CAPM, NCD, float>& sh,
                           const Grid& g, const TileGeo& tg, const WaveDesc32& wv, double R, int nH, int n, bool wrap,
-                          float Lf, float invLf, float rc2f, float rc2g, double& acc, float& s1, float& s2,
-                          unsigned long long& viol) {
+                          float Lf, float invLf, float rc2f, float rc2g, float Rp2f, double& acc, float& s1,
+                          float& s2, unsigned long long& viol) {
     // the margin sums need only a few correct digits: hardware reciprocal square root (1 ulp)
     auto rsq = [](float v) { return __builtin_amdgcn_rsqf(v); };
     const int tid = threadIdx.x;
@@ -1723,6 +1726,9 @@ __device__ void tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared
                 if (tm >= 0 && m < sl) continue;
                 const float mx = sh.x[m], my = sh.y[m], mz = sh.z[m];
                 const float r2o = r2_f32(jx - mx, jy - my, jz - mz, wrap, Lf, invLf);
+                // beyond r_cut + 2 dmax (widened past rc2g's widening and the FP32 error) a pair's new
+                // FP32 distance also lies beyond rc2g: it adds nothing, margin sums included
+                if (r2o > Rp2f) continue;
                 float nx = mx, ny = my, nz = mz;
                 if (tm >= 0) {
                     float v0, v1, v2;
@@ -2177,8 +2183,10 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 const double K2 = 9.0 + 66.0 * P.A0;
                 const float rc2g = (float)(P.rc2 * (1.0 + 0x1p-20 * (K2 * Hm / fmax(P.rc, 1e-3) + 2.0)));
                 float s1 = 0.0f, s2 = 0.0f;
+                const double rp = P.rc + 2.0 * dmax;
+                const float Rp2f = (float)(rp * rp * ((double)rc2g / P.rc2) * (1.0 + 0x1p-9));
                 tile_dU32<W, CAPH, CAPM, NCD>(P, D, sh, g, tg, wv32, Rq, nH, n, wrap, (float)L, (float)invL,
-                                              (float)P.rc2, rc2g, acc, s1, s2, c_viol);
+                                              (float)P.rc2, rc2g, Rp2f, acc, s1, s2, c_viol);
                 double S1 = (double)s1, S2 = (double)s2;
                 dU = acc;
                 block_sum3<W>(dU, S1, S2, sh.red3);
@@ -2188,7 +2196,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                     double a64 = 0.0;
                     unsigned long long v64 = 0;
                     tile_dU<W, CAPH, CAPM, NCD, float, WaveDesc32>(P, D, s, sh, g, tg, wv32, Rq, nH, n, a64, v64,
-                                                                    rc2g);
+                                                                    rc2g, rp * rp * (1.0 + 1e-12));
                     const double d64 = block_sum<W>(a64, sh.red);
                     if (tid == 0) {
                         if (near) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
@@ -2208,7 +2216,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                     if (near) dU = d64;
                 }
             } else {
-                tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, acc, c_viol);
+                const double rp = (P.rc + 2.0 * dmax) * (1.0 + 1e-12);
+                tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, acc, c_viol, 0.0f, rp * rp);
                 dU = block_sum<W>(acc, sh.red);
             }
             const bool accept = dU <= thr;
