@@ -54,8 +54,9 @@ def measured_traffic(cls: str):
 def algorithmic_bytes_per_sweep(cls: str, N: int, n_fine: int, pw_attempts_per_sweep: float) -> float:
     """Bytes one sweep's launches of a kernel class must move at minimum.
 
-    level passes: every bead's position is read and written once per level, plus its
-      neighbour-grid entry (4 B index + 4 B cell start): N (24 + 24 + 8).
+    level passes: every bead's position is read and written once per level, plus 16 B of its
+      sorted neighbour-grid entries (index and cell start, read by the halo gather and the pair
+      search): N (24 + 24 + 16) = 64 B per bead.
     grid: per build read positions, write the reference copy and the cell of every bead, count,
       scan, scatter and sort: N (24 + 24 + 4 + 4 + 8 + 8) + 12 n_fine (6 builds per sweep here,
       one per level and one before the plane waves; the caller passes the build count).
@@ -63,7 +64,7 @@ def algorithmic_bytes_per_sweep(cls: str, N: int, n_fine: int, pw_attempts_per_s
       neighbour grid and write accepted positions: N (24 + 24 + 24 + 8 + 24).
     """
     if cls.startswith("level"):
-        return N * (24 + 24 + 8)
+        return N * (24 + 24 + 16)
     if cls == "grid":
         return N * (24 + 24 + 4 + 4 + 8 + 8) + 12.0 * n_fine
     if cls == "plane_waves":
