@@ -133,6 +133,27 @@ def test_mixed_rechecks_near_threshold(verify):
         assert ob["margin_checks"] == 0
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_forced_caps_and_infinite_energies(precision):
+    """Large moves (A0 = 2) with a retry cap of 2 on the semi-dilute solution: many tests stretch a
+    FENE bond past R0 (an infinite dU, always rejected) and many chains end at the cap; the trace,
+    the infinite records and the counters equal the oracle's."""
+    cfg = _workload(3, 0.0625)
+    g, o = build_pair(cfg, precision=precision, A0=2.0, retry_cap=2)
+    g.sweep(1)
+    o.sweep(1)
+    tg, to = g.trace(), o.trace()
+    tol, prt = tolerances(precision)
+    compare_traces(tg, to, **tol)
+    moves = to["kind"] != 1
+    assert np.isinf(to["dU"][moves]).sum() > 0
+    assert np.isinf(tg["dU"][tg["kind"] != 1]).sum() == np.isinf(to["dU"][moves]).sum()
+    ob = o.observables()
+    assert ob["caps"].sum() > 0, ob["caps"]
+    compare_counters(g.observables(), ob)
+    compare_positions(g.positions(), o.positions(), rtol=prt)
+
+
 def test_mixed_margin_on_semidilute():
     """mixed_verify on the semi-dilute solution (64 x 128 beads): every FP32-tile test's FP32 error
     stays within its recheck margin, and the decisions still equal the oracle's."""
