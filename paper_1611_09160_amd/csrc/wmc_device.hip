@@ -1184,6 +1184,120 @@ constexpr int32_t ID_MASK = 0x3FFFFFFF;
 constexpr int32_t ID_NEXT = 0x40000000;  // bonded to bead id + 1
 constexpr uint32_t ID_PREV = 0x80000000u;  // bonded to bead id - 1
 
+// One-barrier reductions (LDS tiles): reduction k of a kind uses half k % 2 of its exchange area (the
+// toggles are block-uniform), so a half is written again only after a later reduction's barrier,
+// which every thread passes after its reads of the earlier result. Same results as the block_*
+// helpers, one barrier instead of two.
+template <int W>
+struct Exch {
+    static constexpr int NW = W / 64 > 0 ? W / 64 : 1;
+    double d[2 * NW];
+    double d3[2 * 3 * NW];
+    int i[2 * NW];
+};
+struct ExchPh {
+    int d = 0, d3 = 0, i = 0;
+};
+template <int W>
+__device__ __forceinline__ double xsum(double v, Exch<W>& x, ExchPh& p) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double* r = x.d + p.d * Exch<W>::NW;
+    p.d ^= 1;
+    if (lane == 0) r[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < W / 64; ++i) t += r[i];
+    return t;
+}
+template <int W>
+__device__ __forceinline__ double xmax(double v, Exch<W>& x, ExchPh& p) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double* r = x.d + p.d * Exch<W>::NW;
+    p.d ^= 1;
+    if (lane == 0) r[wv] = v;
+    __syncthreads();
+    double t = r[0];
+    for (int i = 1; i < W / 64; ++i) t = fmax(t, r[i]);
+    return t;
+}
+template <int W>
+__device__ __forceinline__ void xsum3(double& a, double& b, double& c, Exch<W>& x, ExchPh& p) {
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+        c += __shfl_xor(c, o);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double* r = x.d3 + p.d3 * 3 * Exch<W>::NW;
+    p.d3 ^= 1;
+    if (lane == 0) {
+        r[3 * wv] = a;
+        r[3 * wv + 1] = b;
+        r[3 * wv + 2] = c;
+    }
+    __syncthreads();
+    double ta = 0.0, tb = 0.0, tc = 0.0;
+    for (int i = 0; i < W / 64; ++i) {
+        ta += r[3 * i];
+        tb += r[3 * i + 1];
+        tc += r[3 * i + 2];
+    }
+    a = ta;
+    b = tb;
+    c = tc;
+}
+template <int W>
+__device__ __forceinline__ int xmin_int(int v, Exch<W>& x, ExchPh& p) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int* r = x.i + p.i * Exch<W>::NW;
+    p.i ^= 1;
+    if (lane == 0) r[wv] = v;
+    __syncthreads();
+    int t = r[0];
+    for (int i = 1; i < W / 64; ++i) t = min(t, r[i]);
+    return t;
+}
+template <int W>
+__device__ __forceinline__ int xscan_flag(bool f, int& before, Exch<W>& x, ExchPh& p) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t m = __ballot(f);
+    const int in_wave = __popcll(m & ((1ull << lane) - 1ull));
+    int* r = x.i + p.i * Exch<W>::NW;
+    p.i ^= 1;
+    if (lane == 0) r[wv] = __popcll(m);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < W / 64; ++i) {
+        if (i < wv) off += r[i];
+        tot += r[i];
+    }
+    before = off + in_wave;
+    return tot;
+}
+template <int W>
+__device__ __forceinline__ int xscan_count(int v, int& before, Exch<W>& x, ExchPh& p) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int y = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int z = __shfl_up(y, o);
+        if (lane >= o) y += z;
+    }
+    int* r = x.i + p.i * Exch<W>::NW;
+    p.i ^= 1;
+    if (lane == 63) r[wv] = y;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < W / 64; ++i) {
+        if (i < wv) off += r[i];
+        tot += r[i];
+    }
+    before = off + y - v;
+    return tot;
+}
+
 // T = double: absolute FP64 positions (FP64 contexts). T = float (mixed precision): FP32 offsets from
 // the tile's centre, minimg(r - c) rounded once; the FP64 positions stay in HBM.
 template <int W, int CAPH, int CAPM, int NCD, class T = double>
@@ -1204,8 +1318,8 @@ struct TileShared {
     // recomputed when needed)
     T MX[CAPM > 0 ? CAPM : 1], MY[CAPM > 0 ? CAPM : 1], MZ[CAPM > 0 ? CAPM : 1];
     double red[W / 64 > 0 ? W / 64 : 1];
-    double red3[3 * (W / 64 > 0 ? W / 64 : 1)];
     int redi[W / 64 > 0 ? W / 64 : 1];
+    Exch<W> xc;  // exchange area of the one-barrier reductions
     int count;
     double pub_b[3];  // the centre; on an FP32 tile with anchored centres the ball vector V
     float pub_bf[3];  // FP32 tile: the centre's offset from the tile centre
@@ -1771,6 +1885,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     const double rh = lv.hi + lv.r_int, rh2 = rh * rh;
     const double L = s.L, invL = s.invL;
     dl_out = 0.0;
+    ExchPh xp;  // toggles of the one-barrier reductions
     // FP32 tile (mixed precision): offsets from the tile centre, the FP64 positions in HBM
     constexpr bool F32 = std::is_same<T, float>::value;
 
@@ -1819,7 +1934,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             int run = 0;
             for (int c = c0; c < c1; ++c) run += segP[c];
             int before;
-            const int total = block_scan_count<W>(run, before, sh.redi);
+            const int total = xscan_count<W>(run, before, sh.xc, xp);
             for (int c = c0; c < c1; ++c) {
                 const int v = segP[c];
                 segP[c] = before;
@@ -1893,7 +2008,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             f = dist2_cell(g, ic, x, y, z) <= hi2;
         }
         int before;
-        int tot = block_scan_flag<W>(f, before, sh.redi);
+        int tot = xscan_flag<W>(f, before, sh.xc, xp);
         if (f) sh.S[nS + before] = (int16_t)i;
         nS += tot;
     }
@@ -2004,7 +2119,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 hit = cell_of_point(g, bx, by, bz) == cell;
             }
         }
-        int first = block_min_int<W>(hit ? tid : 0x7FFFFFFF, sh.redi);
+        int first = xmin_int<W>(hit ? tid : 0x7FFFFFFF, sh.xc, xp);
         if (first == 0x7FFFFFFF) break;
         if (tid == first) {
             sh.pub_lam = lam_t;
@@ -2078,7 +2193,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                     return ((dx * dx + dy * dy) + dz * dz) <= lam2 || sl == as;
                 }
             };
-            __syncthreads();
+            // (no barrier here: both ways into a test, a chain's start and a redraw, end with one)
             int n = 0;
             if (W >= 256 && nS > W && nS <= 32 * W) {
                 // q consecutive reach entries per thread, one workgroup scan (member order kept);
@@ -2090,7 +2205,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                     if (i < nS && in_ball(sh.S[i])) mask |= 1u << u;
                 }
                 int before;
-                n = block_scan_count<W>(__popc(mask), before, sh.redi);
+                n = xscan_count<W>(__popc(mask), before, sh.xc, xp);
                 for (int u = 0; u < q; ++u)
                     if ((mask >> u) & 1u) sh.M[before++] = sh.S[i0 + u];
             } else {
@@ -2103,7 +2218,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                         f = in_ball(sl);
                     }
                     int before;
-                    int tot = block_scan_flag<W>(f, before, sh.redi);
+                    int tot = xscan_flag<W>(f, before, sh.xc, xp);
                     if (f) sh.M[n + before] = (int16_t)sl;
                     n += tot;
                 }
@@ -2160,7 +2275,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             }
             // barrier: trial positions and tags visible (an FP32 length is raised by 2^-20, more
             // than its rounding)
-            const double dmax = block_max<W>(dmax_l, sh.red) * (F32 ? 1.0 + 0x1p-20 : 1.0);
+            const double dmax = xmax<W>(dmax_l, sh.xc, xp) * (F32 ? 1.0 + 0x1p-20 : 1.0);
             const double Rq = P.rc + 2.0 * dmax + E + 1e-9 * L;
             double acc = 0.0;
             const double thr = accept_threshold<VAR>(P, u_acc);
@@ -2189,7 +2304,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                                               (float)P.rc2, rc2g, Rp2f, acc, s1, s2, c_viol);
                 double S1 = (double)s1, S2 = (double)s2;
                 dU = acc;
-                block_sum3<W>(dU, S1, S2, sh.red3);
+                xsum3<W>(dU, S1, S2, sh.xc, xp);
                 const double m = 0x1.0p-23 * (16.0 * S1 + 8.0 * Hm * S2) + 1e-12;
                 const bool near = !(isfinite(dU) && fabs(dU - thr) > m);
                 if (near || P.mixed_verify) {
@@ -2197,7 +2312,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                     unsigned long long v64 = 0;
                     tile_dU<W, CAPH, CAPM, NCD, float, WaveDesc32>(P, D, s, sh, g, tg, wv32, Rq, nH, n, a64, v64,
                                                                     rc2g, rp * rp * (1.0 + 1e-12));
-                    const double d64 = block_sum<W>(a64, sh.red);
+                    const double d64 = xsum<W>(a64, sh.xc, xp);
                     if (tid == 0) {
                         if (near) atomicAdd(&D.cnt[CNT_RECHECK], 1ull);
                         if (P.mixed_verify) {
@@ -2218,7 +2333,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             } else {
                 const double rp = (P.rc + 2.0 * dmax) * (1.0 + 1e-12);
                 tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, acc, c_viol, 0.0f, rp * rp);
-                dU = block_sum<W>(acc, sh.red);
+                dU = xsum<W>(acc, sh.xc, xp);
             }
             const bool accept = dU <= thr;
             if (tid == 0)
@@ -2297,7 +2412,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                         }
                     }
                 }
-                int fj = block_min_int<W>(h2 ? jj : 0x7FFFFFFF, sh.redi);
+                int fj = xmin_int<W>(h2 ? jj : 0x7FFFFFFF, sh.xc, xp);
                 if (fj != 0x7FFFFFFF) {
                     if (jj == fj) {
                         sh.pub_a = a2;

@@ -135,11 +135,11 @@ def test_mixed_rechecks_near_threshold(verify):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_forced_caps_and_infinite_energies(precision):
-    """Large moves (A0 = 2) with a retry cap of 2 on the semi-dilute solution: many tests stretch a
+    """Large moves (A0 = 5) with a retry cap of 2 on the semi-dilute solution: many tests stretch a
     FENE bond past R0 (an infinite dU, always rejected) and many chains end at the cap; the trace,
     the infinite records and the counters equal the oracle's."""
     cfg = _workload(3, 0.0625)
-    g, o = build_pair(cfg, precision=precision, A0=2.0, retry_cap=2)
+    g, o = build_pair(cfg, precision=precision, A0=5.0, retry_cap=2)
     g.sweep(1)
     o.sweep(1)
     tg, to = g.trace(), o.trace()
