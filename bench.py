@@ -34,12 +34,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch (FP64 pass) from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by a plain
-# copy of known size (profiles/traffic_sweep_semidilute32k.md; levels 3 and 4 share one cell-group
-# kernel, whose average is given for both); valid only for the device source they were measured
-# on, otherwise the bench reports null
-TRAFFIC_SOURCE_SHA16 = "56822d9fb933aaa0"
-TRAFFIC_BYTES_PER_LAUNCH = {"level0": 64.07e6, "level1": 17.40e6, "level2": 16.88e6, "level3": 6.31e6, "level4": 6.31e6, "plane_waves": 28.95e6, "grid": 9.59e6}
+# HBM bytes per launch (FP64 pass, planned launches) from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
+# scaled by a plain copy of known size (profiles/traffic_sweep_semidilute32k.md; levels 3 and 4 share
+# one cell-group kernel, whose average is given for both); valid only for the device source they
+# were measured on, otherwise the bench reports null
+TRAFFIC_SOURCE_SHA16 = "ffd2d21dbd5de7e1"
+TRAFFIC_BYTES_PER_LAUNCH = {"level0": 53.68e6, "level1": 17.18e6, "level2": 16.74e6, "level3": 6.29e6, "level4": 6.29e6, "plane_waves": 28.95e6, "grid": 9.59e6}
 
 
 def measured_traffic(cls: str):
