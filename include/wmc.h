@@ -148,7 +148,7 @@ typedef struct {
 } wmc_obs;
 
 /* One trace record per Metropolis test (kind 0 wavelet, 2 plane wave) and per cell phase
- * (kind 1: trial = trial count, retry = |S_c|, n = |H_c| or 0, accepted = hits). */
+ * (kind 1: trial = trial count, retry = |S_c|, n = 0, accepted = hits). */
 typedef struct {
     int32_t kind, system, sweep, level, cell, trial, retry, n, accepted, extra;
     double dU, thr;
