@@ -1870,7 +1870,7 @@ __device__ void tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared
 // returns false (before any move) when the halo does not fit; the caller then uses the
 // global path for this cell. Dg bounds the drift, since the neighbour grid was built, of every bead
 // the cell can meet; the largest drift of the beads the cell moves is returned in dl_out.
-template <int W, int CAPH, int CAPM, int NCD, bool MIXED, bool VAR, class T>
+template <int W, int CAPH, int CAPM, int NCD, bool VAR, class T>
 __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevPtrs& D, TileShared<W, CAPH, CAPM, NCD, T>& sh, int sys,
                                   int level, int colour, int64_t local, int64_t sweep, const Grid& g,
                                   const double Dg, double& dl_out) {
@@ -2491,7 +2491,7 @@ __global__ __launch_bounds__(W) void k_phase(DevParams P, DevPtrs D, int level, 
         double Dg = 0.0;
         for (int c = 0; c < colour; ++c) Dg = fmax(Dg, __longlong_as_double((long long)D.drift_col[8 * sys + c]));
         double dl = 0.0;
-        if (lv.use_global || !process_cell_tile<W, CAPH, CAPMT, NCD, MIXED, VAR>(P, D, sh.t, sys, level, colour, local, sweep, g,
+        if (lv.use_global || !process_cell_tile<W, CAPH, CAPMT, NCD, VAR>(P, D, sh.t, sys, level, colour, local, sweep, g,
                                                                             Dg, dl)) {
             __syncthreads();
             // global-list cells compute in FP64 in both precisions (their time is not arithmetic: FP32
@@ -2535,7 +2535,7 @@ static bool uses_variants(const DevParams& P) {
     return P.accept_rule != WMC_ACCEPT_METROPOLIS || P.wavelet_map != WMC_MAP_LINEAR || P.centring != WMC_CENTRE_ANCHOR;
 }
 
-// one kernel per precision and variant set: the FP32 terms and their recheck, and the variants,
+// one kernel per precision and variant set: the FP32 tiles with their rechecks, and the variants,
 // cost registers the FP64 path of the paper's method does not need
 void launch_phase(int variant, const DevParams& P, const DevPtrs& D, int level, int colour, int64_t sweep,
                   const int32_t* bmap, int nblocks, hipStream_t st) {
@@ -2617,7 +2617,7 @@ __global__ __launch_bounds__(W, W == 64 ? 2 : 1) void k_level_flow(DevParams P, 
         // a neighbour never published: running now could race with it, so the cell is skipped and
         // the sweep reported invalid (wmc_observables returns WMC_ESCHEDULE)
         if (tid == 0) atomicAdd(&D.cnt[CNT_FLOWWAIT], 1ull);
-    } else if (!process_cell_tile<W, CAPH, CAPMT, NCD, MIXED, VAR>(P, D, sh.t, sys, level, colour, local, sweep, g, Dg, dl)) {
+    } else if (!process_cell_tile<W, CAPH, CAPMT, NCD, VAR>(P, D, sh.t, sys, level, colour, local, sweep, g, Dg, dl)) {
         // the halo does not fit the tile: the global-list path, inline (a call would cost a stack
         // frame and the registers saved around it, for every cell)
         __syncthreads();
