@@ -700,6 +700,34 @@ __device__ __forceinline__ void group_barrier(unsigned* bar, unsigned nblocks, u
     }
 }
 
+// group_barrier in two halves, so that a workgroup can work between its arrival and its wait: the
+// arrival publishes what the workgroup wrote before it; the work in between must not write what
+// another workgroup of the group reads after the barrier. `released` tells thread 0 that its own
+// arrival was the last one.
+__device__ __forceinline__ void group_arrive(unsigned* bar, unsigned nblocks, unsigned gen, bool& released) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    released = true;
+    if (nblocks > 1 && threadIdx.x == 0) {
+        const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        released = arrived == nblocks;
+        if (released) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+__device__ __forceinline__ void group_wait(unsigned* bar, unsigned nblocks, unsigned& gen, bool released) {
+    if (nblocks > 1) {
+        if (threadIdx.x == 0 && !released) {
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        gen = gen + 1u;
+    }
+    __syncthreads();
+}
+
 // --------------------------------------------------------------------- cell phase
 // One workgroup processes one cell of the current colour:
 //  1. reach list S_c = beads within lambda_hi of the cell, ascending index (from the
@@ -1326,6 +1354,7 @@ struct TileShared {
     double pub_lam;
     int32_t pub_a;
     uint32_t pub_next;
+    int spec_found;  // first hit of the speculative redraw chunk, -1 if none
 };
 
 template <int W, int CAPS, int CAPM, int CAPH, int CAPMT, int NCD, class T = double>
@@ -2069,6 +2098,55 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
         slot_pos(a, ax, ay, az);
         return cell_of_point(g, ax + lm * vx, ay + lm * vy, az + lm * vz) == cell;
     };
+    // one try of a recycling redraw (retry rn of trial tc, try jj): anchor and ball vector, or a
+    // uniform centre, and whether the centre lies in the cell
+    auto redraw_try = [&](int64_t tc, int rn, int jj, double lam, Stream& rs, int& a2, double& ex, double& ey,
+                          double& ez, float& g0, float& g1, float& g2) -> bool {
+        rs.init(P, sys, sweep, level, key, tc, rn, jj);
+        if (F32 && !uni) {
+            // the draws of draw_trial_centre (anchor, then ball vector), FP32 cell test
+            a2 = slot_of(rs.index(nS));
+            ball(rs, ex, ey, ez);
+            return hit_f32(a2, lam, ex, ey, ez, g0, g1, g2);
+        }
+        const bool h = draw_trial_centre<VAR>(P, rs, g, ic, cell, lam, nS, slot_of, slot_pos, a2, ex, ey, ez);
+        if (F32) {
+            g0 = (float)minimg(g, ex - tg.c[0]);
+            g1 = (float)minimg(g, ey - tg.c[1]);
+            g2 = (float)minimg(g, ez - tg.c[2]);
+        }
+        return h;
+    };
+    // The first 16 tries of the redraw that follows a rejection, taken speculatively while the test
+    // is evaluated: a rejected test moves nothing, so they see the positions the redraw would see.
+    // The last wave, which holds the fewest pair items, takes them after its own items; the first hit
+    // goes to pub_* (read again only after a redraw; an accepted test ends the chain, whose successor
+    // publishes its own centre) and its try index, or -1, to spec_found, both read after the
+    // reduction barrier of the energy sum. Wider tiles only: a one-wave tile would take them serially.
+    constexpr bool SPEC = W >= 256;
+    auto spec_redraw = [&](int64_t tc, int rn, double lam) {
+        if ((tid >> 6) != W / 64 - 1) return;
+        const int lane = tid & 63;
+        bool h2 = false;
+        double ex = 0, ey = 0, ez = 0;
+        float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+        int a2 = 0;
+        Stream rs;
+        if (lane < 16) h2 = redraw_try(tc, rn, lane, lam, rs, a2, ex, ey, ez, g0, g1, g2);
+        const uint64_t hits = __ballot(h2);
+        const int fj = hits ? __builtin_ctzll(hits) : -1;
+        if (lane == fj) {
+            sh.pub_a = a2;
+            sh.pub_b[0] = ex;
+            sh.pub_b[1] = ey;
+            sh.pub_b[2] = ez;
+            sh.pub_bf[0] = g0;
+            sh.pub_bf[1] = g1;
+            sh.pub_bf[2] = g2;
+            sh.pub_next = rs.next;
+        }
+        if (lane == 0) sh.spec_found = fj;
+    };
     for (int64_t t0 = 0; t0 < K; t0 += W) {
         const int64_t t = t0 + tid;
         const bool drawn = t < K && (nS > 0 || uni);
@@ -2193,7 +2271,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                     return ((dx * dx + dy * dy) + dz * dz) <= lam2 || sl == as;
                 }
             };
-            // (no barrier here: both ways into a test, a chain's start and a redraw, end with one)
+            // (no barrier here: whatever a test reads from LDS before its member scan, the centre in
+            // pub_* included, was written before a barrier)
             int n = 0;
             if (W >= 256 && nS > W && nS <= 32 * W) {
                 // q consecutive reach entries per thread, one workgroup scan (member order kept);
@@ -2302,6 +2381,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 const float Rp2f = (float)(rp * rp * ((double)rc2g / P.rc2) * (1.0 + 0x1p-9));
                 tile_dU32<W, CAPH, CAPM, NCD>(P, D, sh, g, tg, wv32, Rq, nH, n, wrap, (float)L, (float)invL,
                                               (float)P.rc2, rc2g, Rp2f, acc, s1, s2, c_viol);
+                if (SPEC && r + 1 < P.retry_cap) spec_redraw(tc, r + 1, lam);
                 double S1 = (double)s1, S2 = (double)s2;
                 dU = acc;
                 xsum3<W>(dU, S1, S2, sh.xc, xp);
@@ -2333,6 +2413,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             } else {
                 const double rp = (P.rc + 2.0 * dmax) * (1.0 + 1e-12);
                 tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, acc, c_viol, 0.0f, rp * rp);
+                if (SPEC && r + 1 < P.retry_cap) spec_redraw(tc, r + 1, lam);
                 dU = xsum<W>(acc, sh.xc, xp);
             }
             const bool accept = dU <= thr;
@@ -2370,8 +2451,10 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 }
                 tile_tag_clear(sh, sl);
             }
-            __syncthreads();
+            // a rejection changes no position: the next writes of the tags and member lists follow
+            // the next test's member scan, which is a barrier
             if (accept) {
+                __syncthreads();
                 ++c_acc;
                 if (tid == 0) atomicAdd(&D.cnt[CNT_ACC_BEADS], (unsigned long long)n);
                 E += dmax;
@@ -2387,53 +2470,46 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 break;
             }
             // redraws in chunks: 16 tries first (the ball's rejection loop runs as long as its
-            // slowest lane, so a narrow first chunk is cheaper), then W at a time
-            int found = -1;
-            for (int j0 = 0, len = W < 16 ? W : 16; j0 < 4096 && found < 0; j0 += len, len = W) {
-                int jj = j0 + tid;
-                bool h2 = false;
-                double ex = 0, ey = 0, ez = 0;
-                float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
-                int a2 = 0;
-                Stream rs;
-                if (tid < len && jj < 4096) {
-                    rs.init(P, sys, sweep, level, key, tc, r, jj);
-                    if (F32 && !uni) {
-                        // the draws of draw_trial_centre (anchor, then ball vector), FP32 cell test
-                        a2 = slot_of(rs.index(nS));
-                        ball(rs, ex, ey, ez);
-                        h2 = hit_f32(a2, lam, ex, ey, ez, g0, g1, g2);
-                    } else {
-                        h2 = draw_trial_centre<VAR>(P, rs, g, ic, cell, lam, nS, slot_of, slot_pos, a2, ex, ey, ez);
-                        if (F32) {
-                            g0 = (float)minimg(g, ex - tg.c[0]);
-                            g1 = (float)minimg(g, ey - tg.c[1]);
-                            g2 = (float)minimg(g, ez - tg.c[2]);
-                        }
-                    }
-                }
-                int fj = xmin_int<W>(h2 ? jj : 0x7FFFFFFF, sh.xc, xp);
-                if (fj != 0x7FFFFFFF) {
-                    if (jj == fj) {
-                        sh.pub_a = a2;
-                        sh.pub_b[0] = ex;
-                        sh.pub_b[1] = ey;
-                        sh.pub_b[2] = ez;
-                        sh.pub_bf[0] = g0;
-                        sh.pub_bf[1] = g1;
-                        sh.pub_bf[2] = g2;
-                        sh.pub_next = rs.next;
-                    }
-                    found = fj;
-                }
+            // slowest lane, so a narrow first chunk is cheaper; wider tiles took it during the
+            // test), then W at a time
+            int found = -1, j_first = 0;
+            if (SPEC) {
+                found = sh.spec_found;
+                j_first = 16;
             }
-            __syncthreads();
+            if (found < 0) {
+                for (int j0 = j_first, len = j0 == 0 && W > 16 ? 16 : W; j0 < 4096 && found < 0; j0 += len, len = W) {
+                    int jj = j0 + tid;
+                    bool h2 = false;
+                    double ex = 0, ey = 0, ez = 0;
+                    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+                    int a2 = 0;
+                    Stream rs;
+                    if (tid < len && jj < 4096) h2 = redraw_try(tc, r, jj, lam, rs, a2, ex, ey, ez, g0, g1, g2);
+                    int fj = xmin_int<W>(h2 ? jj : 0x7FFFFFFF, sh.xc, xp);
+                    if (fj != 0x7FFFFFFF) {
+                        if (jj == fj) {
+                            sh.pub_a = a2;
+                            sh.pub_b[0] = ex;
+                            sh.pub_b[1] = ey;
+                            sh.pub_b[2] = ez;
+                            sh.pub_bf[0] = g0;
+                            sh.pub_bf[1] = g1;
+                            sh.pub_bf[2] = g2;
+                            sh.pub_next = rs.next;
+                        }
+                        found = fj;
+                    }
+                }
+                __syncthreads();  // the finder's pub_* visible
+            }
             if (found < 0) {
                 c_redraw += 4096;
                 ++c_caps;
                 break;
             }
             c_redraw += (unsigned long long)found;
+            // pub_* are written again only after the next test's member scan (a barrier)
             as = sh.pub_a;
             if constexpr (!F32) {
                 b[0] = sh.pub_b[0];
@@ -2442,7 +2518,6 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             }
             nxt = sh.pub_next;
             jtry = found;
-            __syncthreads();
         }
         from = first + 1;
       }
@@ -2886,12 +2961,36 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
             const double Rq = P.rc + 2.0 * dmax + fmax(Dg, dloc) + 1e-9 * L;
             const double thr = accept_threshold<VAR>(P, u_acc);
             double dU;
+            // first chunk of the redraw a rejection would need (-1: no hit, -2: not taken)
+            int spec = -2;
             {
                 double acc = 0.0;
                 glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, gt, gstride, acc, c_viol);
                 const double pa = block_sum<CW>(acc, sh.red);
                 if (tid == 0) c_acc[wg] = pa;
-                group_barrier(bar, G, gen);  // 3: partial sums
+                bool rel;
+                group_arrive(bar, G, gen, rel);  // 3: partial sums
+                if (r + 1 < P.retry_cap) {
+                    // While the group arrives, this workgroup takes the first CW tries of that redraw:
+                    // a rejected test moves nothing, so they see the positions the redraw would see
+                    // (after an acceptance they are discarded). The hit goes to pub_* (read again
+                    // only after a redraw); every workgroup finds the same.
+                    double ex = 0, ey = 0, ez = 0;
+                    int32_t a2 = 0;
+                    Stream rs;
+                    rs.init(P, sys, sweep, level, key, tc, r + 1, tid);
+                    const bool h2 = draw_trial_centre<VAR>(P, rs, g, ic, cell, lam, nS, Sat, pos_of, a2, ex, ey, ez);
+                    const int fj = block_min_int<CW>(h2 ? tid : 0x7FFFFFFF, sh.redi);
+                    if (tid == fj) {
+                        sh.pub_a = a2;
+                        sh.pub_b[0] = ex;
+                        sh.pub_b[1] = ey;
+                        sh.pub_b[2] = ez;
+                        sh.pub_next = rs.next;
+                    }
+                    spec = fj == 0x7FFFFFFF ? -1 : fj;
+                }
+                group_wait(bar, G, gen, rel);
                 dU = coop_sum(c_acc, G, sh);
             }
             const bool accept = dU <= thr;
@@ -2925,9 +3024,10 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                 ++c_caps;
                 break;
             }
-            // recycle lambda: redraw anchor and centre until the centre is in the cell
-            int found = -1;
-            for (int j0 = 0; j0 < 4096 && found < 0; j0 += CW) {
+            // recycle lambda: redraw anchor and centre until the centre is in the cell (the first
+            // chunk was taken at barrier 3)
+            int found = spec >= 0 ? spec : -1;
+            for (int j0 = spec == -2 ? 0 : CW; j0 < 4096 && found < 0; j0 += CW) {
                 const int jj = j0 + tid;
                 bool h2 = false;
                 double ex = 0, ey = 0, ez = 0;
