@@ -835,11 +835,17 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
             const int64_t row = s.fine_off + (int64_t)nf * (fy + (int64_t)nf * fz);
             const double kx = MXl[k], ky = MYl[k], kz = MZl[k];
             const int xa = f0x, xe = min(f0x + cnx, nf);
-            for (int q2 = D.fstart[row + xa], q3 = D.fstart[row + xe]; q2 < q3; ++q2)
-                term(j, jx, jy, jz, kx, ky, kz, D.fidx[q2]);
-            if (f0x + cnx > nf)
-                for (int q2 = D.fstart[row], q3 = D.fstart[row + (f0x + cnx - nf)]; q2 < q3; ++q2)
-                    term(j, jx, jy, jz, kx, ky, kz, D.fidx[q2]);
+            // the row's beads two at a time, so that the loads of the second overlap the first
+            auto run = [&](int q2, int q3) {
+                for (; q2 + 1 < q3; q2 += 2) {
+                    const int32_t m0 = D.fidx[q2], m1 = D.fidx[q2 + 1];
+                    term(j, jx, jy, jz, kx, ky, kz, m0);
+                    term(j, jx, jy, jz, kx, ky, kz, m1);
+                }
+                if (q2 < q3) term(j, jx, jy, jz, kx, ky, kz, D.fidx[q2]);
+            };
+            run(D.fstart[row + xa], D.fstart[row + xe]);
+            if (f0x + cnx > nf) run(D.fstart[row], D.fstart[row + (f0x + cnx - nf)]);
         }
     } else {
         // infinite system (at most 8192 beads): items are (member, 64-bead block)
@@ -2907,25 +2913,53 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
             direction(cs, px, py, pz);
             const double u_acc = cs.oc();
             __syncthreads();
-            // members in this workgroup's slice of the reach list
-            int cnt = 0;
-            for (int c0 = slo; c0 < shi; c0 += CW) {
-                const int i = c0 + tid;
-                bool f = false;
-                int32_t j = 0;
-                if (i < shi) {
-                    j = Sat(i);
+            // members in this workgroup's slice of the reach list: thread t tests entries t, t + CW,
+            // ... (coalesced loads), one scan orders them thread by thread (any order of the
+            // members gives the same displacements; only the rounding of the sums follows it)
+            int cnt;
+            {
+                uint32_t mask = 0;
+                for (int u = 0, i = slo + tid; i < shi; ++u, i += CW) {
+                    const int32_t j = Sat(i);
                     const double dx = minimg(g, D.x[j] - b[0]), dy = minimg(g, D.y[j] - b[1]),
                                  dz = minimg(g, D.z[j] - b[2]);
-                    f = ((dx * dx + dy * dy) + dz * dz) <= lam2 || j == a;
+                    if (((dx * dx + dy * dy) + dz * dz) <= lam2 || j == a) mask |= 1u << u;
                 }
                 int before;
-                const int tot = block_scan_flag<CW>(f, before, sh.redi);
-                if (f) sh.L[cnt + before] = j;
-                cnt += tot;
+                cnt = block_scan_count<CW>(__popc(mask), before, sh.redi);
+                for (int u = 0, i = slo + tid; i < shi; ++u, i += CW)
+                    if ((mask >> u) & 1u) sh.L[before++] = Sat(i);
             }
             if (tid == 0) ccnt[wg] = cnt;
-            group_barrier(bar, G, gen);  // 1: member counts
+            // Speculation: the first CW tries of the redraw a rejection would need. A rejected test
+            // moves nothing, so they see the positions that redraw would see; after an acceptance
+            // they are dropped. Their draws are taken while the group arrives at barrier 1, their
+            // centres and cell tests at barrier 2; the hit goes to pub_* (read again only after a
+            // redraw; every workgroup finds the same).
+            const bool spec_on = r + 1 < P.retry_cap;
+            int32_t sp_a = 0;
+            double sp_v0 = 0.0, sp_v1 = 0.0, sp_v2 = 0.0;
+            uint32_t sp_next = 0;
+            {
+                bool rel;
+                group_arrive(bar, G, gen, rel);  // 1: member counts
+                if (spec_on) {
+                    // the draws of draw_trial_centre for try tid of retry r + 1
+                    Stream rs;
+                    rs.init(P, sys, sweep, level, key, tc, r + 1, tid);
+                    if (VAR && P.centring == WMC_CENTRE_UNIFORM) {
+                        sp_a = -1;
+                        sp_v0 = g.o[0] + ((double)ic[0] + rs.co()) * g.h;
+                        sp_v1 = g.o[1] + ((double)ic[1] + rs.co()) * g.h;
+                        sp_v2 = g.o[2] + ((double)ic[2] + rs.co()) * g.h;
+                    } else {
+                        sp_a = Sat(rs.index(nS));
+                        ball(rs, sp_v0, sp_v1, sp_v2);
+                    }
+                    sp_next = rs.next;
+                }
+                group_wait(bar, G, gen, rel);
+            }
             int off, n;
             coop_prefix(ccnt, G, wg, sh, off, n);
             WaveDesc wv;
@@ -2956,41 +2990,43 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                 const double m = block_max<CW>(dmax_l, sh.red);
                 if (tid == 0) c_dmax[wg] = m;
             }
-            group_barrier(bar, G, gen);  // 2: members, trial positions, tags
+            // first chunk of the redraw a rejection would need (-1: no hit, -2: not taken)
+            int spec = -2;
+            {
+                bool rel;
+                group_arrive(bar, G, gen, rel);  // 2: members, trial positions, tags
+                if (spec_on) {
+                    double ex = sp_v0, ey = sp_v1, ez = sp_v2;
+                    if (sp_a >= 0) {
+                        double ax, ay, az;
+                        pos_of(sp_a, ax, ay, az);
+                        ex = ax + lam * sp_v0;
+                        ey = ay + lam * sp_v1;
+                        ez = az + lam * sp_v2;
+                    }
+                    const bool h2 = cell_of_point(g, ex, ey, ez) == cell;
+                    const int fj = block_min_int<CW>(h2 ? tid : 0x7FFFFFFF, sh.redi);
+                    if (tid == fj) {
+                        sh.pub_a = sp_a;
+                        sh.pub_b[0] = ex;
+                        sh.pub_b[1] = ey;
+                        sh.pub_b[2] = ez;
+                        sh.pub_next = sp_next;
+                    }
+                    spec = fj == 0x7FFFFFFF ? -1 : fj;
+                }
+                group_wait(bar, G, gen, rel);
+            }
             const double dmax = coop_max(c_dmax, G, sh);
             const double Rq = P.rc + 2.0 * dmax + fmax(Dg, dloc) + 1e-9 * L;
             const double thr = accept_threshold<VAR>(P, u_acc);
             double dU;
-            // first chunk of the redraw a rejection would need (-1: no hit, -2: not taken)
-            int spec = -2;
             {
                 double acc = 0.0;
                 glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, gt, gstride, acc, c_viol);
                 const double pa = block_sum<CW>(acc, sh.red);
                 if (tid == 0) c_acc[wg] = pa;
-                bool rel;
-                group_arrive(bar, G, gen, rel);  // 3: partial sums
-                if (r + 1 < P.retry_cap) {
-                    // While the group arrives, this workgroup takes the first CW tries of that redraw:
-                    // a rejected test moves nothing, so they see the positions the redraw would see
-                    // (after an acceptance they are discarded). The hit goes to pub_* (read again
-                    // only after a redraw); every workgroup finds the same.
-                    double ex = 0, ey = 0, ez = 0;
-                    int32_t a2 = 0;
-                    Stream rs;
-                    rs.init(P, sys, sweep, level, key, tc, r + 1, tid);
-                    const bool h2 = draw_trial_centre<VAR>(P, rs, g, ic, cell, lam, nS, Sat, pos_of, a2, ex, ey, ez);
-                    const int fj = block_min_int<CW>(h2 ? tid : 0x7FFFFFFF, sh.redi);
-                    if (tid == fj) {
-                        sh.pub_a = a2;
-                        sh.pub_b[0] = ex;
-                        sh.pub_b[1] = ey;
-                        sh.pub_b[2] = ez;
-                        sh.pub_next = rs.next;
-                    }
-                    spec = fj == 0x7FFFFFFF ? -1 : fj;
-                }
-                group_wait(bar, G, gen, rel);
+                group_barrier(bar, G, gen);  // 3: partial sums
                 dU = coop_sum(c_acc, G, sh);
             }
             const bool accept = dU <= thr;
@@ -3025,7 +3061,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                 break;
             }
             // recycle lambda: redraw anchor and centre until the centre is in the cell (the first
-            // chunk was taken at barrier 3)
+            // chunk was taken at barriers 1 and 2)
             int found = spec >= 0 ? spec : -1;
             for (int j0 = spec == -2 ? 0 : CW; j0 < 4096 && found < 0; j0 += CW) {
                 const int jj = j0 + tid;
