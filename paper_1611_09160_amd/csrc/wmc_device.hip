@@ -1649,8 +1649,16 @@ __device__ __forceinline__ int tile_find(const TileShared<W, CAPH, CAPM, NCD, T>
 // FP64 terms. On an FP32 tile (T = float, WV = WaveDesc32) this is the FP64 recheck: the same bonds and pairs
 // (found from the FP32 tile), evaluated from the FP64 positions in HBM plus the FP32 displacements
 // that an accept would apply.
+// The wave with the least work in the energy layout below: the last one, unless it holds the bonds
+// (split layout) while the pair items leave lanes of the last pair wave idle.
+template <int W>
+__device__ __forceinline__ int tile_light_wave(bool split, int items, int G) {
+    return split && items * G < W - 64 ? W / 64 - 2 : W / 64 - 1;
+}
+
+// returns the wave with the least work (tile_light_wave)
 template <int W, int CAPH, int CAPM, int NCD, class T = double, class WV = WaveDesc>
-__device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
+__device__ int tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                         const TileShared<W, CAPH, CAPM, NCD, T>& sh, const Grid& g, const TileGeo& tg,
                         const WV& wv, double R,
                         int nH, int n, double& acc, unsigned long long& viol, float rc2g = 0.0f,
@@ -1781,6 +1789,7 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
             }
         }
     }
+    return tile_light_wave<W>(split, items, G);
 }
 
 // Energy change of the current test on an FP32 tile: the bonds and pairs of tile_dU, with FP32
@@ -1788,7 +1797,7 @@ __device__ void tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
 // s1 and s2 sum every counted term's sensitivity and sensitivity / r for the recheck margin; a
 // pair that FP32 places just outside the cut-off (r2 < rc2g) adds the sensitivity at the cut-off.
 template <int W, int CAPH, int CAPM, int NCD>
-__device__ void tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared<W, CAPH, CAPM, NCD, float>& sh,
+__device__ int tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared<W, CAPH, CAPM, NCD, float>& sh,
                           const Grid& g, const TileGeo& tg, const WaveDesc32& wv, double R, int nH, int n, bool wrap,
                           float Lf, float invLf, float rc2f, float rc2g, float Rp2f, double& acc, float& s1,
                           float& s2, unsigned long long& viol) {
@@ -1900,6 +1909,7 @@ __device__ void tile_dU32(const DevParams& P, const DevPtrs& D, const TileShared
             }
         }
     }
+    return tile_light_wave<W>(split, items, G);
 }
 
 // returns false (before any move) when the halo does not fit; the caller then uses the
@@ -2125,13 +2135,13 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     };
     // The first 16 tries of the redraw that follows a rejection, taken speculatively while the test
     // is evaluated: a rejected test moves nothing, so they see the positions the redraw would see.
-    // The last wave, which holds the fewest pair items, takes them after its own items; the first hit
-    // goes to pub_* (read again only after a redraw; an accepted test ends the chain, whose successor
-    // publishes its own centre) and its try index, or -1, to spec_found, both read after the
-    // reduction barrier of the energy sum. Wider tiles only: a one-wave tile would take them serially.
+    // The wave with the least energy work takes them after its own; the first hit goes to pub_*
+    // (read again only after a redraw; an accepted test ends the chain, whose successor publishes
+    // its own centre) and its try index, or -1, to spec_found, both read after the reduction barrier
+    // of the energy sum. Wider tiles only: a one-wave tile would take them serially.
     constexpr bool SPEC = W >= 256;
-    auto spec_redraw = [&](int64_t tc, int rn, double lam) {
-        if ((tid >> 6) != W / 64 - 1) return;
+    auto spec_redraw = [&](int64_t tc, int rn, double lam, int wave) {
+        if ((tid >> 6) != wave) return;
         const int lane = tid & 63;
         bool h2 = false;
         double ex = 0, ey = 0, ez = 0;
@@ -2385,9 +2395,9 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 float s1 = 0.0f, s2 = 0.0f;
                 const double rp = P.rc + 2.0 * dmax;
                 const float Rp2f = (float)(rp * rp * ((double)rc2g / P.rc2) * (1.0 + 0x1p-9));
-                tile_dU32<W, CAPH, CAPM, NCD>(P, D, sh, g, tg, wv32, Rq, nH, n, wrap, (float)L, (float)invL,
-                                              (float)P.rc2, rc2g, Rp2f, acc, s1, s2, c_viol);
-                if (SPEC && r + 1 < P.retry_cap) spec_redraw(tc, r + 1, lam);
+                const int light = tile_dU32<W, CAPH, CAPM, NCD>(P, D, sh, g, tg, wv32, Rq, nH, n, wrap, (float)L,
+                                                                (float)invL, (float)P.rc2, rc2g, Rp2f, acc, s1, s2, c_viol);
+                if (SPEC && r + 1 < P.retry_cap) spec_redraw(tc, r + 1, lam, light);
                 double S1 = (double)s1, S2 = (double)s2;
                 dU = acc;
                 xsum3<W>(dU, S1, S2, sh.xc, xp);
@@ -2418,8 +2428,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 }
             } else {
                 const double rp = (P.rc + 2.0 * dmax) * (1.0 + 1e-12);
-                tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, acc, c_viol, 0.0f, rp * rp);
-                if (SPEC && r + 1 < P.retry_cap) spec_redraw(tc, r + 1, lam);
+                const int light = tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, acc, c_viol, 0.0f, rp * rp);
+                if (SPEC && r + 1 < P.retry_cap) spec_redraw(tc, r + 1, lam, light);
                 dU = xsum<W>(acc, sh.xc, xp);
             }
             const bool accept = dU <= thr;
@@ -2775,6 +2785,7 @@ struct CoopShared {
     int32_t pub_a;
     uint32_t pub_next;
     int pub_off;
+    int spec_found;  // first hit of the speculative redraw tries, -1 if none
 };
 
 // exclusive prefix (at the workgroup of rank wg in its group) and total of the group's
@@ -2931,11 +2942,12 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                     if ((mask >> u) & 1u) sh.L[before++] = Sat(i);
             }
             if (tid == 0) ccnt[wg] = cnt;
-            // Speculation: the first CW tries of the redraw a rejection would need. A rejected test
+            // Speculation: the first 16 tries of the redraw a rejection would need, on the first 16
+            // lanes (the ball's rejection loop lasts as long as its slowest lane). A rejected test
             // moves nothing, so they see the positions that redraw would see; after an acceptance
             // they are dropped. Their draws are taken while the group arrives at barrier 1, their
             // centres and cell tests at barrier 2; the hit goes to pub_* (read again only after a
-            // redraw; every workgroup finds the same).
+            // redraw; every workgroup finds the same) and its try index, or -1, to spec_found.
             const bool spec_on = r + 1 < P.retry_cap;
             int32_t sp_a = 0;
             double sp_v0 = 0.0, sp_v1 = 0.0, sp_v2 = 0.0;
@@ -2943,7 +2955,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
             {
                 bool rel;
                 group_arrive(bar, G, gen, rel);  // 1: member counts
-                if (spec_on) {
+                if (spec_on && tid < 16) {
                     // the draws of draw_trial_centre for try tid of retry r + 1
                     Stream rs;
                     rs.init(P, sys, sweep, level, key, tc, r + 1, tid);
@@ -2990,22 +3002,24 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                 const double m = block_max<CW>(dmax_l, sh.red);
                 if (tid == 0) c_dmax[wg] = m;
             }
-            // first chunk of the redraw a rejection would need (-1: no hit, -2: not taken)
-            int spec = -2;
             {
                 bool rel;
                 group_arrive(bar, G, gen, rel);  // 2: members, trial positions, tags
-                if (spec_on) {
+                if (spec_on && tid < 64) {
+                    bool h2 = false;
                     double ex = sp_v0, ey = sp_v1, ez = sp_v2;
-                    if (sp_a >= 0) {
-                        double ax, ay, az;
-                        pos_of(sp_a, ax, ay, az);
-                        ex = ax + lam * sp_v0;
-                        ey = ay + lam * sp_v1;
-                        ez = az + lam * sp_v2;
+                    if (tid < 16) {
+                        if (sp_a >= 0) {
+                            double ax, ay, az;
+                            pos_of(sp_a, ax, ay, az);
+                            ex = ax + lam * sp_v0;
+                            ey = ay + lam * sp_v1;
+                            ez = az + lam * sp_v2;
+                        }
+                        h2 = cell_of_point(g, ex, ey, ez) == cell;
                     }
-                    const bool h2 = cell_of_point(g, ex, ey, ez) == cell;
-                    const int fj = block_min_int<CW>(h2 ? tid : 0x7FFFFFFF, sh.redi);
+                    const uint64_t hits = __ballot(h2);
+                    const int fj = hits ? __builtin_ctzll(hits) : -1;
                     if (tid == fj) {
                         sh.pub_a = sp_a;
                         sh.pub_b[0] = ex;
@@ -3013,10 +3027,12 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                         sh.pub_b[2] = ez;
                         sh.pub_next = sp_next;
                     }
-                    spec = fj == 0x7FFFFFFF ? -1 : fj;
+                    if (tid == 0) sh.spec_found = fj;
                 }
                 group_wait(bar, G, gen, rel);
             }
+            // first 16 tries of the redraw a rejection would need (-1: no hit, -2: not taken)
+            const int spec = spec_on ? sh.spec_found : -2;
             const double dmax = coop_max(c_dmax, G, sh);
             const double Rq = P.rc + 2.0 * dmax + fmax(Dg, dloc) + 1e-9 * L;
             const double thr = accept_threshold<VAR>(P, u_acc);
@@ -3063,7 +3079,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
             // recycle lambda: redraw anchor and centre until the centre is in the cell (the first
             // chunk was taken at barriers 1 and 2)
             int found = spec >= 0 ? spec : -1;
-            for (int j0 = spec == -2 ? 0 : CW; j0 < 4096 && found < 0; j0 += CW) {
+            for (int j0 = spec == -2 ? 0 : 16; j0 < 4096 && found < 0; j0 += CW) {
                 const int jj = j0 + tid;
                 bool h2 = false;
                 double ex = 0, ey = 0, ez = 0;
