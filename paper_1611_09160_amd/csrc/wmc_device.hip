@@ -2945,33 +2945,11 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
             // Speculation: the first 16 tries of the redraw a rejection would need, on the first 16
             // lanes (the ball's rejection loop lasts as long as its slowest lane). A rejected test
             // moves nothing, so they see the positions that redraw would see; after an acceptance
-            // they are dropped. Their draws are taken while the group arrives at barrier 1, their
-            // centres and cell tests at barrier 2; the hit goes to pub_* (read again only after a
+            // they are dropped. Their draws are taken while the group arrives at barrier 2, their
+            // centres and cell tests at barrier 3; the hit goes to pub_* (read again only after a
             // redraw; every workgroup finds the same) and its try index, or -1, to spec_found.
             const bool spec_on = r + 1 < P.retry_cap;
-            int32_t sp_a = 0;
-            double sp_v0 = 0.0, sp_v1 = 0.0, sp_v2 = 0.0;
-            uint32_t sp_next = 0;
-            {
-                bool rel;
-                group_arrive(bar, G, gen, rel);  // 1: member counts
-                if (spec_on && tid < 16) {
-                    // the draws of draw_trial_centre for try tid of retry r + 1
-                    Stream rs;
-                    rs.init(P, sys, sweep, level, key, tc, r + 1, tid);
-                    if (VAR && P.centring == WMC_CENTRE_UNIFORM) {
-                        sp_a = -1;
-                        sp_v0 = g.o[0] + ((double)ic[0] + rs.co()) * g.h;
-                        sp_v1 = g.o[1] + ((double)ic[1] + rs.co()) * g.h;
-                        sp_v2 = g.o[2] + ((double)ic[2] + rs.co()) * g.h;
-                    } else {
-                        sp_a = Sat(rs.index(nS));
-                        ball(rs, sp_v0, sp_v1, sp_v2);
-                    }
-                    sp_next = rs.next;
-                }
-                group_wait(bar, G, gen, rel);
-            }
+            group_barrier(bar, G, gen);  // 1: member counts
             int off, n;
             coop_prefix(ccnt, G, wg, sh, off, n);
             WaveDesc wv;
@@ -3002,10 +2980,42 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                 const double m = block_max<CW>(dmax_l, sh.red);
                 if (tid == 0) c_dmax[wg] = m;
             }
+            int32_t sp_a = 0;
+            double sp_v0 = 0.0, sp_v1 = 0.0, sp_v2 = 0.0;
+            uint32_t sp_next = 0;
             {
                 bool rel;
                 group_arrive(bar, G, gen, rel);  // 2: members, trial positions, tags
+                if (spec_on && tid < 16) {
+                    // the draws of draw_trial_centre for try tid of retry r + 1
+                    Stream rs;
+                    rs.init(P, sys, sweep, level, key, tc, r + 1, tid);
+                    if (VAR && P.centring == WMC_CENTRE_UNIFORM) {
+                        sp_a = -1;
+                        sp_v0 = g.o[0] + ((double)ic[0] + rs.co()) * g.h;
+                        sp_v1 = g.o[1] + ((double)ic[1] + rs.co()) * g.h;
+                        sp_v2 = g.o[2] + ((double)ic[2] + rs.co()) * g.h;
+                    } else {
+                        sp_a = Sat(rs.index(nS));
+                        ball(rs, sp_v0, sp_v1, sp_v2);
+                    }
+                    sp_next = rs.next;
+                }
+                group_wait(bar, G, gen, rel);
+            }
+            const double dmax = coop_max(c_dmax, G, sh);
+            const double Rq = P.rc + 2.0 * dmax + fmax(Dg, dloc) + 1e-9 * L;
+            const double thr = accept_threshold<VAR>(P, u_acc);
+            double dU;
+            {
+                double acc = 0.0;
+                glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, gt, gstride, acc, c_viol);
+                const double pa = block_sum<CW>(acc, sh.red);
+                if (tid == 0) c_acc[wg] = pa;
+                bool rel;
+                group_arrive(bar, G, gen, rel);  // 3: partial sums
                 if (spec_on && tid < 64) {
+                    // (positions are unchanged unless the test is accepted, which drops this)
                     bool h2 = false;
                     double ex = sp_v0, ey = sp_v1, ez = sp_v2;
                     if (tid < 16) {
@@ -3030,21 +3040,10 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                     if (tid == 0) sh.spec_found = fj;
                 }
                 group_wait(bar, G, gen, rel);
+                dU = coop_sum(c_acc, G, sh);
             }
             // first 16 tries of the redraw a rejection would need (-1: no hit, -2: not taken)
             const int spec = spec_on ? sh.spec_found : -2;
-            const double dmax = coop_max(c_dmax, G, sh);
-            const double Rq = P.rc + 2.0 * dmax + fmax(Dg, dloc) + 1e-9 * L;
-            const double thr = accept_threshold<VAR>(P, u_acc);
-            double dU;
-            {
-                double acc = 0.0;
-                glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, gt, gstride, acc, c_viol);
-                const double pa = block_sum<CW>(acc, sh.red);
-                if (tid == 0) c_acc[wg] = pa;
-                group_barrier(bar, G, gen);  // 3: partial sums
-                dU = coop_sum(c_acc, G, sh);
-            }
             const bool accept = dU <= thr;
             if (wg == 0 && tid == 0) trace_push(D, 0, sys, sweep, level, key, tc, r, n, accept ? 1 : 0, a, dU, thr);
             ++c_att;
@@ -3077,7 +3076,7 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
                 break;
             }
             // recycle lambda: redraw anchor and centre until the centre is in the cell (the first
-            // chunk was taken at barriers 1 and 2)
+            // 16 tries were taken at barriers 2 and 3)
             int found = spec >= 0 ? spec : -1;
             for (int j0 = spec == -2 ? 0 : 16; j0 < 4096 && found < 0; j0 += CW) {
                 const int jj = j0 + tid;
