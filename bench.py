@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-others", action="store_true", help="skip the dilute and ideal-chain lines")
     ap.add_argument("--batch-equilibrate", type=int, default=100)
-    ap.add_argument("--tune", type=int, default=3, metavar="K",
+    ap.add_argument("--tune", type=int, default=6, metavar="K",
                     help="launch tuning before the timed sweeps, K trial sweeps per choice (0: the plan's launches)")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MB",
                     help="only copy a buffer of MB megabytes 4 times (reference for HBM byte counters)")

@@ -2290,6 +2290,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             // (no barrier here: whatever a test reads from LDS before its member scan, the centre in
             // pub_* included, was written before a barrier)
             int n = 0;
+            int own_k = -1, own_sl = 0;  // a one-round scan's member of this thread
             if (W >= 256 && nS > W && nS <= 32 * W) {
                 // q consecutive reach entries per thread, one workgroup scan (member order kept);
                 // a one-wave tile keeps the round-by-round scan, which measured faster there
@@ -2303,6 +2304,22 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 n = xscan_count<W>(__popc(mask), before, sh.xc, xp);
                 for (int u = 0; u < q; ++u)
                     if ((mask >> u) & 1u) sh.M[before++] = sh.S[i0 + u];
+            } else if (nS <= W) {
+                // one round: a thread holds at most one member and displaces it itself below, so the
+                // member list needs no barrier before the displacements
+                bool f = false;
+                int sl = 0;
+                if (tid < nS) {
+                    sl = sh.S[tid];
+                    f = in_ball(sl);
+                }
+                int before;
+                n = xscan_flag<W>(f, before, sh.xc, xp);
+                if (f) {
+                    sh.M[before] = (int16_t)sl;
+                    own_k = before;
+                    own_sl = sl;
+                }
             } else {
                 for (int c0 = 0; c0 < nS; c0 += W) {
                     int i = c0 + tid;
@@ -2318,7 +2335,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                     n += tot;
                 }
             }
-            __syncthreads();
+            if (nS > W) __syncthreads();
             WaveDesc wv;
             wv.b[0] = b[0];
             wv.b[1] = b[1];
@@ -2342,8 +2359,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 wv32.invlam = (float)(1.0 / lam);
                 wv32.A = (float)wv.A;
                 wv32.rot = wv.rot;
-                for (int k = tid; k < n; k += W) {
-                    const int sl = sh.M[k];
+                for (int k = nS <= W ? own_k : tid; k >= 0 && k < n; k += nS <= W ? n : W) {
+                    const int sl = nS <= W ? own_sl : sh.M[k];
                     float w0, w1, w2;
                     wavelet_disp32(wv32, sh.x[sl], sh.y[sl], sh.z[sl], w0, w1, w2);
                     if (CAPM > 0 && k < CAPM) {
@@ -2355,8 +2372,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                     dmax_l = fmax(dmax_l, (double)sqrtf((w0 * w0 + w1 * w1) + w2 * w2));
                 }
             } else {
-                for (int k = tid; k < n; k += W) {
-                    const int sl = sh.M[k];
+                for (int k = nS <= W ? own_k : tid; k >= 0 && k < n; k += nS <= W ? n : W) {
+                    const int sl = nS <= W ? own_sl : sh.M[k];
                     double w0, w1, w2;
                     wavelet_disp(g, wv, sh.x[sl], sh.y[sl], sh.z[sl], w0, w1, w2);
                     if (CAPM > 0 && k < CAPM) {
