@@ -1649,14 +1649,18 @@ __device__ __forceinline__ int tile_find(const TileShared<W, CAPH, CAPM, NCD, T>
 // FP64 terms. On an FP32 tile (T = float, WV = WaveDesc32) this is the FP64 recheck: the same bonds and pairs
 // (found from the FP32 tile), evaluated from the FP64 positions in HBM plus the FP32 displacements
 // that an accept would apply.
-// The wave with the least work in the energy layout below: the last one, unless it holds the bonds
-// (split layout) while the pair items leave lanes of the last pair wave idle.
+// A wave with slack in the energy layout below, or -1: in the split layout the last pair wave when
+// the pair items leave it idle (the bond wave is nearly as busy as the pair waves); otherwise the
+// last wave when its lanes take fewer rounds of pair items than the first lanes.
 template <int W>
 __device__ __forceinline__ int tile_light_wave(bool split, int items, int G) {
-    return split && items * G < W - 64 ? W / 64 - 2 : W / 64 - 1;
+    const int slots = items * G;
+    if (split) return slots <= W - 128 ? W / 64 - 2 : -1;
+    const int first = (slots + W - 1) / W, last = slots > W - 1 ? (slots - W) / W + 1 : 0;
+    return last < first ? W / 64 - 1 : -1;
 }
 
-// returns the wave with the least work (tile_light_wave)
+// returns a wave with slack (tile_light_wave)
 template <int W, int CAPH, int CAPM, int NCD, class T = double, class WV = WaveDesc>
 __device__ int tile_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s,
                         const TileShared<W, CAPH, CAPM, NCD, T>& sh, const Grid& g, const TileGeo& tg,
@@ -2135,10 +2139,10 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
     };
     // The first 16 tries of the redraw that follows a rejection, taken speculatively while the test
     // is evaluated: a rejected test moves nothing, so they see the positions the redraw would see.
-    // The wave with the least energy work takes them after its own; the first hit goes to pub_*
-    // (read again only after a redraw; an accepted test ends the chain, whose successor publishes
-    // its own centre) and its try index, or -1, to spec_found, both read after the reduction barrier
-    // of the energy sum. Wider tiles only: a one-wave tile would take them serially.
+    // A wave with slack in the energy sum takes them after its own work (with none, the redraw runs
+    // as usual); the first hit goes to pub_* (read again only after a redraw; an accepted test ends
+    // the chain, whose successor publishes its own centre) and its try index, or -1, to spec_found,
+    // both read after the reduction barrier of the energy sum. Wider tiles only.
     constexpr bool SPEC = W >= 256;
     auto spec_redraw = [&](int64_t tc, int rn, double lam, int wave) {
         if ((tid >> 6) != wave) return;
@@ -2392,6 +2396,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             double acc = 0.0;
             const double thr = accept_threshold<VAR>(P, u_acc);
             double dU;
+            bool spec_taken = false;  // the first redraw tries were taken during the energy sum
             if constexpr (F32) {
                 // error of the FP32 sum (eps = 2^-24; every offset magnitude <= Hq). Worst case: an
                 // offset carries <= eps Hq, the centre's <= 3 eps Hq, so x_r is off by <= 5 eps Hq/lambda
@@ -2414,7 +2419,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
                 const float Rp2f = (float)(rp * rp * ((double)rc2g / P.rc2) * (1.0 + 0x1p-9));
                 const int light = tile_dU32<W, CAPH, CAPM, NCD>(P, D, sh, g, tg, wv32, Rq, nH, n, wrap, (float)L,
                                                                 (float)invL, (float)P.rc2, rc2g, Rp2f, acc, s1, s2, c_viol);
-                if (SPEC && r + 1 < P.retry_cap) spec_redraw(tc, r + 1, lam, light);
+                spec_taken = SPEC && r + 1 < P.retry_cap && light >= 0;
+                if (spec_taken) spec_redraw(tc, r + 1, lam, light);
                 double S1 = (double)s1, S2 = (double)s2;
                 dU = acc;
                 xsum3<W>(dU, S1, S2, sh.xc, xp);
@@ -2446,7 +2452,8 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             } else {
                 const double rp = (P.rc + 2.0 * dmax) * (1.0 + 1e-12);
                 const int light = tile_dU<W, CAPH, CAPM, NCD>(P, D, s, sh, g, tg, wv, Rq, nH, n, acc, c_viol, 0.0f, rp * rp);
-                if (SPEC && r + 1 < P.retry_cap) spec_redraw(tc, r + 1, lam, light);
+                spec_taken = SPEC && r + 1 < P.retry_cap && light >= 0;
+                if (spec_taken) spec_redraw(tc, r + 1, lam, light);
                 dU = xsum<W>(acc, sh.xc, xp);
             }
             const bool accept = dU <= thr;
@@ -2506,7 +2513,7 @@ __device__ __forceinline__ bool process_cell_tile(const DevParams& P, const DevP
             // slowest lane, so a narrow first chunk is cheaper; wider tiles took it during the
             // test), then W at a time
             int found = -1, j_first = 0;
-            if (SPEC) {
+            if (spec_taken) {
                 found = sh.spec_found;
                 j_first = 16;
             }
