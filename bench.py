@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # scaled by a plain copy of known size (profiles/traffic_sweep_semidilute32k.md; levels 3 and 4 share
 # one cell-group kernel, whose average is given for both); valid only for the device source they
 # were measured on, otherwise the bench reports null
-TRAFFIC_SOURCE_SHA16 = "ffd2d21dbd5de7e1"
-TRAFFIC_BYTES_PER_LAUNCH = {"level0": 53.68e6, "level1": 17.18e6, "level2": 16.74e6, "level3": 6.29e6, "level4": 6.29e6, "plane_waves": 28.95e6, "grid": 9.59e6}
+TRAFFIC_SOURCE_SHA16 = "94c0460f4655adb5"
+TRAFFIC_BYTES_PER_LAUNCH = {"level0": 37.28e6, "level1": 17.05e6, "level2": 17.04e6, "level3": 6.14e6, "level4": 6.14e6, "plane_waves": 28.97e6, "grid": 9.59e6}
 
 
 def measured_traffic(cls: str):
