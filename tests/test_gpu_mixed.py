@@ -76,3 +76,23 @@ def test_mixed_long_run_statistics():
               f"(standard error {s:.1e})")
         assert abs(m["cov"][i] - f["cov"][i]) <= 5.0 * s
     print(f"mixed: {m['attempts']} tests, {m['rechecks']} decision rechecks, {m['member_rechecks']} support rechecks")
+
+
+def test_margin_over_a_long_run():
+    """mixed_verify over 100 sweeps of the 32,768-bead solution from its generated start (millions of
+    FP32-tile tests, each evaluated in FP64 too): the FP32 error of the energy change never reaches
+    the recheck margin, so every decision taken without a recheck is the FP64 one."""
+    from paper_1611_09160_amd import wmc, workloads as W
+
+    cfg = W.config(3)
+    g = wmc.WMC(dict(cfg["params"], precision="mixed", mixed_verify=1), cfg["sys_offset"], cfg["chain_offset"],
+                cfg["pos"], trace_capacity=0)
+    for k in range(10):
+        g.sweep(10)
+        ob = g.observables()
+        print(f"{10 * (k + 1)} sweeps: verified tests {ob['margin_checks']}, max |dU32 - dU64| / margin "
+              f"{ob['margin_max_ratio']:.4f}, rechecks {ob['rechecks']}", flush=True)
+    g.close()
+    assert ob["margin_checks"] > 5_000_000, ob["margin_checks"]
+    assert ob["margin_fails"] == 0 and ob["margin_max_ratio"] < 1.0, (ob["margin_fails"], ob["margin_max_ratio"])
+    assert ob["overflows"] == 0 and ob["wait_timeouts"] == 0
