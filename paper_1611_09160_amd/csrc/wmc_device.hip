@@ -779,7 +779,7 @@ __device__ __forceinline__ void cell_coords(const DevParams& P, const LevelDesc&
 // Work items are dealt to threads t0, t0 + stride, ... (one workgroup, or a whole grid).
 __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, const int32_t* Ml, const double* MXl,
                         const double* MYl, const double* MZl, int n, double R, int t0, int stride,
-                        double& acc, unsigned long long& viol) {
+                        double& acc, unsigned long long& viol, bool pairs = true) {
     const double L = s.L, invL = s.invL;
     auto term = [&](int32_t j, double jx, double jy, double jz, double kx, double ky, double kz, int32_t m) {
         if (m == j) return;
@@ -813,7 +813,7 @@ __device__ void glob_dU(const DevParams& P, const DevPtrs& D, const SysDesc& s, 
             }
         }
     }
-    if (!P.wca) return;
+    if (!P.wca || !pairs) return;
     if (P.periodic) {
         const int nf = s.nf;
         const int NR = min(nf, (int)floor(2.0 * R * s.invg) + 2);
@@ -2800,8 +2800,16 @@ constexpr int CW = 256;     // threads per workgroup
 constexpr int CAPL = COOP_LIST_CAP;  // list entries one workgroup keeps in LDS
 constexpr int CMAXG = 256;  // at most this many workgroups per group (one count per thread)
 
+constexpr int CPB = 512;  // (member, row) items per batch of the balanced pair search
+
 struct CoopShared {
     int32_t L[CAPL];
+    // balanced pair search: per item the member's current and trial position, its bead, the start
+    // of its row's first and second (wrapped) run of the sorted index and the first run's length,
+    // and the exclusive prefix of the items' candidate counts
+    double ip[6][CPB];
+    int32_t ij[CPB], is0[CPB], il0[CPB], is1[CPB];
+    int32_t pre[CPB + 1];
     double red[CW / 64];
     int redi[CW / 64];
     double pub_b[3];
@@ -2828,6 +2836,116 @@ __device__ __forceinline__ double coop_sum(const double* part, int G, CoopShared
 }
 __device__ __forceinline__ double coop_max(const double* part, int G, CoopShared& sh) {
     return block_max<CW>((int)threadIdx.x < G ? part[threadIdx.x] : 0.0, sh.red);
+}
+
+// Pair energy changes of a cell group's test, balanced over the lanes of each workgroup. The
+// (member, grid row) items of the pair search are split into equal contiguous blocks per workgroup.
+// A batch of items is first resolved into its row runs of the sorted neighbour index (member data
+// and run bounds in LDS); a workgroup scan of the runs' lengths then gives every thread an equal,
+// contiguous share of the batch's candidate partners (found by one binary search, then walked), so
+// a long row no longer holds up its lane while the others idle. Same terms as glob_dU's pair part;
+// only the order of the sum differs.
+__device__ void coop_pairs(const DevParams& P, const DevPtrs& D, const SysDesc& s, const int32_t* Ml,
+                           const double* MXl, const double* MYl, const double* MZl, int n, double R, int wg,
+                           int G, CoopShared& sh, double& acc) {
+    const int tid = threadIdx.x;
+    const double L = s.L, invL = s.invL;
+    const int nf = s.nf;
+    const int NR = min(nf, (int)floor(2.0 * R * s.invg) + 2);
+    const int per = NR * NR;
+    const int total = n * per;
+    const int Q = (total + G - 1) / G;
+    const int i0 = min(total, wg * Q), i1 = min(total, i0 + Q);
+    for (int b0 = i0; b0 < i1; b0 += CPB) {
+        const int nb = min(CPB, i1 - b0);
+        // 1. items: member data and row runs
+        for (int i = tid; i < nb; i += CW) {
+            const int it = b0 + i;
+            const int k = it / per, q = it - k * per;
+            const int qy = q % NR, qz = q / NR;
+            const int32_t j = Ml[k];
+            const double jx = D.x[j], jy = D.y[j], jz = D.z[j];
+            int f0y, cny, f0z, cnz;
+            fine_range(wrap01(jy, L, invL) - R, wrap01(jy, L, invL) + R, s.invg, nf, f0y, cny);
+            fine_range(wrap01(jz, L, invL) - R, wrap01(jz, L, invL) + R, s.invg, nf, f0z, cnz);
+            int cnt = 0;
+            if (qy < cny && qz < cnz) {
+                int f0x, cnx;
+                const double cx = wrap01(jx, L, invL);
+                fine_range(cx - R, cx + R, s.invg, nf, f0x, cnx);
+                const int fy = (f0y + qy) % nf, fz = (f0z + qz) % nf;
+                const int64_t row = s.fine_off + (int64_t)nf * (fy + (int64_t)nf * fz);
+                const int xe = min(f0x + cnx, nf);
+                const int s0 = D.fstart[row + f0x], l0 = D.fstart[row + xe] - s0;
+                int s1 = 0, l1 = 0;
+                if (f0x + cnx > nf) {
+                    s1 = D.fstart[row];
+                    l1 = D.fstart[row + (f0x + cnx - nf)] - s1;
+                }
+                cnt = l0 + l1;
+                sh.ip[0][i] = jx;
+                sh.ip[1][i] = jy;
+                sh.ip[2][i] = jz;
+                sh.ip[3][i] = MXl[k];
+                sh.ip[4][i] = MYl[k];
+                sh.ip[5][i] = MZl[k];
+                sh.ij[i] = j;
+                sh.is0[i] = s0;
+                sh.il0[i] = l0;
+                sh.is1[i] = s1;
+            }
+            sh.pre[i] = cnt;
+        }
+        __syncthreads();
+        // 2. exclusive prefix of the candidate counts (each thread sums CPB / CW consecutive items)
+        {
+            constexpr int PT = CPB / CW;
+            int v[PT], run = 0;
+            for (int u = 0; u < PT; ++u) {
+                const int i = tid * PT + u;
+                v[u] = i < nb ? sh.pre[i] : 0;
+                run += v[u];
+            }
+            int before;
+            const int tot = block_scan_count<CW>(run, before, sh.redi);
+            for (int u = 0; u < PT; ++u) {
+                const int i = tid * PT + u;
+                if (i < nb) sh.pre[i] = before;
+                before += v[u];
+            }
+            if (tid == 0) sh.pre[nb] = tot;
+        }
+        __syncthreads();
+        // 3. an equal contiguous share of the candidates per thread
+        const int C = sh.pre[nb];
+        const int ch = (C + CW - 1) / CW;
+        int c = tid * ch;
+        const int cend = min(C, c + ch);
+        if (c < cend) {
+            int lo = 0, hi = nb - 1;  // the last item whose prefix is <= c
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sh.pre[mid] <= c) lo = mid; else hi = mid - 1;
+            }
+            int i = lo;
+            for (; c < cend; ++c) {
+                while (sh.pre[i + 1] <= c) ++i;
+                const int o = c - sh.pre[i];
+                const int l0 = sh.il0[i];
+                const int32_t m = D.fidx[o < l0 ? sh.is0[i] + o : sh.is1[i] + (o - l0)];
+                const int32_t j = sh.ij[i];
+                if (m == j) continue;
+                const int km = D.tag[m];
+                if (km >= 0 && m < j) continue;
+                const double mx = D.x[m], my = D.y[m], mz = D.z[m];
+                const double nx = km >= 0 ? MXl[km] : mx, ny = km >= 0 ? MYl[km] : my, nz = km >= 0 ? MZl[km] : mz;
+                const double r2o = pair_r2(P, invL, L, sh.ip[0][i], sh.ip[1][i], sh.ip[2][i], mx, my, mz);
+                const double r2n = pair_r2(P, invL, L, sh.ip[3][i], sh.ip[4][i], sh.ip[5][i], nx, ny, nz);
+                if (r2o < P.rc2 || r2n < P.rc2) acc += u_pair(P, r2n) - u_pair(P, r2o);
+            }
+        }
+        __syncthreads();  // the next batch rewrites the arrays
+    }
 }
 
 // one cell of colour `colour` for the group `grp` (index gi); gen is the group's barrier
@@ -3033,7 +3151,8 @@ __device__ void coop_cell(const DevParams& P, const DevPtrs& D, int level, int c
             double dU;
             {
                 double acc = 0.0;
-                glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, gt, gstride, acc, c_viol);
+                glob_dU(P, D, s, Mg, MXg, MYg, MZg, n, Rq, gt, gstride, acc, c_viol, false);  // bonds
+                if (P.wca) coop_pairs(P, D, s, Mg, MXg, MYg, MZg, n, Rq, wg, G, sh, acc);
                 const double pa = block_sum<CW>(acc, sh.red);
                 if (tid == 0) c_acc[wg] = pa;
                 bool rel;
