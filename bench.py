@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # scaled by a plain copy of known size (profiles/traffic_sweep_semidilute32k.md; levels 3 and 4 share
 # one cell-group kernel, whose average is given for both); valid only for the device source they
 # were measured on, otherwise the bench reports null
-TRAFFIC_SOURCE_SHA16 = "94c0460f4655adb5"
-TRAFFIC_BYTES_PER_LAUNCH = {"level0": 37.28e6, "level1": 17.05e6, "level2": 17.04e6, "level3": 6.14e6, "level4": 6.14e6, "plane_waves": 28.97e6, "grid": 9.59e6}
+TRAFFIC_SOURCE_SHA16 = "81d604046c9f7362"
+TRAFFIC_BYTES_PER_LAUNCH = {"level0": 42.86e6, "level1": 17.40e6, "level2": 16.88e6, "level3": 6.02e6, "level4": 6.02e6, "plane_waves": 28.94e6, "grid": 9.59e6}
 
 
 def measured_traffic(cls: str):
